@@ -1,0 +1,94 @@
+"""Seeded synthetic inputs shared by the oracle tests and the GPU tests.
+
+This module only draws random inputs; it holds none of the method's
+arithmetic. The recipe follows the paper's benchmark fluid (sec. 4): point
+particles of mass m placed uniformly at random in a cubic periodic box,
+Gaussian velocities at temperature kT, and a constant shift that removes the
+net momentum. Embedded beads (sec. 2, solutes) are laid out as random walks.
+
+Everything is drawn from numpy.random.default_rng(seed) in a fixed order, so
+the same seed gives the same input on every machine.
+"""
+import math
+
+import numpy as np
+
+DEG130 = 130.0 * math.pi / 180.0
+
+
+def _uniform_positions(rng, n, L):
+    pos = rng.random((n, 3)) * L
+    # rng.random() < 1, but the product can round up to L for some L
+    return np.where(pos >= L, 0.0, pos)
+
+
+def fluid(n_cells, density, kT=1.0, mass=1.0, seed=1, a=1.0):
+    """Uniform positions in [0, L)^3, velocities N(0, kT/m) per component,
+    then the mean velocity subtracted so the net momentum is zero (sec. 4.1:
+    a constant correction on every particle). N = round(density * cells)."""
+    n_cells = tuple(int(x) for x in np.broadcast_to(n_cells, (3,)))
+    L = np.array(n_cells, dtype=np.float64) * a
+    n = int(round(density * n_cells[0] * n_cells[1] * n_cells[2]))
+    rng = np.random.default_rng(seed)
+    pos = _uniform_positions(rng, n, L)
+    vel = rng.normal(0.0, math.sqrt(kT / mass), size=(n, 3))
+    vel -= vel.mean(axis=0)
+    return pos, vel
+
+
+def beads(n_cells, n_chains, chain_len, bond=0.97, kT=1.0, mass=5.0, seed=2,
+          a=1.0):
+    """Random-walk chains of beads: the first bead uniform in the box, each
+    next bead one bond length away in a uniformly random direction, wrapped
+    into the box; velocities N(0, kT/mass). Returns (pos, vel, mass)."""
+    n_cells = tuple(int(x) for x in np.broadcast_to(n_cells, (3,)))
+    L = np.array(n_cells, dtype=np.float64) * a
+    rng = np.random.default_rng(seed)
+    n = n_chains * chain_len
+    start = _uniform_positions(rng, n_chains, L)
+    steps = rng.normal(size=(n_chains, chain_len - 1, 3))
+    steps *= bond / np.linalg.norm(steps, axis=2, keepdims=True)
+    walk = np.concatenate([start[:, None, :],
+                           start[:, None, :] + np.cumsum(steps, axis=1)], axis=1)
+    pos = np.mod(walk.reshape(n, 3), L)
+    pos = np.where(pos >= L, 0.0, pos)
+    vel = rng.normal(0.0, math.sqrt(kT / mass), size=(n, 3))
+    return pos, vel, np.full(n, float(mass))
+
+
+def zero_net_momentum(vel_list, mass_list):
+    """Subtract the common centre-of-mass velocity from every group so the
+    total momentum of all groups together is zero."""
+    P = sum((m[:, None] * v).sum(axis=0) for v, m in zip(vel_list, mass_list))
+    M = sum(m.sum() for m in mass_list)
+    return [v - P / M for v in vel_list]
+
+
+def non_gaussian_fluid(n_cells, density, kT=1.0, mass=1.0, seed=1, a=1.0):
+    """Same positions as `fluid`, but every speed equal to sqrt(3 kT / m)
+    with uniformly random directions (a far-from-Maxwellian start), then the
+    net momentum removed."""
+    n_cells = tuple(int(x) for x in np.broadcast_to(n_cells, (3,)))
+    L = np.array(n_cells, dtype=np.float64) * a
+    n = int(round(density * n_cells[0] * n_cells[1] * n_cells[2]))
+    rng = np.random.default_rng(seed)
+    pos = _uniform_positions(rng, n, L)
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    vel = d * math.sqrt(3.0 * kT / mass)
+    vel -= vel.mean(axis=0)
+    return pos, vel
+
+
+# Named workloads of the benchmark suite (sizes of the paper's benchmark
+# fluid, sec. 4 and Table 1, scaled to one GPU).
+CONFIGS = {
+    "srd_20c_rho5_fp64": dict(n_cells=(20, 20, 20), density=5, kT=1.0,
+                              thermostat=False, steps=100, seed=1),
+    "srd_100c_rho10_mbthermo": dict(n_cells=(100, 100, 100), density=10,
+                                    kT=1.0, thermostat=True, steps=1000,
+                                    seed=1),
+    "srd_400c_rho5_beads": dict(n_cells=(400, 400, 400), density=5, kT=1.0,
+                                thermostat=False, steps=200, seed=1,
+                                chains=20000, chain_len=50, bead_mass=5.0),
+}
