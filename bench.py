@@ -1,0 +1,170 @@
+"""Throughput of the SRD-MPCD step on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Workload: the 100^3-cell fluid at 10 particles per cell (10^7 particles),
+alpha = 130 deg, dt = 0.1, kT = 1, random grid shift, Maxwell-Boltzmann
+cell thermostat, synthetic positions/velocities (seed 1). The headline value
+is the FP32 cell-relative form; the plain FP64 form runs on the same input
+and is reported beside it. A step is one whole pass of the hot path: stream,
+grid shift, binning (count sort), cell reduction, draws and rotation.
+
+Prints one JSON line. `roofline` is for the dominant kernel (the collide
+kernel), timed with HIP events on the library's own stream during the timed
+region; `cpu_baseline` is the FP64 numpy oracle on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "srd_100c_rho10_mbthermo"
+
+# Algorithmic bytes per particle of one collide launch (read once / write
+# once what its contract names): list entry 4, state, tag 4 in; state, tag 4,
+# (cell, rank) 8 out; plus the offsets read and the counts written per cell.
+STATE_BYTES = {"fp32": 28, "fp64": 48}
+
+
+def collide_bytes_per_particle(form, rho):
+    s = STATE_BYTES[form]
+    return (4 + s + 4) + (s + 4 + 8) + 8.0 / rho
+
+
+def floor_bytes_per_update(form, rho):
+    """Whole-step floor: state read once and written once, occupancy once."""
+    return 2 * STATE_BYTES[form] + 8.0 / rho
+
+
+def run_form(m, pos, vel, cfg, precision, steps, warmup):
+    import torch
+    sim = m.Sim(pos, vel, cfg["n_cells"], kT=cfg["kT"], seed=cfg["seed"],
+                precision=precision, thermostat=cfg["thermostat"])
+    try:
+        sim.step(warmup)
+        sim.sync()
+        sim.profile(True)
+        sim.profile_read(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        sim.sync()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        coll_ms, coll_n = sim.profile_read(0)
+        sim.profile(False)
+        P, ke, kT = sim.totals()
+    finally:
+        sim.close()
+    return dict(seconds=t1 - t0, collide_ms=coll_ms, collide_launches=coll_n,
+                net_momentum=float(np.abs(P).max()), kT=kT)
+
+
+def cpu_baseline(pos, vel, cfg, nsteps):
+    from oracle import srd
+    p = srd.Params(cfg["n_cells"], seed=cfg["seed"], thermostat=cfg["thermostat"],
+                   kT=cfg["kT"])
+    mass = np.ones(pos.shape[0])
+    t0 = time.perf_counter()
+    srd.run(pos, vel, mass, p, 0, nsteps)
+    dt = time.perf_counter() - t0
+    return dict(value=pos.shape[0] * nsteps / dt, unit="particle-updates/s", cores=1,
+                kind="oracle",
+                sample=f"{nsteps} FP64 oracle steps of the full {pos.shape[0]}-particle "
+                       f"workload ({dt:.1f} s, numpy, single thread)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="fp32,fp64")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(independent boxes shard one per GPU; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1801_10187_amd as m
+    import workloads
+
+    cfg = workloads.CONFIGS[WORKLOAD]
+    pos, vel = workloads.fluid(cfg["n_cells"], cfg["density"], kT=cfg["kT"],
+                               seed=cfg["seed"])
+    N = pos.shape[0]
+    rho = cfg["density"]
+    torch.cuda.init()
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    res = {}
+    for form in forms:
+        prec = m.FP32 if form == "fp32" else m.FP64
+        r = run_form(m, pos, vel, cfg, prec, args.steps, args.warmup)
+        r["updates_per_s"] = N * args.steps / r["seconds"]
+        r["ms_per_step"] = 1e3 * r["seconds"] / args.steps
+        avg_us = 1e3 * r["collide_ms"] / max(r["collide_launches"], 1)
+        r["collide_avg_us"] = avg_us
+        per_launch = collide_bytes_per_particle(form, rho) * N
+        r["collide_GBs"] = per_launch / (avg_us * 1e-6) / 1e9
+        r["step_floor_frac"] = r["updates_per_s"] * floor_bytes_per_update(form, rho) / (HBM_PEAK_GBS * 1e9)
+        res[form] = r
+        print(f"[bench] {form}: {r['updates_per_s']:.4g} updates/s, "
+              f"{r['ms_per_step']:.4f} ms/step, collide {avg_us:.1f} us "
+              f"({r['collide_GBs']:.0f} GB/s)", file=sys.stderr, flush=True)
+
+    head = res.get("fp32") or res[forms[0]]
+    head_form = "fp32" if "fp32" in res else forms[0]
+    out = {
+        "metric": "particle-updates/s (stream+bin+SRD collide) FP32 vs FP64; p99 batch latency",
+        "value": head["updates_per_s"],
+        "unit": "particle-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if head_form == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "n_cells": list(cfg["n_cells"]),
+                   "particles": N, "density": rho, "alpha_deg": 130, "dt": 0.1,
+                   "kT": cfg["kT"], "thermostat": "maxwell-boltzmann",
+                   "grid_shift": True, "form": head_form},
+        "roofline": {
+            "bound": "hbm",
+            "achieved": head["collide_GBs"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": head["collide_GBs"] / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel": "k_collide",
+            "kernel_avg_us": head["collide_avg_us"],
+            "bytes_per_particle": collide_bytes_per_particle(head_form, rho),
+        },
+        "step_floor_frac": head["step_floor_frac"],
+        "forms": {f: {"updates_per_s": r["updates_per_s"], "ms_per_step": r["ms_per_step"],
+                      "collide_avg_us": r["collide_avg_us"], "collide_GBs": r["collide_GBs"],
+                      "step_floor_frac": r["step_floor_frac"], "kT_end": r["kT"],
+                      "net_momentum_end": r["net_momentum"]} for f, r in res.items()},
+    }
+    if "fp32" in res and "fp64" in res:
+        out["fp32_over_fp64"] = res["fp32"]["updates_per_s"] / res["fp64"]["updates_per_s"]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(pos, vel, cfg, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

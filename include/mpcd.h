@@ -1,0 +1,191 @@
+/*
+ * mpcd.h -- C ABI of libmpcd, a stochastic-rotation-dynamics (SRD) variant of
+ * multiparticle collision dynamics (MPCD) for one AMD MI355X (gfx950) GPU.
+ *
+ * The method is that of Howard, Panagiotopoulos and Nikoubashman,
+ * arXiv:1801.10187. One time step (sec. 3, flow diagram of Fig. 1) is:
+ *   stream   r <- r + v dt in a periodic box                        (eq. 1)
+ *   bin      random grid shift, cubic cells of edge a               (sec. 2, 3.4)
+ *   collide  per-cell mass, momentum and kinetic energy (sec. 3.5, eq. 3),
+ *            a random axis per cell (sec. 3.6), optional Maxwell-Boltzmann
+ *            scale factor (sec. 2, 3.6), rotation v <- u + xi R(alpha)(v - u)
+ *            (eq. 2, Alg. 1)
+ *
+ * Conventions for every entry point
+ *  - Every call returns an mpcd_status; no C++ exception crosses the ABI.
+ *    mpcd_last_error() returns a thread-local text for the last failure.
+ *  - Positions and velocities cross the ABI as row-major N x 3 arrays of
+ *    double, (x0, y0, z0, x1, ...). A flag says whether a pointer is host or
+ *    device memory. The context copies what it is given and never keeps a
+ *    caller pointer; outputs go to caller-owned buffers.
+ *  - Particles are identified by their tag: the solvent particles are tags
+ *    0 .. n_solvent-1 in the order given to mpcd_create, embedded particles
+ *    follow. Every get_* returns data in tag order, whatever the internal
+ *    (cell-sorted) order.
+ *  - The box is [0, L)^3 with L = n_cells[d] * a, periodic.
+ *  - Call order within a step is mpcd_stream -> mpcd_bin -> mpcd_collide;
+ *    any other order returns MPCD_ESTATE. mpcd_step runs whole steps from the
+ *    state after a collide (or after create).
+ *  - All device work is enqueued on the context's HIP stream. Errors raised
+ *    inside kernels (range checks) are reported by mpcd_sync and by any get_*.
+ *  - A context is not thread-safe; use one per host thread.
+ */
+#ifndef MPCD_H
+#define MPCD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPCD_ABI_VERSION 1
+
+typedef struct mpcd_ctx_s* mpcd_ctx;
+
+typedef enum {
+  MPCD_OK = 0,
+  MPCD_EINVAL = 1, /* bad argument: sizes, parameters, positions outside the box */
+  MPCD_ENOMEM = 2, /* device or host allocation failed                            */
+  MPCD_EHIP = 3,   /* a HIP runtime call failed                                   */
+  MPCD_ERANGE = 4, /* a kernel range check failed: a particle moved a whole box    */
+                   /* length in one step (FP64 form), a momentum outside the       */
+                   /* fixed-point range, or the Gamma sampler hit its attempt cap  */
+  MPCD_ESTATE = 5  /* call out of order                                           */
+} mpcd_status;
+
+typedef enum { MPCD_FP64 = 0, MPCD_FP32 = 1 } mpcd_precision;
+
+/* Problem parameters as the paper states the problem (sec. 2, sec. 4). */
+typedef struct {
+  int32_t n_cells[3];  /* cells per axis (>= 1); FP32 form: <= 1024 per axis    */
+  double a;            /* cell edge (> 0)                                        */
+  double alpha;        /* SRD rotation angle in radians (eq. 2)                  */
+  double dt;           /* collision time (>= 0) (eq. 1)                          */
+  double kT;           /* thermostat temperature (>= 0)                          */
+  uint64_t seed;       /* user seed of the per-cell random streams (sec. 3.6)    */
+  double solvent_mass; /* mass m of every solvent particle (> 0) (sec. 3.2)      */
+  int32_t precision;   /* mpcd_precision: storage form of positions/velocities   */
+  int32_t thermostat;  /* 0 none, 1 Maxwell-Boltzmann cell scaling (sec. 2, 3.6) */
+  int32_t grid_shift;  /* 1 random grid shift each step (sec. 2), 0 none         */
+  int32_t flags;       /* reserved, must be 0                                    */
+} mpcd_params;
+
+/* Create a context and upload the initial state (sec. 3.2 particle data).
+ *  pos, vel      n_solvent x 3 doubles; positions inside [0, L) per axis.
+ *  n_embedded    embedded (solute) particles that take part in collisions
+ *                only and stream ballistically (sec. 2, sec. 3.6); 0 for none.
+ *  emb_pos/vel   n_embedded x 3 doubles; emb_mass n_embedded doubles (> 0).
+ *  pointers_on_device  0: all arrays are host memory; 1: device memory.
+ *  hip_stream    hipStream_t to enqueue on, or NULL for a stream the context
+ *                creates (default priority) and owns.
+ * The step counter starts at 0. Errors: MPCD_EINVAL for bad parameters or a
+ * position outside the box, MPCD_ENOMEM, MPCD_EHIP. On error *out is NULL. */
+mpcd_status mpcd_create(const mpcd_params* params, int64_t n_solvent,
+                        const double* pos, const double* vel,
+                        int64_t n_embedded, const double* emb_pos,
+                        const double* emb_vel, const double* emb_mass,
+                        int32_t pointers_on_device, void* hip_stream,
+                        mpcd_ctx* out);
+
+/* Streaming (eq. 1): r <- r + v dt, wrapped into the box. Needs the state
+ * after create or after a collide. */
+mpcd_status mpcd_stream(mpcd_ctx ctx);
+
+/* Binning (sec. 3.4): draw the grid shift of the current step counter n,
+ * assign each particle its collision cell on the shifted grid, count the
+ * occupancy and build the cell-ordered particle list (count sort).
+ * Needs a preceding mpcd_stream. */
+mpcd_status mpcd_bin(mpcd_ctx ctx);
+
+/* Collision (sec. 3.5, 3.6, eq. 2, Alg. 1): cell sums, per-cell axis and
+ * thermostat factor drawn from counter n, rotation; particles end up stored
+ * in cell order. Increments the step counter. Needs a preceding mpcd_bin. */
+mpcd_status mpcd_collide(mpcd_ctx ctx);
+
+/* nsteps whole steps (stream, bin, collide), equivalent to calling the three
+ * entry points nsteps times. nsteps >= 0. */
+mpcd_status mpcd_step(mpcd_ctx ctx, int64_t nsteps);
+
+/* Copy the state out in tag order: pos, vel are n_total x 3 doubles, where
+ * n_total = n_solvent + n_embedded. Synchronises the context's stream. */
+mpcd_status mpcd_get_state(mpcd_ctx ctx, double* pos, double* vel,
+                           int32_t pointers_on_device);
+
+/* Cells of the most recent mpcd_bin (or binning inside mpcd_step):
+ * cell_of_tag[n_total] the x-fastest cell index ix + nx*(iy + ny*iz) on the
+ * shifted grid, counts[n_cells] the occupancy. Either pointer may be NULL.
+ * MPCD_ESTATE if nothing has been binned yet. Synchronises. */
+mpcd_status mpcd_get_cells(mpcd_ctx ctx, int32_t* cell_of_tag, int32_t* counts,
+                           int32_t pointers_on_device);
+
+/* Cell properties (sec. 3.5) of the binned, not yet collided state:
+ * mass[n_cells], momentum[n_cells x 3], ek[n_cells] (eq. 3, relative to the
+ * centre-of-mass velocity). Only valid between mpcd_bin and mpcd_collide
+ * (else MPCD_ESTATE). Any pointer may be NULL. Synchronises. */
+mpcd_status mpcd_get_cell_props(mpcd_ctx ctx, double* mass, double* momentum,
+                                double* ek, int32_t pointers_on_device);
+
+/* Per-cell random draws of the binned state for the current step counter:
+ * axis[n_cells x 3] (sec. 3.6, cylindrical projection) and xi[n_cells]
+ * (thermostat scale; 1 when the thermostat is off or N_c < 2). Cells with no
+ * particle get axis (0, 0, 0) and xi 1. Only valid between mpcd_bin and
+ * mpcd_collide. Either pointer may be NULL. Synchronises. */
+mpcd_status mpcd_get_cell_draws(mpcd_ctx ctx, double* axis, double* xi,
+                                int32_t pointers_on_device);
+
+/* Grid shift drawn for step counter n, s[3] in (-a/2, a/2) (zero when the
+ * shift is off). Host-only computation; any state. */
+mpcd_status mpcd_get_shift(mpcd_ctx ctx, uint64_t n, double s[3]);
+
+/* Step counter: read, or set (to resume from a checkpoint; only in the
+ * state after create or after a collide). */
+mpcd_status mpcd_get_step(mpcd_ctx ctx, uint64_t* n);
+mpcd_status mpcd_set_step(mpcd_ctx ctx, uint64_t n);
+
+/* Net properties (sec. 3.5): total momentum p[3], kinetic energy ke and the
+ * kinetic temperature of the motion relative to the centre of mass,
+ * 2 (ke - |p|^2 / 2M) / (3 (n_total - 1)). Synchronises. */
+mpcd_status mpcd_totals(mpcd_ctx ctx, double p[3], double* ke, double* kT);
+
+/* Wait for the context's work and report kernel range errors. */
+mpcd_status mpcd_sync(mpcd_ctx ctx);
+
+/* Counts and sizes: n_total particles, n_cells cells. */
+mpcd_status mpcd_get_sizes(mpcd_ctx ctx, int64_t* n_total, int64_t* n_cells);
+
+/* Kernel timing with HIP events on the context's stream. which: 0 collide,
+ * 1 bin (incl. stream+bin), 2 count scan + list. While enabled, each launch
+ * of the kernel is bracketed by two events; mpcd_profile_read synchronises,
+ * returns the summed milliseconds and launch count since the last read,
+ * and clears them. */
+mpcd_status mpcd_profile_enable(mpcd_ctx ctx, int32_t on);
+mpcd_status mpcd_profile_read(mpcd_ctx ctx, int32_t which, double* total_ms,
+                              int64_t* launches);
+
+void mpcd_destroy(mpcd_ctx ctx);
+
+/* Thread-local text of the last failure in this thread ("" if none). */
+const char* mpcd_last_error(void);
+
+/* ---- building blocks exposed for tests and measurement ---------------- */
+
+/* Philox4x32-10 (Salmon et al., SC'11; the counter-based generator family
+ * of sec. 3.6) evaluated on the GPU: ctr is n x 4 uint32 counters, key the
+ * 64-bit key (low word k0, high word k1), out n x 4 uint32. Host pointers.
+ * Synchronous. */
+mpcd_status mpcd_philox4x32_10(const uint32_t* ctr, int64_t n, uint64_t key,
+                               uint32_t* out);
+
+/* Plain device-to-device copy of `bytes` bytes with the library's streaming
+ * kernel; used to measure the achievable HBM bandwidth and to calibrate
+ * hardware byte counters. Device pointers; hip_stream may be NULL.
+ * Asynchronous on the stream. */
+mpcd_status mpcd_copy_kernel(const void* src, void* dst, int64_t bytes,
+                             void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPCD_H */

@@ -1,0 +1,10 @@
+"""SRD multiparticle collision dynamics on one AMD MI355X (gfx950).
+
+The hot path lives in libmpcd.so (HIP kernels behind the C ABI of
+include/mpcd.h); `binding` marshals arguments to it with ctypes.
+"""
+from .binding import (FP32, FP64, MpcdError, Sim, copy_kernel, declared_symbols,
+                      load, make_params, philox)
+
+__all__ = ["FP32", "FP64", "MpcdError", "Sim", "copy_kernel", "declared_symbols",
+           "load", "make_params", "philox"]

@@ -1,0 +1,257 @@
+"""ctypes binding of libmpcd (include/mpcd.h): argument marshalling only.
+
+Every step of the SRD path runs in the library's HIP kernels; this module
+converts numpy arrays (or torch device tensors) to pointers and status codes
+to exceptions. It raises at import of the library if libmpcd.so has not been
+built; there is no fallback.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+LIB_PATH = os.path.join(HERE, "libmpcd.so")
+HEADER = os.path.join(ROOT, "include", "mpcd.h")
+
+MPCD_OK, MPCD_EINVAL, MPCD_ENOMEM, MPCD_EHIP, MPCD_ERANGE, MPCD_ESTATE = range(6)
+FP64, FP32 = 0, 1
+STATUS_NAMES = {0: "MPCD_OK", 1: "MPCD_EINVAL", 2: "MPCD_ENOMEM", 3: "MPCD_EHIP",
+                4: "MPCD_ERANGE", 5: "MPCD_ESTATE"}
+
+
+class MpcdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n_cells", ctypes.c_int32 * 3),
+                ("a", ctypes.c_double),
+                ("alpha", ctypes.c_double),
+                ("dt", ctypes.c_double),
+                ("kT", ctypes.c_double),
+                ("seed", ctypes.c_uint64),
+                ("solvent_mass", ctypes.c_double),
+                ("precision", ctypes.c_int32),
+                ("thermostat", ctypes.c_int32),
+                ("grid_shift", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+def load():
+    """Load libmpcd.so (built by paper_1801_10187_amd.build); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run "
+                          "`python -m paper_1801_10187_amd.build` first")
+    lib = ctypes.CDLL(LIB_PATH)
+    st = ctypes.c_int
+    sig = {
+        "mpcd_create": (st, [ctypes.POINTER(Params), ctypes.c_int64, _P, _P, ctypes.c_int64,
+                              _P, _P, _P, ctypes.c_int32, _P, ctypes.POINTER(_P)]),
+        "mpcd_stream": (st, [_P]),
+        "mpcd_bin": (st, [_P]),
+        "mpcd_collide": (st, [_P]),
+        "mpcd_step": (st, [_P, ctypes.c_int64]),
+        "mpcd_get_state": (st, [_P, _P, _P, ctypes.c_int32]),
+        "mpcd_get_cells": (st, [_P, _P, _P, ctypes.c_int32]),
+        "mpcd_get_cell_props": (st, [_P, _P, _P, _P, ctypes.c_int32]),
+        "mpcd_get_cell_draws": (st, [_P, _P, _P, ctypes.c_int32]),
+        "mpcd_get_shift": (st, [_P, ctypes.c_uint64, _P]),
+        "mpcd_get_step": (st, [_P, ctypes.POINTER(ctypes.c_uint64)]),
+        "mpcd_set_step": (st, [_P, ctypes.c_uint64]),
+        "mpcd_totals": (st, [_P, _P, _D, _D]),
+        "mpcd_sync": (st, [_P]),
+        "mpcd_get_sizes": (st, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+        "mpcd_profile_enable": (st, [_P, ctypes.c_int32]),
+        "mpcd_profile_read": (st, [_P, ctypes.c_int32, _D, ctypes.POINTER(ctypes.c_int64)]),
+        "mpcd_destroy": (None, [_P]),
+        "mpcd_last_error": (ctypes.c_char_p, []),
+        "mpcd_philox4x32_10": (st, [_P, ctypes.c_int64, ctypes.c_uint64, _P]),
+        "mpcd_copy_kernel": (st, [_P, _P, ctypes.c_int64, _P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def declared_symbols():
+    """Entry points declared in include/mpcd.h."""
+    import re
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(mpcd_[a-z0-9_]+)\s*\(", text)))
+
+
+def _check(status):
+    if status != MPCD_OK:
+        raise MpcdError(status, load().mpcd_last_error().decode())
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def make_params(n_cells, a=1.0, alpha=130.0 * math.pi / 180.0, dt=0.1, kT=1.0,
+                seed=1, solvent_mass=1.0, precision=FP64, thermostat=False,
+                grid_shift=True, flags=0):
+    p = Params()
+    n = [int(x) for x in np.broadcast_to(np.asarray(n_cells), (3,))]
+    p.n_cells[:] = n
+    p.a, p.alpha, p.dt, p.kT = float(a), float(alpha), float(dt), float(kT)
+    p.seed = int(seed)
+    p.solvent_mass = float(solvent_mass)
+    p.precision = int(precision)
+    p.thermostat = int(bool(thermostat)) if thermostat in (0, 1, True, False) else int(thermostat)
+    p.grid_shift = int(bool(grid_shift)) if grid_shift in (0, 1, True, False) else int(grid_shift)
+    p.flags = int(flags)
+    return p
+
+
+class Sim:
+    """One SRD-MPCD system on the GPU (a thin owner of an mpcd_ctx)."""
+
+    def __init__(self, pos, vel, n_cells, a=1.0, alpha=130.0 * math.pi / 180.0,
+                 dt=0.1, kT=1.0, seed=1, solvent_mass=1.0, precision=FP64,
+                 thermostat=False, grid_shift=True, emb_pos=None, emb_vel=None,
+                 emb_mass=None, hip_stream=None):
+        lib = load()
+        self.params = make_params(n_cells, a, alpha, dt, kT, seed, solvent_mass,
+                                  precision, thermostat, grid_shift)
+        pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+        vel = np.ascontiguousarray(vel, dtype=np.float64).reshape(-1, 3)
+        n_emb = 0
+        ep = ev = em = None
+        if emb_pos is not None:
+            ep = np.ascontiguousarray(emb_pos, dtype=np.float64).reshape(-1, 3)
+            ev = np.ascontiguousarray(emb_vel, dtype=np.float64).reshape(-1, 3)
+            em = np.ascontiguousarray(emb_mass, dtype=np.float64).reshape(-1)
+            n_emb = ep.shape[0]
+        ctx = ctypes.c_void_p()
+        _check(lib.mpcd_create(ctypes.byref(self.params), pos.shape[0], _ptr(pos), _ptr(vel),
+                               n_emb, _ptr(ep), _ptr(ev), _ptr(em), 0,
+                               None if hip_stream is None else ctypes.c_void_p(hip_stream),
+                               ctypes.byref(ctx)))
+        self._ctx = ctx
+        self.n_solvent = pos.shape[0]
+        self.n_embedded = n_emb
+        self.n_total = pos.shape[0] + n_emb
+        self.ncells = int(np.prod([int(x) for x in self.params.n_cells]))
+
+    # -- steps
+    def stream(self):
+        _check(load().mpcd_stream(self._ctx))
+
+    def bin(self):
+        _check(load().mpcd_bin(self._ctx))
+
+    def collide(self):
+        _check(load().mpcd_collide(self._ctx))
+
+    def step(self, nsteps=1):
+        _check(load().mpcd_step(self._ctx, int(nsteps)))
+
+    def sync(self):
+        _check(load().mpcd_sync(self._ctx))
+
+    # -- readback
+    def get_state(self):
+        pos = np.empty((self.n_total, 3))
+        vel = np.empty((self.n_total, 3))
+        _check(load().mpcd_get_state(self._ctx, _ptr(pos), _ptr(vel), 0))
+        return pos, vel
+
+    def get_cells(self):
+        cells = np.empty(self.n_total, dtype=np.int32)
+        counts = np.empty(self.ncells, dtype=np.int32)
+        _check(load().mpcd_get_cells(self._ctx, _ptr(cells), _ptr(counts), 0))
+        return cells, counts
+
+    def get_cell_props(self):
+        mass = np.empty(self.ncells)
+        mom = np.empty((self.ncells, 3))
+        ek = np.empty(self.ncells)
+        _check(load().mpcd_get_cell_props(self._ctx, _ptr(mass), _ptr(mom), _ptr(ek), 0))
+        return mass, mom, ek
+
+    def get_cell_draws(self):
+        axis = np.empty((self.ncells, 3))
+        xi = np.empty(self.ncells)
+        _check(load().mpcd_get_cell_draws(self._ctx, _ptr(axis), _ptr(xi), 0))
+        return axis, xi
+
+    def shift(self, n):
+        s = np.empty(3)
+        _check(load().mpcd_get_shift(self._ctx, int(n), _ptr(s)))
+        return s
+
+    @property
+    def step_count(self):
+        n = ctypes.c_uint64()
+        _check(load().mpcd_get_step(self._ctx, ctypes.byref(n)))
+        return n.value
+
+    @step_count.setter
+    def step_count(self, n):
+        _check(load().mpcd_set_step(self._ctx, int(n)))
+
+    def totals(self):
+        p = np.empty(3)
+        ke = ctypes.c_double()
+        kT = ctypes.c_double()
+        _check(load().mpcd_totals(self._ctx, _ptr(p), ctypes.byref(ke), ctypes.byref(kT)))
+        return p, ke.value, kT.value
+
+    # -- timing
+    def profile(self, on=True):
+        _check(load().mpcd_profile_enable(self._ctx, int(bool(on))))
+
+    def profile_read(self, which=0):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(load().mpcd_profile_read(self._ctx, int(which), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            load().mpcd_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def philox(ctr, key):
+    """Philox4x32-10 on the GPU: ctr (n, 4) uint32, key 64-bit int."""
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    out = np.empty_like(ctr)
+    _check(load().mpcd_philox4x32_10(_ptr(ctr), ctr.shape[0], int(key), _ptr(out)))
+    return out
+
+
+def copy_kernel(src_ptr, dst_ptr, nbytes, hip_stream=None):
+    """Device copy with the library's streaming kernel (device pointers)."""
+    _check(load().mpcd_copy_kernel(ctypes.c_void_p(src_ptr), ctypes.c_void_p(dst_ptr),
+                                   int(nbytes), None if hip_stream is None else ctypes.c_void_p(hip_stream)))

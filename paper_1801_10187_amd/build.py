@@ -1,0 +1,52 @@
+"""Build libmpcd.so in-tree with hipcc for gfx950.
+
+    python -m paper_1801_10187_amd.build        (or build() from Python)
+
+Flags that matter for results:
+  -ffp-contract=off   every floating-point operation rounds once, in the
+                      order written (stream, binning and the fixed-point
+                      split rely on it);
+  -Xclang -target-feature -Xclang -packed-fp32-ops
+                      no packed FP32 instructions.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SRC = os.path.join(HERE, "csrc", "mpcd.hip")
+DEPS = [SRC, os.path.join(HERE, "csrc", "mpcd_kernels.hpp"),
+        os.path.join(HERE, "csrc", "mpcd_device.hpp"),
+        os.path.join(ROOT, "include", "mpcd.h")]
+LIB = os.path.join(HERE, "libmpcd.so")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+
+FLAGS = [
+    "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-shared",
+    "-ffp-contract=off",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wno-unused-command-line-argument",
+    "-I", os.path.join(ROOT, "include"),
+]
+
+
+def build(verbose=False):
+    """Compile the library (always; a fresh build each call)."""
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, *FLAGS, SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed building libmpcd.so")
+    if verbose and res.stderr.strip():
+        sys.stderr.write(res.stderr)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,214 @@
+// Device building blocks of the SRD step: Philox4x32-10, the word -> uniform
+// map, exact fixed-point accumulation, periodic wrap and binning in both
+// storage forms, the per-cell draws (axis, Maxwell-Boltzmann factor) and the
+// rotation matrix. Everything here is compiled with -ffp-contract=off so each
+// floating-point operation rounds once, in the order written.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+namespace mpcd {
+
+// ---------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): the counter-based,
+// stateless generator family the paper's per-cell streams rely on (sec. 3.6).
+// Counter layout used by the library: (cell, step, purpose, attempt),
+// key = (seed low word, seed high word).
+struct U4 {
+  uint32_t x, y, z, w;
+};
+
+constexpr uint32_t TAG_AXIS = 0;
+constexpr uint32_t TAG_THERMO = 1;
+constexpr uint32_t TAG_SHIFT = 2;
+constexpr int GAMMA_MAX_ATTEMPTS = 64;
+
+__host__ __device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    U4 n;
+    n.x = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+    n.y = (uint32_t)p1;
+    n.z = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+    n.w = (uint32_t)p0;
+    c = n;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// u = (w + 1/2) 2^-32: exact in FP64, strictly inside (0, 1).
+__host__ __device__ inline double u01(uint32_t w) {
+  return ((double)w + 0.5) * 0x1p-32;
+}
+
+// Grid shift of step n (sec. 2): each component uniform on (-a/2, a/2).
+__host__ __device__ inline void grid_shift(uint32_t k0, uint32_t k1, uint32_t n,
+                                           double a, double s[3]) {
+  const U4 w = philox4x32_10(U4{0u, n, TAG_SHIFT, 0u}, k0, k1);
+  s[0] = (u01(w.x) - 0.5) * a;
+  s[1] = (u01(w.y) - 0.5) * a;
+  s[2] = (u01(w.z) - 0.5) * a;
+}
+
+// ------------------------------------------------------------ fixed point
+// A value x is split into two int64 limbs, hi = round(x 2^20) and
+// lo = round((x - hi 2^-20) 2^72); the remainder x - hi 2^-20 is exact
+// (|x - hi 2^-20| <= 2^-21 and the operands are within a factor two, or hi is
+// 0). Sums of limbs are exact integer sums, so a cell total does not depend on
+// the order its particles are visited in: results are deterministic although
+// the count sort places particles of a cell in a run-dependent order. The
+// resolution is 2^-72 and the range |x| < 2^30 per term.
+struct Fx {
+  long long hi, lo;
+};
+
+__device__ inline void fx_add(Fx& acc, double x, bool& bad) {
+  const double C = 6755399441055744.0;  // 1.5 * 2^52: rounds to an integer
+  const long long CB = 0x4338000000000000LL;
+  bad |= !(fabs(x) < 0x1p30);
+  const double t = x * 0x1p20 + C;
+  const double hd = t - C;  // exact
+  const double r = x - hd * 0x1p-20;  // exact
+  const double t2 = r * 0x1p72 + C;
+  acc.hi += __double_as_longlong(t) - CB;
+  acc.lo += __double_as_longlong(t2) - CB;
+}
+
+__device__ inline double fx_value(const Fx& a) {
+  return (double)a.hi * 0x1p-20 + (double)a.lo * 0x1p-72;
+}
+
+// ------------------------------------------------------ wrap and binning
+// w in (-L, 2L) -> [0, L); the subtraction is exact (Sterbenz), an addition
+// that rounds up to L gives 0.
+__device__ inline double wrap_box(double w, double L) {
+  if (w >= L) {
+    w -= L;
+  } else if (w < 0.0) {
+    w += L;
+    if (w >= L) w = 0.0;
+  }
+  return w;
+}
+
+__device__ inline int bin_axis64(double x, double s, double L, double inv_a,
+                                 int n) {
+  const double w = wrap_box(x + s, L);
+  const int i = (int)floor(w * inv_a);
+  // w is in [0, L) for any position the stream produced, so only the top
+  // clamp can act; the bottom one keeps a corrupt position inside the grid.
+  return i < 0 ? 0 : (i < n - 1 ? i : n - 1);
+}
+
+// FP32 cell-relative form: position = home cell h (per axis) + offset o in
+// [0, a), all single-precision operations rounded once, no contraction.
+__device__ inline int wrap_index(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+__device__ inline void stream_axis32(float& o, int& h, float v, float dt32,
+                                     float a32, float inv_a32, int n) {
+  const float t = v * dt32;
+  const float o1 = o + t;
+  float kf = floorf(o1 * inv_a32);
+  kf = fminf(fmaxf(kf, -1.0e9f), 1.0e9f);
+  float o2 = o1 - kf * a32;
+  int k = (int)kf;
+  if (o2 >= a32) {
+    o2 = 0.0f;
+    k += 1;
+  }
+  if (o2 < 0.0f) o2 = 0.0f;
+  o = o2;
+  h = wrap_index(h + (k % n), n);
+}
+
+__device__ inline int bin_axis32(float o, int h, float s32, float inv_a32,
+                                 int n) {
+  const float q = o + s32;
+  int j = (int)floorf(q * inv_a32);
+  j = j < -1 ? -1 : (j > 1 ? 1 : j);
+  int c = h + j;
+  if (c < 0) c += n;
+  if (c >= n) c -= n;
+  return c;
+}
+
+__device__ inline uint32_t pack_home(int hx, int hy, int hz) {
+  return (uint32_t)hx | ((uint32_t)hy << 10) | ((uint32_t)hz << 20);
+}
+__device__ inline void unpack_home(uint32_t h, int& hx, int& hy, int& hz) {
+  hx = (int)(h & 1023u);
+  hy = (int)((h >> 10) & 1023u);
+  hz = (int)(h >> 20);
+}
+
+// ------------------------------------------------------- per-cell draws
+// Rotation axis by the cylindrical projection (sec. 3.6): z = 2 u1 - 1,
+// phi = 2 pi u2, n = (r cos phi, r sin phi, z), r = sqrt(1 - z^2).
+__device__ inline void cell_axis(uint32_t cell, uint32_t step, uint32_t k0,
+                                 uint32_t k1, double n[3]) {
+  const U4 w = philox4x32_10(U4{cell, step, TAG_AXIS, 0u}, k0, k1);
+  const double z = 2.0 * u01(w.x) - 1.0;
+  const double phi = (2.0 * M_PI) * u01(w.y);
+  const double r = sqrt(fmax(0.0, 1.0 - z * z));
+  n[0] = r * cos(phi);
+  n[1] = r * sin(phi);
+  n[2] = z;
+}
+
+// Gamma(k, theta) for k >= 1 by Marsaglia and Tsang's rejection method with a
+// Box-Muller normal (cos branch), attempt j drawn from counter
+// (cell, step, TAG_THERMO, j): words 0, 1 -> normal, word 2 -> acceptance.
+__device__ inline double gamma_mt(double k, uint32_t cell, uint32_t step,
+                                  uint32_t k0, uint32_t k1, double theta,
+                                  bool& cap_hit) {
+  const double d = k - 1.0 / 3.0;
+  const double c = 1.0 / sqrt(9.0 * d);
+  for (uint32_t j = 0; j < (uint32_t)GAMMA_MAX_ATTEMPTS; ++j) {
+    const U4 w = philox4x32_10(U4{cell, step, TAG_THERMO, j}, k0, k1);
+    const double u0 = u01(w.x), u1 = u01(w.y), u2 = u01(w.z);
+    const double g = sqrt(-2.0 * log(u0)) * cos((2.0 * M_PI) * u1);
+    const double t = 1.0 + c * g;
+    if (t <= 0.0) continue;
+    const double V = t * t * t;
+    if (log(u2) < 0.5 * g * g + d - d * V + d * log(V)) return d * V * theta;
+  }
+  cap_hit = true;
+  return k * theta;
+}
+
+// Maxwell-Boltzmann cell thermostat factor xi = sqrt(E_hat / E_k) with
+// E_hat ~ Gamma(3 (N_c - 1) / 2, kT); 1 for N_c < 2 or E_k == 0.
+__device__ inline double thermo_xi(uint32_t cnt, double ek, uint32_t cell,
+                                   uint32_t step, uint32_t k0, uint32_t k1,
+                                   double kT, bool& cap_hit) {
+  if (cnt < 2u || !(ek > 0.0)) return 1.0;
+  const double e_hat =
+      gamma_mt(1.5 * (double)(cnt - 1u), cell, step, k0, k1, kT, cap_hit);
+  return sqrt(e_hat / ek);
+}
+
+// xi * R(alpha, n) in row-major order, R = cos a I + sin a [n]x +
+// (1 - cos a) n n^T (Rodrigues; right-handed rotation by +alpha).
+__device__ inline void rotation_matrix(const double n[3], double ca, double sa,
+                                       double omc, double xi, double R[9]) {
+  R[0] = xi * (ca + omc * n[0] * n[0]);
+  R[1] = xi * (-sa * n[2] + omc * n[0] * n[1]);
+  R[2] = xi * (sa * n[1] + omc * n[0] * n[2]);
+  R[3] = xi * (sa * n[2] + omc * n[1] * n[0]);
+  R[4] = xi * (ca + omc * n[1] * n[1]);
+  R[5] = xi * (-sa * n[0] + omc * n[1] * n[2]);
+  R[6] = xi * (-sa * n[1] + omc * n[2] * n[0]);
+  R[7] = xi * (sa * n[0] + omc * n[2] * n[1]);
+  R[8] = xi * (ca + omc * n[2] * n[2]);
+}
+
+}  // namespace mpcd
