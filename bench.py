@@ -28,15 +28,14 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "srd_100c_rho10_mbthermo"
 
-# Algorithmic bytes per particle of one collide launch (read once / write
-# once what its contract names): list entry 4, state, tag 4 in; state, tag 4,
-# (cell, rank) 8 out; plus the offsets read and the counts written per cell.
+# Algorithmic bytes per particle of one step kernel (what its contract reads
+# once and writes once): the particle state and its 4-byte tag in, the same
+# out. The per-tile counters (a few bytes per ~640 particles) are left out.
 STATE_BYTES = {"fp32": 28, "fp64": 48}
 
 
 def collide_bytes_per_particle(form, rho):
-    s = STATE_BYTES[form]
-    return (4 + s + 4) + (s + 4 + 8) + 8.0 / rho
+    return 2.0 * (STATE_BYTES[form] + 4)
 
 
 def floor_bytes_per_update(form, rho):
@@ -149,7 +148,7 @@ def main():
             "unit": "GB/s",
             "frac": head["collide_GBs"] / HBM_PEAK_GBS,
             "traffic": None,
-            "kernel": "k_collide",
+            "kernel": "k_tile (collide + stream + bin + scatter)",
             "kernel_avg_us": head["collide_avg_us"],
             "bytes_per_particle": collide_bytes_per_particle(head_form, rho),
         },

@@ -68,8 +68,13 @@ typedef struct {
   int32_t precision;   /* mpcd_precision: storage form of positions/velocities   */
   int32_t thermostat;  /* 0 none, 1 Maxwell-Boltzmann cell scaling (sec. 2, 3.6) */
   int32_t grid_shift;  /* 1 random grid shift each step (sec. 2), 0 none         */
-  int32_t flags;       /* reserved, must be 0                                    */
+  int32_t flags;       /* 0, or MPCD_FLAG_TIGHT_SLABS                            */
 } mpcd_params;
+
+/* Test-only layout flag: size the per-tile particle slabs to exactly the
+ * initial maximum occupancy (no headroom), so that the first steps overflow
+ * them and the enlarge-and-replay path runs. Results are unchanged. */
+#define MPCD_FLAG_TIGHT_SLABS 1
 
 /* Create a context and upload the initial state (sec. 3.2 particle data).
  *  pos, vel      n_solvent x 3 doubles; positions inside [0, L) per axis.
@@ -92,19 +97,23 @@ mpcd_status mpcd_create(const mpcd_params* params, int64_t n_solvent,
  * after create or after a collide. */
 mpcd_status mpcd_stream(mpcd_ctx ctx);
 
-/* Binning (sec. 3.4): draw the grid shift of the current step counter n,
- * assign each particle its collision cell on the shifted grid, count the
- * occupancy and build the cell-ordered particle list (count sort).
- * Needs a preceding mpcd_stream. */
+/* Binning (sec. 3.4): draw the grid shift of the current step counter n and
+ * group the particles by the tile of their collision cell on the shifted
+ * grid (tiles are blocks of 4x4x4 to 8x8x4 cells, each owning a fixed-size
+ * slab of particle slots). Needs a preceding mpcd_stream. Waits for the
+ * device at its end: if a tile's slab overflowed, the slabs are enlarged and
+ * the binning redone before returning. */
 mpcd_status mpcd_bin(mpcd_ctx ctx);
 
 /* Collision (sec. 3.5, 3.6, eq. 2, Alg. 1): cell sums, per-cell axis and
- * thermostat factor drawn from counter n, rotation; particles end up stored
- * in cell order. Increments the step counter. Needs a preceding mpcd_bin. */
+ * thermostat factor drawn from counter n, rotation. Increments the step
+ * counter. Needs a preceding mpcd_bin. */
 mpcd_status mpcd_collide(mpcd_ctx ctx);
 
 /* nsteps whole steps (stream, bin, collide), equivalent to calling the three
- * entry points nsteps times. nsteps >= 0. */
+ * entry points nsteps times: one launch per step, each step's collision
+ * fused with the next step's stream and binning. nsteps >= 0. Waits for the
+ * device at its end (see mpcd_bin about slab overflow). */
 mpcd_status mpcd_step(mpcd_ctx ctx, int64_t nsteps);
 
 /* Copy the state out in tag order: pos, vel are n_total x 3 doubles, where
@@ -154,9 +163,16 @@ mpcd_status mpcd_sync(mpcd_ctx ctx);
 /* Counts and sizes: n_total particles, n_cells cells. */
 mpcd_status mpcd_get_sizes(mpcd_ctx ctx, int64_t* n_total, int64_t* n_cells);
 
-/* Kernel timing with HIP events on the context's stream. which: 0 collide,
- * 1 bin (incl. stream+bin), 2 count scan + list. While enabled, each launch
- * of the kernel is bracketed by two events; mpcd_profile_read synchronises,
+/* Particle storage layout: tile size in cells, number of tiles, slots per
+ * tile slab, and how many times the slabs were enlarged. Any pointer may be
+ * NULL. */
+mpcd_status mpcd_get_layout(mpcd_ctx ctx, int32_t tile[3], int64_t* n_tiles,
+                            int64_t* capacity, int64_t* regrows);
+
+/* Kernel timing with HIP events on the context's stream. which: 0 the
+ * collision kernel (collide, stream and bin of the next step), 1 the
+ * stream / stream+bin kernels, 2 unused (always 0 launches). While enabled,
+ * each launch is bracketed by two events; mpcd_profile_read synchronises,
  * returns the summed milliseconds and launch count since the last read,
  * and clears them. */
 mpcd_status mpcd_profile_enable(mpcd_ctx ctx, int32_t on);

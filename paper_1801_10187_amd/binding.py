@@ -18,6 +18,7 @@ HEADER = os.path.join(ROOT, "include", "mpcd.h")
 
 MPCD_OK, MPCD_EINVAL, MPCD_ENOMEM, MPCD_EHIP, MPCD_ERANGE, MPCD_ESTATE = range(6)
 FP64, FP32 = 0, 1
+FLAG_TIGHT_SLABS = 1
 STATUS_NAMES = {0: "MPCD_OK", 1: "MPCD_EINVAL", 2: "MPCD_ENOMEM", 3: "MPCD_EHIP",
                 4: "MPCD_ERANGE", 5: "MPCD_ESTATE"}
 
@@ -74,6 +75,8 @@ def load():
         "mpcd_totals": (st, [_P, _P, _D, _D]),
         "mpcd_sync": (st, [_P]),
         "mpcd_get_sizes": (st, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+        "mpcd_get_layout": (st, [_P, _P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                 ctypes.POINTER(ctypes.c_int64)]),
         "mpcd_profile_enable": (st, [_P, ctypes.c_int32]),
         "mpcd_profile_read": (st, [_P, ctypes.c_int32, _D, ctypes.POINTER(ctypes.c_int64)]),
         "mpcd_destroy": (None, [_P]),
@@ -127,10 +130,10 @@ class Sim:
     def __init__(self, pos, vel, n_cells, a=1.0, alpha=130.0 * math.pi / 180.0,
                  dt=0.1, kT=1.0, seed=1, solvent_mass=1.0, precision=FP64,
                  thermostat=False, grid_shift=True, emb_pos=None, emb_vel=None,
-                 emb_mass=None, hip_stream=None):
+                 emb_mass=None, hip_stream=None, flags=0):
         lib = load()
         self.params = make_params(n_cells, a, alpha, dt, kT, seed, solvent_mass,
-                                  precision, thermostat, grid_shift)
+                                  precision, thermostat, grid_shift, flags)
         pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
         vel = np.ascontiguousarray(vel, dtype=np.float64).reshape(-1, 3)
         n_emb = 0
@@ -214,6 +217,14 @@ class Sim:
         kT = ctypes.c_double()
         _check(load().mpcd_totals(self._ctx, _ptr(p), ctypes.byref(ke), ctypes.byref(kT)))
         return p, ke.value, kT.value
+
+    def layout(self):
+        """(tile size in cells, number of tiles, slots per tile, regrows)."""
+        tile = (ctypes.c_int32 * 3)()
+        nt, cap, rg = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(load().mpcd_get_layout(self._ctx, ctypes.cast(tile, ctypes.c_void_p), ctypes.byref(nt),
+                                      ctypes.byref(cap), ctypes.byref(rg)))
+        return tuple(tile), nt.value, cap.value, rg.value
 
     # -- timing
     def profile(self, on=True):

@@ -1,10 +1,12 @@
 // libmpcd: host side of the C ABI declared in include/mpcd.h.
 //
 // The context owns every device buffer (hipMalloc at create, hipFree at
-// destroy) and enqueues all work on one HIP stream. A step is launched as
-//   stream+bin (first step only) | scan -> list -> collide(+stream+bin next)
-// so that after the first step every step costs one pass over the particles
-// plus the small per-cell scan.
+// destroy) and enqueues all work on one HIP stream. Particles live in
+// fixed-capacity per-tile slabs (see mpcd_kernels.hpp). A call to mpcd_step
+// launches one stream+bin kernel and then one tile kernel per step; it waits
+// for the stream at its end to confirm that no slab overflowed. If one did,
+// the input of the failing launch is still intact: the slabs are enlarged,
+// that input is repacked, and the launches are replayed from there.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,13 +43,28 @@ mpcd_status fail(mpcd_status st, const char* fmt, ...) {
       return fail(MPCD_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));       \
   } while (0)
 
+#define ST_TRY(expr)                    \
+  do {                                  \
+    mpcd_status s_ = (expr);            \
+    if (s_ != MPCD_OK) return s_;       \
+  } while (0)
+
 enum class Phase { Idle, Streamed, Binned };
+
+// One queued kernel of a stepping call.
+enum class Op { BinStream, Bin, CollideScatter, Collide };
+struct Launch {
+  Op op;
+  uint64_t step;
+};
 
 constexpr uint32_t kGrid = 256;  // threads per block of the elementwise kernels
 
 inline uint32_t blocks_for(uint64_t n, uint32_t per) {
   return (uint32_t)((n + per - 1) / per);
 }
+
+inline uint32_t round_up(uint64_t x, uint32_t m) { return (uint32_t)(((x + m - 1) / m) * m); }
 
 }  // namespace
 
@@ -56,41 +73,36 @@ struct mpcd_ctx_s {
   int form = 0;
   uint32_t n_solv = 0, n_emb = 0, N = 0;
   Box box{};
-  int cpb = 128;
+  int cpt = 64;  // cells per tile rounded up to 64/128/256 (kernel template)
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  int device = 0;
 
-  // device memory
-  std::vector<void*> allocs;
+  std::vector<void*> allocs;       // everything but the slabs
+  std::vector<void*> slab_allocs;  // the two particle buffers
   Particles buf[2]{};
   int cur = 0;
-  uint2* cr = nullptr;
-  uint32_t* perm = nullptr;
-  uint32_t* count = nullptr;
-  uint32_t* off = nullptr;
-  uint32_t* partial = nullptr;
-  uint32_t n_partial = 0;
+  uint32_t* cnt[3] = {nullptr, nullptr, nullptr};
+  int ci = 0;                      // cnt[ci] describes buf[cur]
   double* emb_mass = nullptr;
-  uint32_t* err = nullptr;
+  uint32_t* status = nullptr;      // [0] errors, [1] overflow, [2] failing launch
   long long* tot = nullptr;
 
   uint64_t step = 0;
+  uint64_t last_bin_step = 0;
   Phase phase = Phase::Idle;
-  bool have_bin = false;       // a binning has happened
-  bool sorted_by_bin = false;  // current buffer is in the cell order of the last bin
+  bool have_bin = false;
+  int64_t regrows = 0;
 
-  // profiling: pairs of events per instrumented launch
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[3];
 
   void* dalloc(size_t bytes) {
-    void* p = nullptr;
+    void* q = nullptr;
     if (bytes == 0) bytes = 256;
-    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
-    allocs.push_back(p);
-    return p;
+    if (hipMalloc(&q, bytes) != hipSuccess) return nullptr;
+    allocs.push_back(q);
+    return q;
   }
 };
 
@@ -103,15 +115,15 @@ mpcd_status check_ctx(mpcd_ctx c) {
 
 mpcd_status take_err(mpcd_ctx c) {
   uint32_t e = 0;
-  HIP_TRY(hipMemcpyAsync(&e, c->err, sizeof e, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(&e, c->status, sizeof e, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   if (e) {
-    HIP_TRY(hipMemsetAsync(c->err, 0, sizeof e, c->stream));
+    HIP_TRY(hipMemsetAsync(c->status, 0, sizeof e, c->stream));
     return fail(MPCD_ERANGE, "kernel range check failed (flags 0x%x: %s%s%s%s)", e,
                 (e & ERR_STREAM_RANGE) ? "displacement >= box length; " : "",
                 (e & ERR_FIXED_RANGE) ? "value outside fixed-point range; " : "",
                 (e & ERR_GAMMA_CAP) ? "Gamma sampler attempt cap; " : "",
-                (e & ERR_LIST) ? "cell list inconsistent; " : "");
+                (e & ERR_TILE) ? "particle outside its tile; " : "");
   }
   return MPCD_OK;
 }
@@ -154,103 +166,188 @@ struct ProfScope {
   }
 };
 
-// --- launch wrappers
-mpcd_status launch_stream(mpcd_ctx c) {
-  if (c->N == 0) return MPCD_OK;
-  ProfScope ps(c, 1);
-  if (c->form == 0)
-    k_stream<0><<<blocks_for(c->N, kGrid), kGrid, 0, c->stream>>>(c->buf[c->cur], c->box, c->N, c->err);
-  else
-    k_stream<1><<<blocks_for(c->N, kGrid), kGrid, 0, c->stream>>>(c->buf[c->cur], c->box, c->N, c->err);
-  HIP_TRY(hipGetLastError());
-  return MPCD_OK;
+uint32_t slab_blocks(const mpcd_ctx c, uint32_t cap) {
+  return c->box.ntiles * ((cap + 255u) / 256u);
 }
 
-mpcd_status launch_bin(mpcd_ctx c, bool with_stream) {
-  if (c->N == 0) return MPCD_OK;
-  double s[3];
-  float s32[3];
-  shift_for(c, c->step, s, s32);
-  ProfScope ps(c, 1);
-  const uint32_t nb = blocks_for(c->N, kGrid);
-  Particles& P = c->buf[c->cur];
-#define BIN_LAUNCH(F, S)                                                                   \
-  k_bin<F, S><<<nb, kGrid, 0, c->stream>>>(P, c->box, c->N, s[0], s[1], s[2], s32[0], s32[1], \
-                                           s32[2], c->count, c->cr, c->err)
-  if (c->form == 0) {
-    if (with_stream) BIN_LAUNCH(0, true); else BIN_LAUNCH(0, false);
+// --- tile kernel dispatch
+template <int F, int CPT, int MODE, bool SI>
+void tile_inst2(mpcd_ctx c, const TileArgs& a, bool th, bool em) {
+  const uint32_t nb = c->box.ntiles;
+  if (th) {
+    if (em) k_tile<F, CPT, MODE, SI, true, true><<<nb, TT, 0, c->stream>>>(a);
+    else k_tile<F, CPT, MODE, SI, true, false><<<nb, TT, 0, c->stream>>>(a);
   } else {
-    if (with_stream) BIN_LAUNCH(1, true); else BIN_LAUNCH(1, false);
+    if (em) k_tile<F, CPT, MODE, SI, false, true><<<nb, TT, 0, c->stream>>>(a);
+    else k_tile<F, CPT, MODE, SI, false, false><<<nb, TT, 0, c->stream>>>(a);
   }
-#undef BIN_LAUNCH
-  HIP_TRY(hipGetLastError());
-  return MPCD_OK;
 }
 
-// counts -> offsets (count cleared), then the cell-ordered list
-mpcd_status launch_scan_list(mpcd_ctx c) {
-  ProfScope ps(c, 2);
-  const uint32_t C = c->box.ncells;
-  const uint32_t nb = c->n_partial;
-  k_scan_partial<<<nb, SCAN_T, 0, c->stream>>>(c->count, C, c->partial);
-  k_scan_top<<<1, 1024, 0, c->stream>>>(c->partial, nb);
-  k_scan_final<<<nb, SCAN_T, 0, c->stream>>>(c->count, C, c->partial, c->off, c->N);
-  if (c->N) k_perm<<<blocks_for(c->N, kGrid), kGrid, 0, c->stream>>>(c->cr, c->off, c->perm, c->N, c->err);
-  HIP_TRY(hipGetLastError());
-  return MPCD_OK;
-}
-
-template <int F, int CPB, bool SN, bool TH, bool EM>
-void collide_inst(mpcd_ctx c, const CollideArgs& a) {
-  const uint32_t nb = blocks_for(c->box.ncells, CPB);
-  k_collide<F, CPB, SN, TH, EM><<<nb, COLLIDE_T, 0, c->stream>>>(a);
-}
-
-template <int F, int CPB>
-void collide_dispatch3(mpcd_ctx c, const CollideArgs& a, bool sn, bool th, bool em) {
-  if (sn) {
-    if (th) { if (em) collide_inst<F, CPB, true, true, true>(c, a); else collide_inst<F, CPB, true, true, false>(c, a); }
-    else    { if (em) collide_inst<F, CPB, true, false, true>(c, a); else collide_inst<F, CPB, true, false, false>(c, a); }
-  } else {
-    if (th) { if (em) collide_inst<F, CPB, false, true, true>(c, a); else collide_inst<F, CPB, false, true, false>(c, a); }
-    else    { if (em) collide_inst<F, CPB, false, false, true>(c, a); else collide_inst<F, CPB, false, false, false>(c, a); }
+template <int F, int CPT>
+void tile_inst1(mpcd_ctx c, const TileArgs& a, int mode, bool stream_in, bool th, bool em) {
+  switch (mode) {
+    case MODE_BIN:
+      // binning needs no cell sums: thermostat/embedded variants are the same
+      if (stream_in) tile_inst2<F, CPT, MODE_BIN, true>(c, a, false, false);
+      else tile_inst2<F, CPT, MODE_BIN, false>(c, a, false, false);
+      break;
+    case MODE_COLLIDE: tile_inst2<F, CPT, MODE_COLLIDE, false>(c, a, th, em); break;
+    case MODE_COLLIDE_SCATTER: tile_inst2<F, CPT, MODE_COLLIDE_SCATTER, false>(c, a, th, em); break;
+    default: tile_inst2<F, CPT, MODE_DIAG, false>(c, a, th, em); break;
   }
 }
 
 template <int F>
-void collide_dispatch(mpcd_ctx c, const CollideArgs& a, bool sn, bool th, bool em) {
-  switch (c->cpb) {
-    case 256: collide_dispatch3<F, 256>(c, a, sn, th, em); break;
-    case 64: collide_dispatch3<F, 64>(c, a, sn, th, em); break;
-    default: collide_dispatch3<F, 128>(c, a, sn, th, em); break;
+void tile_dispatch(mpcd_ctx c, const TileArgs& a, int mode, bool stream_in) {
+  const bool th = c->p.thermostat != 0, em = c->n_emb > 0;
+  switch (c->cpt) {
+    case 64: tile_inst1<F, 64>(c, a, mode, stream_in, th, em); break;
+    case 128: tile_inst1<F, 128>(c, a, mode, stream_in, th, em); break;
+    default: tile_inst1<F, 256>(c, a, mode, stream_in, th, em); break;
   }
 }
 
-// collide with counter c->step; with stream_next, stream and bin for
-// c->step + 1 as well. Swaps the particle buffers.
-mpcd_status launch_collide(mpcd_ctx c, bool stream_next) {
-  CollideArgs a{};
-  a.cur = c->buf[c->cur];
-  a.nxt = c->buf[1 - c->cur];
+TileArgs tile_args(mpcd_ctx c) {
+  TileArgs a{};
+  a.in = c->buf[c->cur];
+  a.out = c->buf[1 - c->cur];
   a.B = c->box;
-  a.off = c->off;
-  a.perm = c->perm;
+  a.cnt_in = c->cnt[c->ci];
+  a.cnt_out = c->cnt[(c->ci + 1) % 3];
+  a.cnt_clear = c->cnt[(c->ci + 2) % 3];
   a.emb_mass = c->emb_mass;
-  a.step = (uint32_t)c->step;
-  a.step_next = (uint32_t)(c->step + 1);
-  shift_for(c, c->step + 1, a.sn, a.sn32);
-  a.count = c->count;
-  a.cr_next = c->cr;
-  a.err = c->err;
-  if (c->box.ncells > 0) {
-    ProfScope ps(c, 0);
-    const bool th = c->p.thermostat != 0, em = c->n_emb > 0;
-    if (c->form == 0) collide_dispatch<0>(c, a, stream_next, th, em);
-    else collide_dispatch<1>(c, a, stream_next, th, em);
+  a.status = c->status;
+  return a;
+}
+
+mpcd_status launch_tile(mpcd_ctx c, Op op, uint64_t n, uint32_t seq) {
+  TileArgs a = tile_args(c);
+  a.step = (uint32_t)n;
+  a.seq = seq;
+  shift_for(c, n, a.s, a.s32);
+  int mode;
+  bool stream_in = false;
+  switch (op) {
+    case Op::BinStream: mode = MODE_BIN; stream_in = true; break;
+    case Op::Bin: mode = MODE_BIN; break;
+    case Op::CollideScatter: mode = MODE_COLLIDE_SCATTER; shift_for(c, n + 1, a.sn, a.sn32); break;
+    default: mode = MODE_COLLIDE; break;
+  }
+  {
+    ProfScope ps(c, mode == MODE_BIN ? 1 : 0);
+    if (c->form == 0) tile_dispatch<0>(c, a, mode, stream_in);
+    else tile_dispatch<1>(c, a, mode, stream_in);
     HIP_TRY(hipGetLastError());
   }
   c->cur = 1 - c->cur;
+  if (mode != MODE_COLLIDE) c->ci = (c->ci + 1) % 3;
   return MPCD_OK;
+}
+
+// --- slabs
+mpcd_status alloc_slabs(mpcd_ctx c, uint32_t cap, Particles out[2], std::vector<void*>& owned) {
+  const size_t S = (size_t)c->box.ntiles * cap;
+  auto get = [&](size_t bytes) -> void* {
+    void* q = nullptr;
+    if (hipMalloc(&q, bytes ? bytes : 256) != hipSuccess) return nullptr;
+    owned.push_back(q);
+    return q;
+  };
+  for (int b = 0; b < 2; ++b) {
+    Particles& P = out[b];
+    P = Particles{};
+    if (c->form == 0) {
+      for (int d = 0; d < 3; ++d) {
+        P.x[d] = (double*)get(S * 8);
+        P.v[d] = (double*)get(S * 8);
+        if (!P.x[d] || !P.v[d]) return fail(MPCD_ENOMEM, "device allocation of the slabs failed");
+      }
+    } else {
+      P.h = (uint32_t*)get(S * 4);
+      if (!P.h) return fail(MPCD_ENOMEM, "device allocation of the slabs failed");
+      for (int d = 0; d < 3; ++d) {
+        P.o[d] = (float*)get(S * 4);
+        P.vf[d] = (float*)get(S * 4);
+        if (!P.o[d] || !P.vf[d]) return fail(MPCD_ENOMEM, "device allocation of the slabs failed");
+      }
+    }
+    P.tag = (uint32_t*)get(S * 4);
+    if (!P.tag) return fail(MPCD_ENOMEM, "device allocation of the slabs failed");
+  }
+  return MPCD_OK;
+}
+
+void free_all(std::vector<void*>& v) {
+  for (void* q : v) (void)hipFree(q);
+  v.clear();
+}
+
+// A slab overflowed in a launch whose input was (in_cur, in_ci). Enlarge
+// the slabs to hold the largest count the failed launch tried to place (plus
+// headroom), repack that intact input and reset the counters.
+mpcd_status regrow(mpcd_ctx c, int in_cur, int in_ci) {
+  const uint32_t nt = c->box.ntiles;
+  std::vector<uint32_t> want(nt);
+  HIP_TRY(hipMemcpy(want.data(), c->cnt[(in_ci + 1) % 3], (size_t)nt * 4, hipMemcpyDeviceToHost));
+  uint32_t mx = 0;
+  for (uint32_t v : want) mx = std::max(mx, v);
+  const uint32_t old_cap = c->box.cap;
+  const uint64_t target = std::max<uint64_t>((uint64_t)mx + mx / 4 + 64, (uint64_t)old_cap + old_cap / 2);
+  const uint32_t new_cap = round_up(target, 64);
+  if ((uint64_t)new_cap * nt >= (1ull << 32)) return fail(MPCD_ENOMEM, "slab storage beyond 2^32 slots");
+  Particles nb[2];
+  std::vector<void*> owned;
+  mpcd_status st = alloc_slabs(c, new_cap, nb, owned);
+  if (st != MPCD_OK) {
+    free_all(owned);
+    return st;
+  }
+  Box B = c->box;
+  B.cap = new_cap;
+  const uint32_t blocks = nt * ((old_cap + 255u) / 256u);
+  if (c->form == 0)
+    k_repack<0><<<blocks, 256, 0, c->stream>>>(c->buf[in_cur], nb[0], B, old_cap, c->cnt[in_ci]);
+  else
+    k_repack<1><<<blocks, 256, 0, c->stream>>>(c->buf[in_cur], nb[0], B, old_cap, c->cnt[in_ci]);
+  HIP_TRY(hipGetLastError());
+  if (in_ci != 0)
+    HIP_TRY(hipMemcpyAsync(c->cnt[0], c->cnt[in_ci], (size_t)nt * 4, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(hipMemsetAsync(c->cnt[1], 0, (size_t)nt * 4, c->stream));
+  HIP_TRY(hipMemsetAsync(c->cnt[2], 0, (size_t)nt * 4, c->stream));
+  const uint32_t st_reset[2] = {0u, 0xFFFFFFFFu};
+  HIP_TRY(hipMemcpyAsync(c->status + 1, st_reset, 8, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  free_all(c->slab_allocs);
+  c->slab_allocs = owned;
+  c->buf[0] = nb[0];
+  c->buf[1] = nb[1];
+  c->box.cap = new_cap;
+  c->cur = 0;
+  c->ci = 0;
+  c->regrows += 1;
+  return MPCD_OK;
+}
+
+// Run a list of tile launches, then confirm that no slab overflowed; replay
+// from the failing launch after enlarging the slabs if one did.
+mpcd_status run_launches(mpcd_ctx c, const std::vector<Launch>& L) {
+  size_t from = 0;
+  for (int attempt = 0; attempt < 16; ++attempt) {
+    std::vector<std::pair<int, int>> in_state;
+    in_state.reserve(L.size() - from);
+    for (size_t k = from; k < L.size(); ++k) {
+      in_state.emplace_back(c->cur, c->ci);
+      ST_TRY(launch_tile(c, L[k].op, L[k].step, (uint32_t)(k - from)));
+    }
+    uint32_t st[3];
+    HIP_TRY(hipMemcpyAsync(st, c->status, 12, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (st[1] == 0) return MPCD_OK;
+    const size_t bad = std::min<size_t>(st[2], in_state.size() - 1);
+    ST_TRY(regrow(c, in_state[bad].first, in_state[bad].second));
+    from += bad;
+  }
+  return fail(MPCD_ENOMEM, "slab capacity kept overflowing");
 }
 
 mpcd_status validate(const mpcd_params* p, int64_t ns, int64_t ne) {
@@ -269,13 +366,42 @@ mpcd_status validate(const mpcd_params* p, int64_t ns, int64_t ne) {
     return fail(MPCD_EINVAL, "precision must be MPCD_FP64 or MPCD_FP32");
   if (p->thermostat != 0 && p->thermostat != 1) return fail(MPCD_EINVAL, "thermostat must be 0 or 1");
   if (p->grid_shift != 0 && p->grid_shift != 1) return fail(MPCD_EINVAL, "grid_shift must be 0 or 1");
-  if (p->flags != 0) return fail(MPCD_EINVAL, "flags must be 0");
+  if ((uint32_t)p->flags & ~(uint32_t)MPCD_FLAG_TIGHT_SLABS) return fail(MPCD_EINVAL, "unknown flags");
   if (p->precision == MPCD_FP32)
     for (int d = 0; d < 3; ++d)
       if (p->n_cells[d] > 1024) return fail(MPCD_EINVAL, "FP32 form supports at most 1024 cells per axis");
   if (ns < 0 || ne < 0) return fail(MPCD_EINVAL, "negative particle count");
   if (ns + ne >= (int64_t)1 << 31) return fail(MPCD_EINVAL, "at most 2^31 - 1 particles");
   return MPCD_OK;
+}
+
+// Tile shape: about 640 particles per tile at the system's mean density.
+void choose_tiles(mpcd_ctx c) {
+  Box& B = c->box;
+  const double rho = B.ncells ? (double)c->N / (double)B.ncells : 0.0;
+  int td[3];
+  if (rho >= 7.0) {
+    td[0] = 4; td[1] = 4; td[2] = 4; c->cpt = 64;
+  } else if (rho >= 3.5) {
+    td[0] = 8; td[1] = 4; td[2] = 4; c->cpt = 128;
+  } else {
+    td[0] = 8; td[1] = 8; td[2] = 4; c->cpt = 256;
+  }
+  B.ntiles = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (B.n[d] <= td[d]) {
+      B.td[d] = B.n[d];
+      B.nt[d] = 1;
+      B.tsh[d] = 0;
+    } else {
+      B.td[d] = td[d];
+      B.nt[d] = (B.n[d] + td[d] - 1) / td[d];
+      int sh = 0;
+      while ((1 << sh) < td[d]) ++sh;
+      B.tsh[d] = sh;
+    }
+    B.ntiles *= (uint32_t)B.nt[d];
+  }
 }
 
 }  // namespace
@@ -297,7 +423,6 @@ mpcd_status mpcd_create(const mpcd_params* params, int64_t n_solvent, const doub
   if (n_solvent > 0 && (!pos || !vel)) return fail(MPCD_EINVAL, "pos/vel NULL");
   if (n_embedded > 0 && (!emb_pos || !emb_vel || !emb_mass))
     return fail(MPCD_EINVAL, "embedded arrays NULL");
-  std::vector<double> hmass;
   if (n_embedded > 0 && !pointers_on_device) {
     for (int64_t i = 0; i < n_embedded; ++i)
       if (!(emb_mass[i] > 0.0) || !std::isfinite(emb_mass[i]))
@@ -307,7 +432,9 @@ mpcd_status mpcd_create(const mpcd_params* params, int64_t n_solvent, const doub
   mpcd_ctx c = new (std::nothrow) mpcd_ctx_s();
   if (!c) return fail(MPCD_ENOMEM, "host allocation failed");
   auto cleanup = [&](mpcd_status s) {
+    std::string keep = g_err;
     mpcd_destroy(c);
+    g_err = keep;
     return s;
   };
   c->p = *params;
@@ -335,102 +462,128 @@ mpcd_status mpcd_create(const mpcd_params* params, int64_t n_solvent, const doub
   B.k0 = (uint32_t)(params->seed & 0xFFFFFFFFull);
   B.k1 = (uint32_t)(params->seed >> 32);
   B.n_solvent = c->n_solv;
-  const double rho = B.ncells ? (double)c->N / (double)B.ncells : 0.0;
-  c->cpb = rho * 256.0 <= 1400.0 ? 256 : (rho * 128.0 <= 1400.0 ? 128 : 64);
+  choose_tiles(c);
 
-  if (hipGetDevice(&c->device) != hipSuccess) return cleanup(fail(MPCD_EHIP, "no HIP device"));
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
   } else {
     if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
-      return cleanup(fail(MPCD_EHIP, "hipStreamCreate failed"));
+      return cleanup(fail(MPCD_EHIP, "hipStreamCreate failed (no usable GPU?)"));
     c->own_stream = true;
   }
-
-  const size_t N = c->N;
-  const size_t C = B.ncells;
-  for (int b = 0; b < 2; ++b) {
-    Particles& P = c->buf[b];
-    if (c->form == 0) {
-      for (int d = 0; d < 3; ++d) {
-        P.x[d] = (double*)c->dalloc(N * 8);
-        P.v[d] = (double*)c->dalloc(N * 8);
-        if (!P.x[d] || !P.v[d]) return cleanup(fail(MPCD_ENOMEM, "device allocation failed"));
-      }
-    } else {
-      P.h = (uint32_t*)c->dalloc(N * 4);
-      if (!P.h) return cleanup(fail(MPCD_ENOMEM, "device allocation failed"));
-      for (int d = 0; d < 3; ++d) {
-        P.o[d] = (float*)c->dalloc(N * 4);
-        P.vf[d] = (float*)c->dalloc(N * 4);
-        if (!P.o[d] || !P.vf[d]) return cleanup(fail(MPCD_ENOMEM, "device allocation failed"));
-      }
-    }
-    P.tag = (uint32_t*)c->dalloc(N * 4);
-    if (!P.tag) return cleanup(fail(MPCD_ENOMEM, "device allocation failed"));
-  }
-  c->n_partial = blocks_for(C, SCAN_CHUNK);
-  c->cr = (uint2*)c->dalloc(N * 8);
-  c->perm = (uint32_t*)c->dalloc(N * 4);
-  c->count = (uint32_t*)c->dalloc(C * 4 + 64);
-  c->off = (uint32_t*)c->dalloc(C * 4 + 64);
-  c->partial = (uint32_t*)c->dalloc((size_t)c->n_partial * 4);
-  c->err = (uint32_t*)c->dalloc(256);
+  const size_t NT = B.ntiles;
+  for (int k = 0; k < 3; ++k) c->cnt[k] = (uint32_t*)c->dalloc(NT * 4);
+  c->status = (uint32_t*)c->dalloc(256);
   c->tot = (long long*)c->dalloc(10 * 8);
   c->emb_mass = (double*)c->dalloc((size_t)c->n_emb * 8);
-  if (!c->cr || !c->perm || !c->count || !c->off || !c->partial || !c->err || !c->tot ||
-      !c->emb_mass)
+  uint32_t* bad = (uint32_t*)c->dalloc(256);
+  if (!c->cnt[0] || !c->cnt[1] || !c->cnt[2] || !c->status || !c->tot || !c->emb_mass || !bad)
     return cleanup(fail(MPCD_ENOMEM, "device allocation failed"));
-  if (hipMemsetAsync(c->count, 0, C * 4 + 64, c->stream) != hipSuccess ||
-      hipMemsetAsync(c->err, 0, 256, c->stream) != hipSuccess)
+  const uint32_t st_init[3] = {0u, 0u, 0xFFFFFFFFu};
+  if (hipMemsetAsync(c->cnt[0], 0, NT * 4, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->cnt[1], 0, NT * 4, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->cnt[2], 0, NT * 4, c->stream) != hipSuccess ||
+      hipMemsetAsync(bad, 0, 256, c->stream) != hipSuccess ||
+      hipMemcpyAsync(c->status, st_init, 12, hipMemcpyHostToDevice, c->stream) != hipSuccess)
     return cleanup(fail(MPCD_EHIP, "hipMemset failed"));
 
-  // import: host arrays are staged through a temporary device buffer
-  uint32_t* bad = (uint32_t*)c->dalloc(256);
-  if (!bad || hipMemsetAsync(bad, 0, 256, c->stream) != hipSuccess)
-    return cleanup(fail(MPCD_ENOMEM, "device allocation failed"));
-  auto import = [&](const double* hp, const double* hv, uint32_t n, uint32_t tag0) -> mpcd_status {
-    if (n == 0) return MPCD_OK;
-    const double* dp = hp;
-    const double* dv = hv;
-    double* tmp = nullptr;
-    if (!pointers_on_device) {
-      if (hipMalloc(&tmp, (size_t)n * 48) != hipSuccess)
-        return fail(MPCD_ENOMEM, "device allocation of the upload buffer failed");
-      if (hipMemcpyAsync(tmp, hp, (size_t)n * 24, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-          hipMemcpyAsync(tmp + 3 * (size_t)n, hv, (size_t)n * 24, hipMemcpyHostToDevice, c->stream) != hipSuccess) {
-        (void)hipFree(tmp);
-        return fail(MPCD_EHIP, "upload failed");
+  // upload: host arrays are staged through temporary device buffers
+  struct Src {
+    const double* p;
+    const double* v;
+    uint32_t n, tag0;
+    double* tmp;
+  } src[2] = {{pos, vel, c->n_solv, 0u, nullptr}, {emb_pos, emb_vel, c->n_emb, c->n_solv, nullptr}};
+  auto free_tmp = [&]() {
+    for (auto& s : src)
+      if (s.tmp) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(s.tmp);
+        s.tmp = nullptr;
       }
-      dp = tmp;
-      dv = tmp + 3 * (size_t)n;
-    }
-    if (c->form == 0)
-      k_import<0><<<blocks_for(n, kGrid), kGrid, 0, c->stream>>>(c->buf[0], B, dp, dv, n, tag0, bad);
-    else
-      k_import<1><<<blocks_for(n, kGrid), kGrid, 0, c->stream>>>(c->buf[0], B, dp, dv, n, tag0, bad);
-    hipError_t e = hipGetLastError();
-    if (tmp) {
-      (void)hipStreamSynchronize(c->stream);
-      (void)hipFree(tmp);
-    }
-    if (e != hipSuccess) return fail(MPCD_EHIP, "import kernel: %s", hipGetErrorString(e));
-    return MPCD_OK;
   };
-  if ((st = import(pos, vel, c->n_solv, 0)) != MPCD_OK) return cleanup(st);
-  if ((st = import(emb_pos, emb_vel, c->n_emb, c->n_solv)) != MPCD_OK) return cleanup(st);
+  for (auto& s : src) {
+    if (s.n == 0 || pointers_on_device) continue;
+    if (hipMalloc(&s.tmp, (size_t)s.n * 48) != hipSuccess) {
+      free_tmp();
+      return cleanup(fail(MPCD_ENOMEM, "device allocation of the upload buffer failed"));
+    }
+    if (hipMemcpyAsync(s.tmp, s.p, (size_t)s.n * 24, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(s.tmp + 3 * (size_t)s.n, s.v, (size_t)s.n * 24, hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+      free_tmp();
+      return cleanup(fail(MPCD_EHIP, "upload failed"));
+    }
+    s.p = s.tmp;
+    s.v = s.tmp + 3 * (size_t)s.n;
+  }
+  // pass 1: count per tile, check the box
+  for (auto& s : src) {
+    if (s.n == 0) continue;
+    if (c->form == 0)
+      k_import<0, false><<<blocks_for(s.n, kGrid), kGrid, 0, c->stream>>>(c->buf[0], B, s.p, s.v, s.n, s.tag0, c->cnt[1], bad);
+    else
+      k_import<1, false><<<blocks_for(s.n, kGrid), kGrid, 0, c->stream>>>(c->buf[0], B, s.p, s.v, s.n, s.tag0, c->cnt[1], bad);
+  }
+  std::vector<uint32_t> cnt_h(NT);
+  uint32_t hbad = 0;
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(cnt_h.data(), c->cnt[1], NT * 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    free_tmp();
+    return cleanup(fail(MPCD_EHIP, "create: import failed"));
+  }
+  if (hbad) {
+    free_tmp();
+    return cleanup(fail(MPCD_EINVAL, "a position lies outside [0, L)"));
+  }
+  uint32_t mx = 0;
+  for (uint32_t v : cnt_h) mx = std::max(mx, v);
+  const double mean = NT ? (double)c->N / (double)NT : 0.0;
+  if ((uint32_t)params->flags & MPCD_FLAG_TIGHT_SLABS) {
+    B.cap = std::max<uint32_t>(mx, 1u);
+  } else {
+    const uint64_t cap = std::max<uint64_t>((uint64_t)mx + mx / 5, (uint64_t)(mean + 8.0 * std::sqrt(mean) + 64.0));
+    B.cap = round_up(cap, 32);
+  }
+  if ((uint64_t)B.cap * NT >= (1ull << 32)) {
+    free_tmp();
+    return cleanup(fail(MPCD_ENOMEM, "slab storage beyond 2^32 slots"));
+  }
+  if ((st = alloc_slabs(c, B.cap, c->buf, c->slab_allocs)) != MPCD_OK) {
+    free_tmp();
+    return cleanup(st);
+  }
+  if (hipMemsetAsync(c->cnt[1], 0, NT * 4, c->stream) != hipSuccess) {
+    free_tmp();
+    return cleanup(fail(MPCD_EHIP, "hipMemset failed"));
+  }
+  // pass 2: place
+  for (auto& s : src) {
+    if (s.n == 0) continue;
+    if (c->form == 0)
+      k_import<0, true><<<blocks_for(s.n, kGrid), kGrid, 0, c->stream>>>(c->buf[0], B, s.p, s.v, s.n, s.tag0, c->cnt[0], bad);
+    else
+      k_import<1, true><<<blocks_for(s.n, kGrid), kGrid, 0, c->stream>>>(c->buf[0], B, s.p, s.v, s.n, s.tag0, c->cnt[0], bad);
+  }
   if (c->n_emb) {
     if (hipMemcpyAsync(c->emb_mass, emb_mass, (size_t)c->n_emb * 8,
                        pointers_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
-                       c->stream) != hipSuccess)
+                       c->stream) != hipSuccess) {
+      free_tmp();
       return cleanup(fail(MPCD_EHIP, "upload of embedded masses failed"));
+    }
   }
-  uint32_t hbad = 0;
-  if (hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-      hipStreamSynchronize(c->stream) != hipSuccess)
-    return cleanup(fail(MPCD_EHIP, "create: synchronisation failed"));
-  if (hbad) return cleanup(fail(MPCD_EINVAL, "a position lies outside [0, L)"));
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    free_tmp();
+    return cleanup(fail(MPCD_EHIP, "create: placement failed"));
+  }
+  free_tmp();
+  if (hbad) return cleanup(fail(MPCD_EHIP, "create: placement exceeded the slab capacity"));
   c->cur = 0;
+  c->ci = 0;
   c->step = 0;
   c->phase = Phase::Idle;
   *out = c;
@@ -440,7 +593,8 @@ mpcd_status mpcd_create(const mpcd_params* params, int64_t n_solvent, const doub
 void mpcd_destroy(mpcd_ctx c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  for (void* p : c->allocs) (void)hipFree(p);
+  free_all(c->allocs);
+  free_all(c->slab_allocs);
   for (auto& v : c->ev_used)
     for (auto& pr : v) {
       (void)hipEventDestroy(pr.first);
@@ -452,60 +606,60 @@ void mpcd_destroy(mpcd_ctx c) {
 }
 
 mpcd_status mpcd_stream(mpcd_ctx c) {
-  mpcd_status st = check_ctx(c);
-  if (st) return st;
+  ST_TRY(check_ctx(c));
   if (c->phase != Phase::Idle) return fail(MPCD_ESTATE, "mpcd_stream: expected the state after create or collide");
-  if ((st = launch_stream(c)) != MPCD_OK) return st;
+  if (c->N) {
+    ProfScope ps(c, 1);
+    const uint32_t nb = slab_blocks(c, c->box.cap);
+    if (c->form == 0) k_stream<0><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->box, c->cnt[c->ci], c->status);
+    else k_stream<1><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->box, c->cnt[c->ci], c->status);
+    HIP_TRY(hipGetLastError());
+  }
   c->phase = Phase::Streamed;
   return MPCD_OK;
 }
 
 mpcd_status mpcd_bin(mpcd_ctx c) {
-  mpcd_status st = check_ctx(c);
-  if (st) return st;
+  ST_TRY(check_ctx(c));
   if (c->phase != Phase::Streamed) return fail(MPCD_ESTATE, "mpcd_bin: expected a preceding mpcd_stream");
   if (c->step >= 0xFFFFFFFFull) return fail(MPCD_ERANGE, "step counter beyond 2^32 - 1");
-  if ((st = launch_bin(c, false)) != MPCD_OK) return st;
-  if ((st = launch_scan_list(c)) != MPCD_OK) return st;
+  ST_TRY(run_launches(c, {Launch{Op::Bin, c->step}}));
   c->phase = Phase::Binned;
   c->have_bin = true;
-  c->sorted_by_bin = false;
+  c->last_bin_step = c->step;
   return MPCD_OK;
 }
 
 mpcd_status mpcd_collide(mpcd_ctx c) {
-  mpcd_status st = check_ctx(c);
-  if (st) return st;
+  ST_TRY(check_ctx(c));
   if (c->phase != Phase::Binned) return fail(MPCD_ESTATE, "mpcd_collide: expected a preceding mpcd_bin");
-  if ((st = launch_collide(c, false)) != MPCD_OK) return st;
+  ST_TRY(launch_tile(c, Op::Collide, c->step, 0));
   c->step += 1;
   c->phase = Phase::Idle;
-  c->sorted_by_bin = true;
   return MPCD_OK;
 }
 
 mpcd_status mpcd_step(mpcd_ctx c, int64_t nsteps) {
-  mpcd_status st = check_ctx(c);
-  if (st) return st;
+  ST_TRY(check_ctx(c));
   if (nsteps < 0) return fail(MPCD_EINVAL, "nsteps < 0");
   if (c->phase != Phase::Idle) return fail(MPCD_ESTATE, "mpcd_step: expected the state after create or collide");
   if (nsteps == 0) return MPCD_OK;
   if (c->step + (uint64_t)nsteps > 0xFFFFFFFFull) return fail(MPCD_ERANGE, "step counter beyond 2^32 - 1");
-  if ((st = launch_bin(c, true)) != MPCD_OK) return st;
-  for (int64_t k = 0; k < nsteps; ++k) {
-    if ((st = launch_scan_list(c)) != MPCD_OK) return st;
-    if ((st = launch_collide(c, k + 1 < nsteps)) != MPCD_OK) return st;
-    c->step += 1;
-  }
+  std::vector<Launch> L;
+  L.reserve((size_t)nsteps + 1);
+  L.push_back({Op::BinStream, c->step});
+  for (int64_t k = 0; k < nsteps; ++k)
+    L.push_back({k + 1 < nsteps ? Op::CollideScatter : Op::Collide, c->step + (uint64_t)k});
+  ST_TRY(run_launches(c, L));
+  c->step += (uint64_t)nsteps;
+  c->last_bin_step = c->step - 1;
   c->have_bin = true;
-  c->sorted_by_bin = true;
   c->phase = Phase::Idle;
   return MPCD_OK;
 }
 
 mpcd_status mpcd_get_state(mpcd_ctx c, double* pos, double* vel, int32_t on_device) {
-  mpcd_status st = check_ctx(c);
-  if (st) return st;
+  ST_TRY(check_ctx(c));
   if (!pos || !vel) return fail(MPCD_EINVAL, "pos/vel NULL");
   if (c->N == 0) return take_err(c);
   double* dp = pos;
@@ -516,10 +670,11 @@ mpcd_status mpcd_get_state(mpcd_ctx c, double* pos, double* vel, int32_t on_devi
     dp = tmp;
     dv = tmp + 3 * (size_t)c->N;
   }
+  const uint32_t nb = slab_blocks(c, c->box.cap);
   if (c->form == 0)
-    k_export<0><<<blocks_for(c->N, kGrid), kGrid, 0, c->stream>>>(c->buf[c->cur], c->box, c->N, dp, dv);
+    k_export<0><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->box, c->cnt[c->ci], dp, dv);
   else
-    k_export<1><<<blocks_for(c->N, kGrid), kGrid, 0, c->stream>>>(c->buf[c->cur], c->box, c->N, dp, dv);
+    k_export<1><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->box, c->cnt[c->ci], dp, dv);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && tmp) {
     e = hipMemcpyAsync(pos, dp, (size_t)c->N * 24, hipMemcpyDeviceToHost, c->stream);
@@ -532,8 +687,7 @@ mpcd_status mpcd_get_state(mpcd_ctx c, double* pos, double* vel, int32_t on_devi
 }
 
 mpcd_status mpcd_get_cells(mpcd_ctx c, int32_t* cell_of_tag, int32_t* counts, int32_t on_device) {
-  mpcd_status st = check_ctx(c);
-  if (st) return st;
+  ST_TRY(check_ctx(c));
   if (!c->have_bin) return fail(MPCD_ESTATE, "mpcd_get_cells: nothing has been binned");
   const size_t C = c->box.ncells;
   int32_t* dcell = cell_of_tag;
@@ -544,15 +698,19 @@ mpcd_status mpcd_get_cells(mpcd_ctx c, int32_t* cell_of_tag, int32_t* counts, in
     dcell = cell_of_tag ? tmp : nullptr;
     dcnt = counts ? tmp + c->N : nullptr;
   }
-  if (c->sorted_by_bin) {
-    if (C) k_cells_from_order<<<blocks_for(C, kGrid), kGrid, 0, c->stream>>>(c->buf[c->cur].tag, c->off, (uint32_t)C, dcell, dcnt);
-  } else {
-    if (dcell && c->N)
-      k_cells_from_cr<<<blocks_for(c->N, kGrid), kGrid, 0, c->stream>>>(c->buf[c->cur].tag, c->cr, c->N, dcell);
-    if (dcnt && C)
-      k_cells_from_order<<<blocks_for(C, kGrid), kGrid, 0, c->stream>>>(c->buf[c->cur].tag, c->off, (uint32_t)C, nullptr, dcnt);
+  hipError_t e = hipSuccess;
+  if (dcnt && C) e = hipMemsetAsync(dcnt, 0, C * 4, c->stream);
+  double s[3];
+  float s32[3];
+  shift_for(c, c->last_bin_step, s, s32);
+  if (e == hipSuccess && c->N && (dcell || dcnt)) {
+    const uint32_t nb = slab_blocks(c, c->box.cap);
+    if (c->form == 0)
+      k_cells<0><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->box, c->cnt[c->ci], s[0], s[1], s[2], s32[0], s32[1], s32[2], dcell, (uint32_t*)dcnt);
+    else
+      k_cells<1><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->box, c->cnt[c->ci], s[0], s[1], s[2], s32[0], s32[1], s32[2], dcell, (uint32_t*)dcnt);
+    e = hipGetLastError();
   }
-  hipError_t e = hipGetLastError();
   if (e == hipSuccess && tmp) {
     if (cell_of_tag && c->N) e = hipMemcpyAsync(cell_of_tag, dcell, (size_t)c->N * 4, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess && counts && C) e = hipMemcpyAsync(counts, dcnt, C * 4, hipMemcpyDeviceToHost, c->stream);
@@ -565,37 +723,34 @@ mpcd_status mpcd_get_cells(mpcd_ctx c, int32_t* cell_of_tag, int32_t* counts, in
 
 static mpcd_status cell_diag(mpcd_ctx c, double* mass, double* mom, double* ek, double* axis,
                              double* xi, int32_t on_device) {
-  mpcd_status st = check_ctx(c);
-  if (st) return st;
+  ST_TRY(check_ctx(c));
   if (c->phase != Phase::Binned) return fail(MPCD_ESTATE, "cell diagnostics need the binned state");
   const size_t C = c->box.ncells;
   if (C == 0) return MPCD_OK;
   double* tmp = nullptr;
   HIP_TRY(hipMalloc(&tmp, C * 8 * 9));
-  double *dm = tmp, *dmom = tmp + C, *dek = tmp + 4 * C, *dax = tmp + 5 * C, *dxi = tmp + 8 * C;
-  const bool th = c->p.thermostat != 0, em = c->n_emb > 0;
-  const uint32_t nb = blocks_for(C, kGrid);
-  const Particles P = c->buf[c->cur];
-#define DIAG(F, T, E)                                                                     \
-  k_cell_diag<F, T, E><<<nb, kGrid, 0, c->stream>>>(P, c->box, c->off, c->perm, c->emb_mass, \
-                                                    (uint32_t)c->step, dm, dek, dax, dxi, c->err)
-#define MOM(F, E) \
-  k_cell_momentum<F, E><<<nb, kGrid, 0, c->stream>>>(P, c->box, c->off, c->perm, c->emb_mass, dmom, c->err)
-  if (c->form == 0) {
-    if (th) { if (em) DIAG(0, true, true); else DIAG(0, true, false); }
-    else    { if (em) DIAG(0, false, true); else DIAG(0, false, false); }
-    if (em) MOM(0, true); else MOM(0, false);
-  } else {
-    if (th) { if (em) DIAG(1, true, true); else DIAG(1, true, false); }
-    else    { if (em) DIAG(1, false, true); else DIAG(1, false, false); }
-    if (em) MOM(1, true); else MOM(1, false);
+  TileArgs a = tile_args(c);
+  a.cnt_out = nullptr;
+  a.cnt_clear = nullptr;
+  a.step = (uint32_t)c->step;
+  shift_for(c, c->step, a.s, a.s32);
+  a.d_mass = tmp;
+  a.d_mom = tmp + C;
+  a.d_ek = tmp + 4 * C;
+  a.d_axis = tmp + 5 * C;
+  a.d_xi = tmp + 8 * C;
+  hipError_t e = hipMemsetAsync(tmp, 0, C * 8 * 9, c->stream);
+  if (e == hipSuccess) {
+    if (c->form == 0) tile_dispatch<0>(c, a, MODE_DIAG, false);
+    else tile_dispatch<1>(c, a, MODE_DIAG, false);
+    e = hipGetLastError();
   }
-#undef DIAG
-#undef MOM
-  hipError_t e = hipGetLastError();
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-  struct { double* dst; double* src; size_t n; } cp[5] = {
-      {mass, dm, C}, {mom, dmom, 3 * C}, {ek, dek, C}, {axis, dax, 3 * C}, {xi, dxi, C}};
+  struct {
+    double* dst;
+    double* src;
+    size_t n;
+  } cp[5] = {{mass, a.d_mass, C}, {mom, a.d_mom, 3 * C}, {ek, a.d_ek, C}, {axis, a.d_axis, 3 * C}, {xi, a.d_xi, C}};
   for (auto& q : cp)
     if (e == hipSuccess && q.dst) e = hipMemcpyAsync(q.dst, q.src, q.n * 8, kind, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -614,8 +769,7 @@ mpcd_status mpcd_get_cell_draws(mpcd_ctx c, double* axis, double* xi, int32_t on
 }
 
 mpcd_status mpcd_get_shift(mpcd_ctx c, uint64_t n, double s[3]) {
-  mpcd_status st = check_ctx(c);
-  if (st) return st;
+  ST_TRY(check_ctx(c));
   if (!s) return fail(MPCD_EINVAL, "s is NULL");
   float s32[3];
   shift_for(c, n, s, s32);
@@ -623,16 +777,14 @@ mpcd_status mpcd_get_shift(mpcd_ctx c, uint64_t n, double s[3]) {
 }
 
 mpcd_status mpcd_get_step(mpcd_ctx c, uint64_t* n) {
-  mpcd_status st = check_ctx(c);
-  if (st) return st;
+  ST_TRY(check_ctx(c));
   if (!n) return fail(MPCD_EINVAL, "n is NULL");
   *n = c->step;
   return MPCD_OK;
 }
 
 mpcd_status mpcd_set_step(mpcd_ctx c, uint64_t n) {
-  mpcd_status st = check_ctx(c);
-  if (st) return st;
+  ST_TRY(check_ctx(c));
   if (c->phase != Phase::Idle) return fail(MPCD_ESTATE, "mpcd_set_step: only between steps");
   if (n >= 0xFFFFFFFFull) return fail(MPCD_ERANGE, "step counter beyond 2^32 - 1");
   c->step = n;
@@ -640,20 +792,20 @@ mpcd_status mpcd_set_step(mpcd_ctx c, uint64_t n) {
 }
 
 mpcd_status mpcd_totals(mpcd_ctx c, double p[3], double* ke, double* kT) {
-  mpcd_status st = check_ctx(c);
-  if (st) return st;
+  ST_TRY(check_ctx(c));
   long long h[10] = {0};
   if (c->N) {
     HIP_TRY(hipMemsetAsync(c->tot, 0, 80, c->stream));
-    const uint32_t nb = std::min<uint32_t>(blocks_for(c->N, kGrid), 2048u);
+    const uint32_t nb = slab_blocks(c, c->box.cap);
     const bool em = c->n_emb > 0;
     const Particles P = c->buf[c->cur];
+    const uint32_t* cn = c->cnt[c->ci];
     if (c->form == 0) {
-      if (em) k_totals<0, true><<<nb, 256, 0, c->stream>>>(P, c->box, c->N, c->emb_mass, c->tot, c->err);
-      else k_totals<0, false><<<nb, 256, 0, c->stream>>>(P, c->box, c->N, c->emb_mass, c->tot, c->err);
+      if (em) k_totals<0, true><<<nb, 256, 0, c->stream>>>(P, c->box, cn, c->emb_mass, c->tot, c->status);
+      else k_totals<0, false><<<nb, 256, 0, c->stream>>>(P, c->box, cn, c->emb_mass, c->tot, c->status);
     } else {
-      if (em) k_totals<1, true><<<nb, 256, 0, c->stream>>>(P, c->box, c->N, c->emb_mass, c->tot, c->err);
-      else k_totals<1, false><<<nb, 256, 0, c->stream>>>(P, c->box, c->N, c->emb_mass, c->tot, c->err);
+      if (em) k_totals<1, true><<<nb, 256, 0, c->stream>>>(P, c->box, cn, c->emb_mass, c->tot, c->status);
+      else k_totals<1, false><<<nb, 256, 0, c->stream>>>(P, c->box, cn, c->emb_mass, c->tot, c->status);
     }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(h, c->tot, 80, hipMemcpyDeviceToHost, c->stream));
@@ -672,30 +824,37 @@ mpcd_status mpcd_totals(mpcd_ctx c, double p[3], double* ke, double* kT) {
 }
 
 mpcd_status mpcd_sync(mpcd_ctx c) {
-  mpcd_status st = check_ctx(c);
-  if (st) return st;
+  ST_TRY(check_ctx(c));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return take_err(c);
 }
 
 mpcd_status mpcd_get_sizes(mpcd_ctx c, int64_t* n_total, int64_t* n_cells) {
-  mpcd_status st = check_ctx(c);
-  if (st) return st;
+  ST_TRY(check_ctx(c));
   if (n_total) *n_total = c->N;
   if (n_cells) *n_cells = c->box.ncells;
   return MPCD_OK;
 }
 
+mpcd_status mpcd_get_layout(mpcd_ctx c, int32_t tile[3], int64_t* n_tiles, int64_t* capacity,
+                            int64_t* regrows) {
+  ST_TRY(check_ctx(c));
+  if (tile)
+    for (int d = 0; d < 3; ++d) tile[d] = c->box.td[d];
+  if (n_tiles) *n_tiles = c->box.ntiles;
+  if (capacity) *capacity = c->box.cap;
+  if (regrows) *regrows = c->regrows;
+  return MPCD_OK;
+}
+
 mpcd_status mpcd_profile_enable(mpcd_ctx c, int32_t on) {
-  mpcd_status st = check_ctx(c);
-  if (st) return st;
+  ST_TRY(check_ctx(c));
   c->prof = on != 0;
   return MPCD_OK;
 }
 
 mpcd_status mpcd_profile_read(mpcd_ctx c, int32_t which, double* total_ms, int64_t* launches) {
-  mpcd_status st = check_ctx(c);
-  if (st) return st;
+  ST_TRY(check_ctx(c));
   if (which < 0 || which > 2) return fail(MPCD_EINVAL, "which must be 0, 1 or 2");
   HIP_TRY(hipStreamSynchronize(c->stream));
   double ms = 0.0;

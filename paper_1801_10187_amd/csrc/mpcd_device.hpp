@@ -68,7 +68,7 @@ struct Fx {
   long long hi, lo;
 };
 
-__device__ inline void fx_add(Fx& acc, double x, bool& bad) {
+__device__ inline void fx_split(double x, long long& hi, long long& lo, bool& bad) {
   const double C = 6755399441055744.0;  // 1.5 * 2^52: rounds to an integer
   const long long CB = 0x4338000000000000LL;
   bad |= !(fabs(x) < 0x1p30);
@@ -76,8 +76,15 @@ __device__ inline void fx_add(Fx& acc, double x, bool& bad) {
   const double hd = t - C;  // exact
   const double r = x - hd * 0x1p-20;  // exact
   const double t2 = r * 0x1p72 + C;
-  acc.hi += __double_as_longlong(t) - CB;
-  acc.lo += __double_as_longlong(t2) - CB;
+  hi = __double_as_longlong(t) - CB;
+  lo = __double_as_longlong(t2) - CB;
+}
+
+__device__ inline void fx_add(Fx& acc, double x, bool& bad) {
+  long long hi, lo;
+  fx_split(x, hi, lo, bad);
+  acc.hi += hi;
+  acc.lo += lo;
 }
 
 __device__ inline double fx_value(const Fx& a) {

@@ -1,27 +1,40 @@
 // Kernels of the SRD step on gfx950 (wave64, 160 KB LDS per CU, 8 XCDs).
 //
-// Data layout in HBM (structure of arrays, one array per component so every
-// per-particle access is a unit-stride stream):
-//   FP64 form: x[3][N], v[3][N] double.
-//   FP32 form: h[N] home cell packed 10:10:10, o[3][N] float offset in the
-//              home cell, v[3][N] float.
-//   tag[N] uint32 (particle identity), all of the above double-buffered.
-//   cr[N] (cell, rank) of each particle in the current order, perm[N] the
-//   cell-ordered list, count[C] / off[C+1] per-cell occupancy and offsets.
+// Data layout in HBM. The box is cut into tiles of td[0] x td[1] x td[2]
+// cells (4x4x4 or 4x4x8). Every tile owns a slab of `cap` particle slots in
+// each of two buffers; the first cnt[T] slots of tile T hold its particles in
+// no particular order. Within a slab the data is structure of arrays, one
+// array per component, so a block reads and writes its tile as unit-stride
+// streams:
+//   FP64 form: x[3][S], v[3][S] double;
+//   FP32 form: h[S] home cell packed 10:10:10, o[3][S] float offset inside the
+//              home cell, v[3][S] float;
+//   tag[S] uint32 particle identity;            S = ntiles * cap.
 //
-// One step in steady state is: scan(count) -> list(perm) -> collide. The
-// collide kernel reads each cell's particles through perm, reduces them per
-// cell, rotates, writes them back in cell order into the other buffer, and
-// (when another step follows) streams and bins them for that step, so the
-// particle data is read once and written once per step.
+// One step is one launch of k_tile: block T gathers its tile (binned for this
+// step: every particle's collision cell lies in T), sums each cell exactly in
+// LDS, draws the cell's axis and thermostat factor, rotates, then streams the
+// particles, bins them for the next step's shift and scatters them to the
+// next tile's slab in the other buffer. Destination slots are reserved with
+// one global atomic per (block, destination tile) pair -- at most 27 per
+// block -- so the particle data is read once and written once per step and
+// no per-particle global atomics are needed.
 #pragma once
 
 #include "mpcd_device.hpp"
 
 namespace mpcd {
 
-enum : uint32_t { ERR_STREAM_RANGE = 1u, ERR_FIXED_RANGE = 2u, ERR_GAMMA_CAP = 4u, ERR_LIST = 8u };
+enum : uint32_t {
+  ERR_STREAM_RANGE = 1u,  // |v dt| >= L in the FP64 form
+  ERR_FIXED_RANGE = 2u,   // a term outside the fixed-point range
+  ERR_GAMMA_CAP = 4u,     // Gamma sampler reached its attempt cap
+  ERR_TILE = 8u,          // a particle was found outside its tile (a bug)
+};
 
+// status[0]: error flags above; status[1]: nonzero once a slab overflowed;
+// status[2]: smallest launch sequence number that overflowed (tile kernels
+// with a larger sequence number return at once).
 struct Box {
   int n[3];
   double L[3];
@@ -32,6 +45,11 @@ struct Box {
   double kT, mass;
   uint32_t k0, k1;     // Philox key = user seed
   uint32_t n_solvent;
+  int td[3];           // tile size in cells
+  int tsh[3];          // log2(td) (td is a power of two whenever nt > 1)
+  int nt[3];           // tiles per axis
+  uint32_t ntiles;
+  uint32_t cap;        // slots per tile
 };
 
 struct Particles {
@@ -44,16 +62,28 @@ struct Particles {
 };
 
 // Blocks are handed to the 8 XCDs round-robin; remapping makes XCD k work on
-// one contiguous range of cells so neighbouring cells share its L2.
+// one contiguous range of tiles, so neighbouring tiles share its L2.
 __device__ inline uint32_t xcd_remap(uint32_t b, uint32_t nb) {
   const uint32_t q = nb >> 3, r = nb & 7u;
   const uint32_t x = b & 7u, i = b >> 3;
   return x < r ? x * (q + 1u) + i : r * (q + 1u) + (x - r) * q + i;
 }
 
-// ------------------------------------------------------------------ helpers
+__device__ inline int tile_coord(int c, const Box& B, int d) {
+  return B.nt[d] == 1 ? 0 : (c >> B.tsh[d]);
+}
+
 template <int FORM>
-__device__ inline void load_vel(const Particles& P, uint32_t i, double v[3]) {
+struct VelT {
+  using T = double;
+};
+template <>
+struct VelT<1> {
+  using T = float;
+};
+
+template <int FORM>
+__device__ inline void load_vel(const Particles& P, size_t i, double v[3]) {
   if constexpr (FORM == 0) {
     v[0] = P.v[0][i];
     v[1] = P.v[1][i];
@@ -65,19 +95,31 @@ __device__ inline void load_vel(const Particles& P, uint32_t i, double v[3]) {
   }
 }
 
-// Stream one particle (eq. 1) in place in registers.
-// FP64: x <- wrap(x + v dt); FP32: offsets and home cells.
+template <int FORM>
+__device__ inline void store_vel(const Particles& P, size_t j, const double w[3]) {
+  if constexpr (FORM == 0) {
+    P.v[0][j] = w[0];
+    P.v[1][j] = w[1];
+    P.v[2][j] = w[2];
+  } else {
+    P.vf[0][j] = (float)w[0];
+    P.vf[1][j] = (float)w[1];
+    P.vf[2][j] = (float)w[2];
+  }
+}
+
+// Position of one particle in registers: stream (eq. 1) and bin (sec. 3.4).
 template <int FORM>
 struct Pos;
 template <>
 struct Pos<0> {
   double x[3];
-  __device__ void load(const Particles& P, uint32_t i) {
+  __device__ void load(const Particles& P, size_t i) {
     x[0] = P.x[0][i];
     x[1] = P.x[1][i];
     x[2] = P.x[2][i];
   }
-  __device__ void store(const Particles& P, uint32_t j) const {
+  __device__ void store(const Particles& P, size_t j) const {
     P.x[0][j] = x[0];
     P.x[1][j] = x[1];
     P.x[2][j] = x[2];
@@ -90,24 +132,26 @@ struct Pos<0> {
       x[d] = wrap_box(x[d] + st, B.L[d]);
     }
   }
-  __device__ uint32_t cell(const Box& B, const double s[3], const float*) const {
-    const int ix = bin_axis64(x[0], s[0], B.L[0], B.inv_a, B.n[0]);
-    const int iy = bin_axis64(x[1], s[1], B.L[1], B.inv_a, B.n[1]);
-    const int iz = bin_axis64(x[2], s[2], B.L[2], B.inv_a, B.n[2]);
-    return (uint32_t)ix + (uint32_t)B.n[0] * ((uint32_t)iy + (uint32_t)B.n[1] * (uint32_t)iz);
+  __device__ void cell3(const Box& B, const double s[3], const float*, int c[3]) const {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) c[d] = bin_axis64(x[d], s[d], B.L[d], B.inv_a, B.n[d]);
+  }
+  __device__ void home3(const Box& B, int c[3]) const {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) c[d] = bin_axis64(x[d], 0.0, B.L[d], B.inv_a, B.n[d]);
   }
 };
 template <>
 struct Pos<1> {
   int h[3];
   float o[3];
-  __device__ void load(const Particles& P, uint32_t i) {
+  __device__ void load(const Particles& P, size_t i) {
     unpack_home(P.h[i], h[0], h[1], h[2]);
     o[0] = P.o[0][i];
     o[1] = P.o[1][i];
     o[2] = P.o[2][i];
   }
-  __device__ void store(const Particles& P, uint32_t j) const {
+  __device__ void store(const Particles& P, size_t j) const {
     P.h[j] = pack_home(h[0], h[1], h[2]);
     P.o[0][j] = o[0];
     P.o[1][j] = o[1];
@@ -119,484 +163,569 @@ struct Pos<1> {
     for (int d = 0; d < 3; ++d)
       stream_axis32(o[d], h[d], (float)v[d], B.dt32, B.a32, B.inv_a32, B.n[d]);
   }
-  __device__ uint32_t cell(const Box& B, const double*, const float s32[3]) const {
-    const int ix = bin_axis32(o[0], h[0], s32[0], B.inv_a32, B.n[0]);
-    const int iy = bin_axis32(o[1], h[1], s32[1], B.inv_a32, B.n[1]);
-    const int iz = bin_axis32(o[2], h[2], s32[2], B.inv_a32, B.n[2]);
-    return (uint32_t)ix + (uint32_t)B.n[0] * ((uint32_t)iy + (uint32_t)B.n[1] * (uint32_t)iz);
+  __device__ void cell3(const Box& B, const double*, const float s32[3], int c[3]) const {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) c[d] = bin_axis32(o[d], h[d], s32[d], B.inv_a32, B.n[d]);
+  }
+  __device__ void home3(const Box&, int c[3]) const {
+    c[0] = h[0];
+    c[1] = h[1];
+    c[2] = h[2];
   }
 };
 
-// ------------------------------------------------------- stream and bin
-template <int FORM>
-__global__ __launch_bounds__(256) void k_stream(Particles P, Box B, uint32_t N,
-                                                uint32_t* err) {
-  const uint32_t j = blockIdx.x * 256u + threadIdx.x;
-  if (j >= N) return;
-  double v[3];
-  load_vel<FORM>(P, j, v);
-  Pos<FORM> r;
-  r.load(P, j);
-  uint32_t e = 0;
-  r.stream(B, v, e);
-  r.store(P, j);
-  if (e) atomicOr(err, e);
+__device__ inline uint32_t cell_index(const Box& B, const int c[3]) {
+  return (uint32_t)c[0] + (uint32_t)B.n[0] * ((uint32_t)c[1] + (uint32_t)B.n[1] * (uint32_t)c[2]);
 }
 
-// Bin (optionally after streaming in place): collision cell on the shifted
-// grid, and a rank inside the cell from one atomic per particle (count sort).
-template <int FORM, bool STREAM>
-__global__ __launch_bounds__(256) void k_bin(Particles P, Box B, uint32_t N,
-                                             double s0, double s1, double s2,
-                                             float t0, float t1, float t2,
-                                             uint32_t* __restrict__ count,
-                                             uint2* __restrict__ cr,
-                                             uint32_t* err) {
-  const uint32_t j = blockIdx.x * 256u + threadIdx.x;
-  if (j >= N) return;
-  Pos<FORM> r;
-  r.load(P, j);
-  if constexpr (STREAM) {
-    double v[3];
-    load_vel<FORM>(P, j, v);
-    uint32_t e = 0;
-    r.stream(B, v, e);
-    r.store(P, j);
-    if (e) atomicOr(err, e);
-  }
-  const double s[3] = {s0, s1, s2};
-  const float s32[3] = {t0, t1, t2};
-  const uint32_t c = r.cell(B, s, s32);
-  const uint32_t rank = atomicAdd(&count[c], 1u);
-  cr[j] = make_uint2(c, rank);
+__device__ inline uint32_t tile_index(const Box& B, const int c[3]) {
+  const int tx = tile_coord(c[0], B, 0), ty = tile_coord(c[1], B, 1), tz = tile_coord(c[2], B, 2);
+  return (uint32_t)tx + (uint32_t)B.nt[0] * ((uint32_t)ty + (uint32_t)B.nt[1] * (uint32_t)tz);
 }
 
-// ---------------------------------------------------------- count scan
-constexpr int SCAN_T = 256;
-constexpr int SCAN_PER = 16;
-constexpr int SCAN_CHUNK = SCAN_T * SCAN_PER;
-
-template <int NT>
-__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t& total) {
-  __shared__ uint32_t wsum[NT / 64];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  uint32_t incl = v;
+// ------------------------------------------------------- scatter helpers
+// Destination bin of a particle leaving tile t for the tile of cell c:
+// 0..26 for the 27 neighbours (periodic wrap), 27 for any other tile.
+__device__ inline uint32_t dest_bin(const Box& B, const int t[3], const int c[3]) {
+  uint32_t bin = 0, mul = 1;
 #pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t y = __shfl_up(incl, d, 64);
-    if (lane >= d) incl += y;
+  for (int d = 0; d < 3; ++d) {
+    const int nt = B.nt[d];
+    const int ct = tile_coord(c[d], B, d);
+    int o;
+    if (ct == t[d]) o = 1;
+    else if (ct == (t[d] + 1 == nt ? 0 : t[d] + 1)) o = 2;
+    else if (ct == (t[d] == 0 ? nt - 1 : t[d] - 1)) o = 0;
+    else return 27u;
+    bin += (uint32_t)o * mul;
+    mul *= 3u;
   }
-  if (lane == 63) wsum[wid] = incl;
-  __syncthreads();
-  uint32_t wpre = 0, tot = 0;
-#pragma unroll
-  for (int w = 0; w < NT / 64; ++w) {
-    const uint32_t s = wsum[w];
-    wpre += (w < wid) ? s : 0u;
-    tot += s;
-  }
-  __syncthreads();
-  total = tot;
-  return wpre + incl - v;
+  return bin;
 }
 
-__global__ __launch_bounds__(SCAN_T) void k_scan_partial(const uint32_t* __restrict__ count,
-                                                         uint32_t ncells,
-                                                         uint32_t* __restrict__ partial) {
-  const uint32_t base = blockIdx.x * (uint32_t)SCAN_CHUNK;
-  uint32_t s = 0;
+__device__ inline uint32_t bin_tile(const Box& B, const int t[3], uint32_t bin) {
+  int c[3];
 #pragma unroll
-  for (int k = 0; k < SCAN_PER; ++k) {
-    const uint32_t c = base + (uint32_t)k * SCAN_T + threadIdx.x;
-    if (c < ncells) s += count[c];
+  for (int d = 0; d < 3; ++d) {
+    const int o = (int)(bin % 3u) - 1;
+    bin /= 3u;
+    int x = t[d] + o;
+    if (x < 0) x += B.nt[d];
+    if (x >= B.nt[d]) x -= B.nt[d];
+    c[d] = x;
   }
-  uint32_t tot;
-  (void)block_exclusive_scan<SCAN_T>(s, tot);
-  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+  return (uint32_t)c[0] + (uint32_t)B.nt[0] * ((uint32_t)c[1] + (uint32_t)B.nt[1] * (uint32_t)c[2]);
 }
 
-__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* partial, uint32_t nb) {
-  uint32_t carry = 0;
-  for (uint32_t base = 0; base < nb; base += 1024u) {
-    const uint32_t i = base + threadIdx.x;
-    const uint32_t v = i < nb ? partial[i] : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_exclusive_scan<1024>(v, tot);
-    if (i < nb) partial[i] = carry + ex;
-    carry += tot;
+// Rank of each active lane among the block's particles with the same bin:
+// lanes of one wave are ranked in lane order (ballot), waves take
+// consecutive ranges through one LDS atomic per (wave, bin).
+__device__ inline uint32_t wave_rank(uint32_t bin, bool active, uint32_t* s_bincnt) {
+  const uint32_t lane = threadIdx.x & 63u;
+  unsigned long long pending = __ballot(active);
+  uint32_t myrank = 0;
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const uint32_t b = __shfl(bin, leader);
+    const unsigned long long m = __ballot(active && bin == b);
+    uint32_t base = 0;
+    if ((int)lane == leader) base = atomicAdd(&s_bincnt[b], (uint32_t)__popcll(m));
+    base = __shfl(base, leader);
+    if (active && bin == b) myrank = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    pending &= ~m;
   }
+  return myrank;
 }
 
-// off[c] = exclusive prefix of count; count is cleared for the next binning.
-__global__ __launch_bounds__(SCAN_T) void k_scan_final(uint32_t* __restrict__ count,
-                                                       uint32_t ncells,
-                                                       const uint32_t* __restrict__ partial,
-                                                       uint32_t* __restrict__ off,
-                                                       uint32_t N) {
-  const uint32_t base = blockIdx.x * (uint32_t)SCAN_CHUNK + threadIdx.x * (uint32_t)SCAN_PER;
-  uint32_t v[SCAN_PER];
-  if (base + SCAN_PER <= ncells) {
-    const uint4* p = reinterpret_cast<const uint4*>(count + base);
-#pragma unroll
-    for (int q = 0; q < SCAN_PER / 4; ++q) {
-      const uint4 t = p[q];
-      v[4 * q] = t.x;
-      v[4 * q + 1] = t.y;
-      v[4 * q + 2] = t.z;
-      v[4 * q + 3] = t.w;
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < SCAN_PER; ++k) v[k] = (base + k < ncells) ? count[base + k] : 0u;
-  }
-  uint32_t s = 0;
-#pragma unroll
-  for (int k = 0; k < SCAN_PER; ++k) s += v[k];
-  uint32_t tot;
-  uint32_t run = partial[blockIdx.x] + block_exclusive_scan<SCAN_T>(s, tot);
-  if (base + SCAN_PER <= ncells) {
-    uint4* o = reinterpret_cast<uint4*>(off + base);
-    uint4* z = reinterpret_cast<uint4*>(count + base);
-#pragma unroll
-    for (int q = 0; q < SCAN_PER / 4; ++q) {
-      uint4 t;
-      t.x = run;
-      run += v[4 * q];
-      t.y = run;
-      run += v[4 * q + 1];
-      t.z = run;
-      run += v[4 * q + 2];
-      t.w = run;
-      run += v[4 * q + 3];
-      o[q] = t;
-      z[q] = make_uint4(0u, 0u, 0u, 0u);
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < SCAN_PER; ++k) {
-      if (base + k < ncells) {
-        off[base + k] = run;
-        count[base + k] = 0u;
-        run += v[k];
-      }
-    }
-  }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) off[ncells] = N;
-}
+// ------------------------------------------------------------ tile kernel
+enum { MODE_BIN = 0, MODE_COLLIDE = 1, MODE_COLLIDE_SCATTER = 2, MODE_DIAG = 3 };
 
-// Cell-ordered particle list: perm[off[c] + rank] = current index.
-__global__ __launch_bounds__(256) void k_perm(const uint2* __restrict__ cr,
-                                              const uint32_t* __restrict__ off,
-                                              uint32_t* __restrict__ perm, uint32_t N,
-                                              uint32_t* err) {
-  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
-  if (i >= N) return;
-  const uint2 q = cr[i];
-  const uint32_t j = off[q.x] + q.y;
-  if (j < N) perm[j] = i;
-  else atomicOr(err, ERR_LIST);
-}
+constexpr int TT = 256;         // threads per tile block
+constexpr int TQ = 4;           // particles per thread held in registers
+constexpr int TREG = TT * TQ;   // beyond this a tile's particles are re-read
 
-// ------------------------------------------------------------ per cell
-// Cell sums (sec. 3.5, eq. 3): mass, momentum and, when asked, the kinetic
-// energy relative to u, accumulated in exact fixed point. `get(k, v, m)`
-// returns the velocity and mass of the cell's k-th particle.
-struct CellSums {
-  double M, u[3], ek;
-};
-
-template <bool EMB, bool EK, class Get>
-__device__ inline CellSums cell_sums(uint32_t cnt, double solvent_mass, Get get,
-                                     bool& bad) {
-  CellSums r;
-  Fx P[3] = {{0, 0}, {0, 0}, {0, 0}};
-  Fx Mx = {0, 0};
-  for (uint32_t k = 0; k < cnt; ++k) {
-    double v[3], m;
-    get(k, v, m);
-    if constexpr (EMB) fx_add(Mx, m, bad);
-    fx_add(P[0], m * v[0], bad);
-    fx_add(P[1], m * v[1], bad);
-    fx_add(P[2], m * v[2], bad);
-  }
-  r.M = EMB ? fx_value(Mx) : (double)cnt * solvent_mass;
-  if (cnt > 0) {
-    r.u[0] = fx_value(P[0]) / r.M;
-    r.u[1] = fx_value(P[1]) / r.M;
-    r.u[2] = fx_value(P[2]) / r.M;
-  } else {
-    r.u[0] = r.u[1] = r.u[2] = 0.0;
-  }
-  r.ek = 0.0;
-  if constexpr (EK) {
-    Fx E = {0, 0};
-    for (uint32_t k = 0; k < cnt; ++k) {
-      double v[3], m;
-      get(k, v, m);
-      const double dx = v[0] - r.u[0], dy = v[1] - r.u[1], dz = v[2] - r.u[2];
-      fx_add(E, m * (dx * dx + dy * dy + dz * dz), bad);
-    }
-    r.ek = 0.5 * fx_value(E);
-  }
-  return r;
-}
-
-// --------------------------------------------------------------- collide
-constexpr int COLLIDE_T = 256;
-constexpr int PCAP = 1664;
-
-struct CollideArgs {
-  Particles cur, nxt;
+struct TileArgs {
+  Particles in, out;
   Box B;
-  const uint32_t* off;
-  const uint32_t* perm;
+  const uint32_t* cnt_in;   // occupancy of the input slabs
+  uint32_t* cnt_out;        // occupancy of the output slabs (scatter modes)
+  uint32_t* cnt_clear;      // cleared for this tile (scatter modes)
   const double* emb_mass;
-  uint32_t step;      // counter of this collision
-  uint32_t step_next; // counter of the following step (STREAM_NEXT)
-  double sn[3];       // shift of the following step
+  uint32_t step;            // counter of the collision
+  double s[3];              // shift binning the input (collide) or output (bin)
+  float s32[3];
+  double sn[3];             // shift of the next step (collide + scatter)
   float sn32[3];
-  uint32_t* count;    // occupancy of the following step (STREAM_NEXT)
-  uint2* cr_next;
-  uint32_t* err;
+  uint32_t* status;
+  uint32_t seq;             // launch sequence number within one API call
+  double* d_mass;           // per-cell outputs of MODE_DIAG (global cell index)
+  double* d_mom;
+  double* d_ek;
+  double* d_axis;
+  double* d_xi;
 };
 
-template <int FORM>
-struct VelLds {
-  using T = double;
-};
-template <>
-struct VelLds<1> {
-  using T = float;
-};
-
-template <int FORM, int CPB, bool STREAM_NEXT, bool THERMO, bool EMB>
-__global__ __launch_bounds__(COLLIDE_T) void k_collide(CollideArgs A) {
-  using VT = typename VelLds<FORM>::T;
-  __shared__ VT s_v[3][PCAP];
-  __shared__ uint32_t s_src[PCAP];
-  __shared__ uint8_t s_lc[PCAP];
-  __shared__ uint32_t s_tag[EMB ? PCAP : 1];
-  __shared__ double s_u[3][CPB];
-  __shared__ double s_R[9][CPB];
-  __shared__ uint32_t s_off[CPB + 1];
+template <int FORM, int CPT, int MODE, bool STREAM_IN, bool THERMO, bool EMB>
+__global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
+  using VT = typename VelT<FORM>::T;
+  constexpr bool COLL = MODE != MODE_BIN;
+  constexpr bool SCAT = MODE == MODE_BIN || MODE == MODE_COLLIDE_SCATTER;
+  constexpr bool EK = THERMO || MODE == MODE_DIAG;
+  constexpr int TPC = TT / CPT;  // threads per cell in the per-cell phase
+  // accumulator rows: 0 count, 1..6 momentum limbs, then energy, then mass
+  constexpr int IE = 7;
+  constexpr int IM = EK ? 9 : 7;
+  constexpr int NACC = COLL ? (IM + (EMB ? 2 : 0)) : 1;
+  constexpr int CC = COLL ? CPT : 1;
+  __shared__ unsigned long long s_acc[NACC][CC];
+  __shared__ double s_u[3][CC];
+  __shared__ double s_R[9][CC];
+  __shared__ double s_g[THERMO ? TPC : 1][THERMO ? CPT : 1];
+  __shared__ uint32_t s_bincnt[28];
+  __shared__ uint32_t s_base[28];
+  __shared__ uint32_t s_quit;
 
   const Box& B = A.B;
-  const uint32_t blk = xcd_remap(blockIdx.x, gridDim.x);
-  const uint32_t c0 = blk * (uint32_t)CPB;
-  const uint32_t nc = min((uint32_t)CPB, B.ncells - c0);
   const uint32_t tid = threadIdx.x;
-  for (uint32_t t = tid; t <= nc; t += COLLIDE_T) s_off[t] = A.off[c0 + t];
+  // quit if an earlier launch of this call overflowed a slab (launches of
+  // the failing one itself run to the end, so its counts are complete)
+  if (tid == 0) s_quit = (A.status[1] != 0u && A.status[2] < A.seq) ? 1u : 0u;
+  if (tid < 28u) s_bincnt[tid] = 0u;
+  if constexpr (COLL)
+    for (uint32_t t = tid; t < (uint32_t)(NACC * CC); t += TT) (&s_acc[0][0])[t] = 0ull;
   __syncthreads();
-  const uint32_t s0 = s_off[0];
-  const uint32_t np = s_off[nc] - s0;
-  const uint32_t nlds = np < (uint32_t)PCAP ? np : (uint32_t)PCAP;
+  if (s_quit) return;
 
-  // phase 1: stage the block's velocities (gathered through the list)
-  for (uint32_t k = tid; k < nlds; k += COLLIDE_T) {
-    const uint32_t i = A.perm[s0 + k];
-    s_src[k] = i;
-    if constexpr (FORM == 0) {
-      s_v[0][k] = A.cur.v[0][i];
-      s_v[1][k] = A.cur.v[1][i];
-      s_v[2][k] = A.cur.v[2][i];
-    } else {
-      s_v[0][k] = A.cur.vf[0][i];
-      s_v[1][k] = A.cur.vf[1][i];
-      s_v[2][k] = A.cur.vf[2][i];
-    }
-    if constexpr (EMB) s_tag[k] = A.cur.tag[i];
-  }
-  __syncthreads();
-
-  // phase 2: one thread per cell -> u, axis, xi, rotation matrix
-  bool bad = false, cap = false;
-  if (tid < nc) {
-    const uint32_t b = s_off[tid] - s0, e = s_off[tid + 1] - s0;
-    const uint32_t cnt = e - b;
-    auto get = [&](uint32_t k, double v[3], double& m) {
-      const uint32_t q = b + k;
-      uint32_t tg;
-      if (q < (uint32_t)PCAP) {
-        v[0] = (double)s_v[0][q];
-        v[1] = (double)s_v[1][q];
-        v[2] = (double)s_v[2][q];
-        if constexpr (EMB) tg = s_tag[q];
-      } else {
-        const uint32_t i = A.perm[s0 + q];
-        load_vel<FORM>(A.cur, i, v);
-        if constexpr (EMB) tg = A.cur.tag[i];
-      }
-      if constexpr (EMB)
-        m = tg >= B.n_solvent ? A.emb_mass[tg - B.n_solvent] : B.mass;
-      else
-        m = B.mass;
-    };
-    const CellSums cs = cell_sums<EMB, THERMO>(cnt, B.mass, get, bad);
-    for (uint32_t q = b; q < e && q < (uint32_t)PCAP; ++q) s_lc[q] = (uint8_t)tid;
-    double n[3] = {0.0, 0.0, 0.0}, xi = 1.0;
-    if (cnt > 0) {
-      cell_axis(c0 + tid, A.step, B.k0, B.k1, n);
-      if constexpr (THERMO) xi = thermo_xi(cnt, cs.ek, c0 + tid, A.step, B.k0, B.k1, B.kT, cap);
-    }
-    double R[9];
-    rotation_matrix(n, B.ca, B.sa, B.omc, xi, R);
-    s_u[0][tid] = cs.u[0];
-    s_u[1][tid] = cs.u[1];
-    s_u[2][tid] = cs.u[2];
+  const uint32_t T = xcd_remap(blockIdx.x, gridDim.x);
+  int t3[3];
+  t3[0] = (int)(T % (uint32_t)B.nt[0]);
+  t3[1] = (int)((T / (uint32_t)B.nt[0]) % (uint32_t)B.nt[1]);
+  t3[2] = (int)(T / ((uint32_t)B.nt[0] * (uint32_t)B.nt[1]));
+  int org[3], ext[3];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) s_R[q][tid] = R[q];
+  for (int d = 0; d < 3; ++d) {
+    org[d] = t3[d] * B.td[d];
+    ext[d] = min(B.td[d], B.n[d] - org[d]);
   }
-  __syncthreads();
+  const uint32_t cnt = min(A.cnt_in[T], B.cap);
+  const uint32_t nreg = min(cnt, (uint32_t)TREG);
+  const size_t base_in = (size_t)T * B.cap;
+  if (SCAT && tid == 0 && A.cnt_clear) A.cnt_clear[T] = 0u;
 
-  // phase 3: rotate each particle (Alg. 1), write it in cell order; when a
-  // step follows, stream it and count it into its next cell.
-  uint32_t e = 0;
-  for (uint32_t k = tid; k < np; k += COLLIDE_T) {
-    uint32_t lc, i;
-    double v[3];
-    if (k < (uint32_t)PCAP) {
-      lc = s_lc[k];
-      i = s_src[k];
-      v[0] = (double)s_v[0][k];
-      v[1] = (double)s_v[1][k];
-      v[2] = (double)s_v[2][k];
-    } else {
-      i = A.perm[s0 + k];
-      load_vel<FORM>(A.cur, i, v);
-      uint32_t lo = 0, hi = nc;  // last cell whose start <= s0 + k
-      while (hi - lo > 1u) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (s_off[mid] <= s0 + k) lo = mid; else hi = mid;
+  uint32_t err = 0;
+  bool bad = false, cap = false;
+
+  auto mass_of = [&](uint32_t tag) -> double {
+    if constexpr (EMB) return tag >= B.n_solvent ? A.emb_mass[tag - B.n_solvent] : B.mass;
+    else return B.mass;
+  };
+  // local cell (inside this tile) of a particle binned with the input shift
+  auto local_cell = [&](const Pos<FORM>& r) -> uint32_t {
+    int c[3];
+    r.cell3(B, A.s, A.s32, c);
+    int l[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      l[d] = c[d] - org[d];
+      if (l[d] < 0 || l[d] >= ext[d]) {
+        err |= ERR_TILE;
+        l[d] = l[d] < 0 ? 0 : ext[d] - 1;
       }
-      lc = lo;
     }
-    const double ux = s_u[0][lc], uy = s_u[1][lc], uz = s_u[2][lc];
-    const double dx = v[0] - ux, dy = v[1] - uy, dz = v[2] - uz;
-    double w[3];
-    w[0] = ux + (s_R[0][lc] * dx + s_R[1][lc] * dy + s_R[2][lc] * dz);
-    w[1] = uy + (s_R[3][lc] * dx + s_R[4][lc] * dy + s_R[5][lc] * dz);
-    w[2] = uz + (s_R[6][lc] * dx + s_R[7][lc] * dy + s_R[8][lc] * dz);
-    const uint32_t j = s0 + k;
-    if constexpr (FORM == 0) {
-      A.nxt.v[0][j] = w[0];
-      A.nxt.v[1][j] = w[1];
-      A.nxt.v[2][j] = w[2];
-    } else {
-      const float f0 = (float)w[0], f1 = (float)w[1], f2 = (float)w[2];
-      A.nxt.vf[0][j] = f0;
-      A.nxt.vf[1][j] = f1;
-      A.nxt.vf[2][j] = f2;
-      w[0] = f0;
-      w[1] = f1;
-      w[2] = f2;
-    }
-    if constexpr (EMB)
-      A.nxt.tag[j] = k < (uint32_t)PCAP ? s_tag[k] : A.cur.tag[i];
-    else
-      A.nxt.tag[j] = A.cur.tag[i];
-    Pos<FORM> r;
-    r.load(A.cur, i);
-    if constexpr (STREAM_NEXT) {
-      r.stream(B, w, e);
-      const uint32_t c = r.cell(B, A.sn, A.sn32);
-      const uint32_t rank = atomicAdd(&A.count[c], 1u);
-      A.cr_next[j] = make_uint2(c, rank);
-    }
-    r.store(A.nxt, j);
-  }
-  if (bad) e |= ERR_FIXED_RANGE;
-  if (cap) e |= ERR_GAMMA_CAP;
-  if (e) atomicOr(A.err, e);
-}
+    return (uint32_t)l[0] + (uint32_t)B.td[0] * ((uint32_t)l[1] + (uint32_t)B.td[1] * (uint32_t)l[2]);
+  };
+  auto add2 = [&](int j, uint32_t lc, double x) {
+    long long hi, lo;
+    fx_split(x, hi, lo, bad);
+    atomicAdd(&s_acc[j][lc], (unsigned long long)hi);
+    atomicAdd(&s_acc[j + 1][lc], (unsigned long long)lo);
+  };
+  auto acc_val = [&](int j, uint32_t lc) {
+    Fx f;
+    f.hi = (long long)s_acc[j][lc];
+    f.lo = (long long)s_acc[j + 1][lc];
+    return fx_value(f);
+  };
 
-// ------------------------------------------------------- diagnostics
-// Cell properties and draws of the binned state, one thread per cell,
-// particles read through the cell-ordered list.
-template <int FORM, bool THERMO, bool EMB>
-__global__ __launch_bounds__(256) void k_cell_diag(Particles P, Box B,
-                                                   const uint32_t* __restrict__ off,
-                                                   const uint32_t* __restrict__ perm,
-                                                   const double* __restrict__ emb_mass,
-                                                   uint32_t step, double* mass,
-                                                   double* ek,
-                                                   double* axis, double* xi_out,
-                                                   uint32_t* err) {
-  const uint32_t c = blockIdx.x * 256u + threadIdx.x;
-  if (c >= B.ncells) return;
-  const uint32_t b = off[c], cnt = off[c + 1] - b;
-  auto get = [&](uint32_t k, double v[3], double& m) {
-    const uint32_t i = perm[b + k];
-    load_vel<FORM>(P, i, v);
-    if constexpr (EMB) {
-      const uint32_t tg = P.tag[i];
-      m = tg >= B.n_solvent ? emb_mass[tg - B.n_solvent] : B.mass;
-    } else {
-      m = B.mass;
+  // ---- gather this tile's particles (register-resident part)
+  VT v[TQ][3];
+  uint32_t tg[TQ];
+  uint32_t lcs[TQ];
+  Pos<FORM> r[TQ];
+#pragma unroll
+  for (int q = 0; q < TQ; ++q) {
+    const uint32_t k = tid + (uint32_t)(q * TT);
+    lcs[q] = 0u;
+    tg[q] = 0u;
+    if (k < nreg) {
+      const size_t i = base_in + k;
+      if constexpr (FORM == 0) {
+        v[q][0] = A.in.v[0][i];
+        v[q][1] = A.in.v[1][i];
+        v[q][2] = A.in.v[2][i];
+      } else {
+        v[q][0] = A.in.vf[0][i];
+        v[q][1] = A.in.vf[1][i];
+        v[q][2] = A.in.vf[2][i];
+      }
+      tg[q] = A.in.tag[i];
+      r[q].load(A.in, i);
+    }
+  }
+
+  // ---- scatter: bin for the destination shift, reserve slots, write
+  auto scatter = [&](const double* sd, const float* sd32, const double (*w)[3]) {
+    // w[q]: velocity to store (already rounded to the storage precision)
+    uint32_t bins[TQ], ranks[TQ], dest[TQ];
+#pragma unroll
+    for (int q = 0; q < TQ; ++q) {
+      const uint32_t k = tid + (uint32_t)(q * TT);
+      const bool act = k < nreg;
+      uint32_t b = 0;
+      dest[q] = 0u;
+      if (act) {
+        int c[3];
+        r[q].cell3(B, sd, sd32, c);
+        b = dest_bin(B, t3, c);
+        dest[q] = b < 27u ? bin_tile(B, t3, b) : tile_index(B, c);
+      }
+      bins[q] = b;
+      ranks[q] = wave_rank(b, act && b < 27u, s_bincnt);
+    }
+    __syncthreads();
+    if (tid < 27u && s_bincnt[tid] > 0u)
+      s_base[tid] = atomicAdd(&A.cnt_out[bin_tile(B, t3, tid)], s_bincnt[tid]);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < TQ; ++q) {
+      const uint32_t k = tid + (uint32_t)(q * TT);
+      if (k < nreg) {
+        const uint32_t slot = bins[q] < 27u ? s_base[bins[q]] + ranks[q]
+                                            : atomicAdd(&A.cnt_out[dest[q]], 1u);
+        if (slot < B.cap) {
+          const size_t j = (size_t)dest[q] * B.cap + slot;
+          store_vel<FORM>(A.out, j, w[q]);
+          A.out.tag[j] = tg[q];
+          r[q].store(A.out, j);
+        } else {
+          atomicMax(&A.status[1], 1u);
+          atomicMin(&A.status[2], A.seq);
+        }
+      }
     }
   };
-  bool bad = false, cap = false;
-  const CellSums cs = cell_sums<EMB, true>(cnt, B.mass, get, bad);
-  mass[c] = cs.M;
-  ek[c] = cs.ek;
-  double n[3] = {0.0, 0.0, 0.0}, xi = 1.0;
-  if (cnt > 0) {
-    cell_axis(c, step, B.k0, B.k1, n);
-    if constexpr (THERMO) xi = thermo_xi(cnt, cs.ek, c, step, B.k0, B.k1, B.kT, cap);
+  // particles beyond the register-resident part: one global atomic each
+  auto scatter_one = [&](Pos<FORM>& rr, const double* sd, const float* sd32, const double w[3],
+                         uint32_t tag) {
+    int c[3];
+    rr.cell3(B, sd, sd32, c);
+    const uint32_t dt = tile_index(B, c);
+    const uint32_t slot = atomicAdd(&A.cnt_out[dt], 1u);
+    if (slot < B.cap) {
+      const size_t j = (size_t)dt * B.cap + slot;
+      store_vel<FORM>(A.out, j, w);
+      A.out.tag[j] = tag;
+      rr.store(A.out, j);
+    } else {
+      atomicMax(&A.status[1], 1u);
+      atomicMin(&A.status[2], A.seq);
+    }
+  };
+
+  if constexpr (MODE == MODE_BIN) {
+    double w[TQ][3];
+#pragma unroll
+    for (int q = 0; q < TQ; ++q) {
+      w[q][0] = (double)v[q][0];
+      w[q][1] = (double)v[q][1];
+      w[q][2] = (double)v[q][2];
+      if (STREAM_IN && tid + (uint32_t)(q * TT) < nreg) r[q].stream(B, w[q], err);
+    }
+    scatter(A.s, A.s32, w);
+    for (uint32_t k = TREG + tid; k < cnt; k += TT) {
+      const size_t i = base_in + k;
+      double vv[3];
+      load_vel<FORM>(A.in, i, vv);
+      Pos<FORM> rr;
+      rr.load(A.in, i);
+      if (STREAM_IN) rr.stream(B, vv, err);
+      scatter_one(rr, A.s, A.s32, vv, A.in.tag[i]);
+    }
+  } else {
+    // ---- cell sums: count, momentum (and mass) in exact fixed point
+    auto sum_mom = [&](uint32_t lc, const double vv[3], double m) {
+      atomicAdd(&s_acc[0][lc], 1ull);
+      add2(1, lc, m * vv[0]);
+      add2(3, lc, m * vv[1]);
+      add2(5, lc, m * vv[2]);
+      if constexpr (EMB) add2(IM, lc, m);
+    };
+#pragma unroll
+    for (int q = 0; q < TQ; ++q) {
+      const uint32_t k = tid + (uint32_t)(q * TT);
+      if (k < nreg) {
+        lcs[q] = local_cell(r[q]);
+        const double vv[3] = {(double)v[q][0], (double)v[q][1], (double)v[q][2]};
+        sum_mom(lcs[q], vv, mass_of(tg[q]));
+      }
+    }
+    for (uint32_t k = TREG + tid; k < cnt; k += TT) {
+      const size_t i = base_in + k;
+      double vv[3];
+      load_vel<FORM>(A.in, i, vv);
+      Pos<FORM> rr;
+      rr.load(A.in, i);
+      sum_mom(local_cell(rr), vv, mass_of(A.in.tag[i]));
+    }
+    __syncthreads();
+
+    // ---- per cell: TPC threads per cell. u and axis on sub-thread 0;
+    // Gamma attempts in parallel (attempt j on sub-thread j; the first
+    // accepted one in attempt order is the draw)
+    const uint32_t l = tid / (uint32_t)TPC, sub = tid % (uint32_t)TPC;
+    int lc3[3];
+    lc3[0] = (int)(l % (uint32_t)B.td[0]);
+    lc3[1] = (int)((l / (uint32_t)B.td[0]) % (uint32_t)B.td[1]);
+    lc3[2] = (int)(l / ((uint32_t)B.td[0] * (uint32_t)B.td[1]));
+    const bool cell_ok = l < (uint32_t)CPT && lc3[0] < ext[0] && lc3[1] < ext[1] && lc3[2] < ext[2];
+    const int gc3[3] = {org[0] + lc3[0], org[1] + lc3[1], org[2] + lc3[2]};
+    const uint32_t gcell = cell_ok ? cell_index(B, gc3) : 0u;
+    const uint32_t nc = cell_ok ? (uint32_t)s_acc[0][l] : 0u;
+    double n[3] = {0.0, 0.0, 0.0};
+    if (sub == 0u) {
+      double u[3] = {0.0, 0.0, 0.0};
+      if (nc > 0u) {
+        const double M = EMB ? acc_val(IM, l) : (double)nc * B.mass;
+        u[0] = acc_val(1, l) / M;
+        u[1] = acc_val(3, l) / M;
+        u[2] = acc_val(5, l) / M;
+        cell_axis(gcell, A.step, B.k0, B.k1, n);
+      }
+      if (l < (uint32_t)CPT) {
+        s_u[0][l] = u[0];
+        s_u[1][l] = u[1];
+        s_u[2][l] = u[2];
+      }
+    }
+    if constexpr (THERMO) {
+      if (l < (uint32_t)CPT) {
+        double g = -1.0;  // -1: rejected or not drawn
+        if (nc >= 2u) {
+          const double k = 1.5 * (double)(nc - 1u);
+          const double d = k - 1.0 / 3.0;
+          const double c = 1.0 / sqrt(9.0 * d);
+          const U4 w = philox4x32_10(U4{gcell, A.step, TAG_THERMO, sub}, B.k0, B.k1);
+          const double u0 = u01(w.x), u1 = u01(w.y), u2 = u01(w.z);
+          const double gn = sqrt(-2.0 * log(u0)) * cos((2.0 * M_PI) * u1);
+          const double t = 1.0 + c * gn;
+          if (t > 0.0) {
+            const double V = t * t * t;
+            if (log(u2) < 0.5 * gn * gn + d - d * V + d * log(V)) g = d * V * B.kT;
+          }
+        }
+        s_g[sub][l] = g;
+      }
+    }
+    __syncthreads();
+
+    if constexpr (EK) {
+      auto sum_energy = [&](uint32_t lc, const double vv[3], double m) {
+        const double dx = vv[0] - s_u[0][lc], dy = vv[1] - s_u[1][lc], dz = vv[2] - s_u[2][lc];
+        add2(IE, lc, m * (dx * dx + dy * dy + dz * dz));
+      };
+#pragma unroll
+      for (int q = 0; q < TQ; ++q) {
+        const uint32_t k = tid + (uint32_t)(q * TT);
+        if (k < nreg) {
+          const double vv[3] = {(double)v[q][0], (double)v[q][1], (double)v[q][2]};
+          sum_energy(lcs[q], vv, mass_of(tg[q]));
+        }
+      }
+      for (uint32_t k = TREG + tid; k < cnt; k += TT) {
+        const size_t i = base_in + k;
+        double vv[3];
+        load_vel<FORM>(A.in, i, vv);
+        Pos<FORM> rr;
+        rr.load(A.in, i);
+        sum_energy(local_cell(rr), vv, mass_of(A.in.tag[i]));
+      }
+      __syncthreads();
+    }
+
+    // ---- per cell: xi and the scaled rotation matrix (sub-thread 0)
+    if (sub == 0u && l < (uint32_t)CPT) {
+      double xi = 1.0;
+      double ek = 0.0;
+      if constexpr (EK) ek = 0.5 * acc_val(IE, l);
+      if constexpr (THERMO) {
+        if (nc >= 2u && ek > 0.0) {
+          double ehat = -1.0;
+          for (uint32_t j = 0; j < (uint32_t)TPC && ehat < 0.0; ++j) ehat = s_g[j][l];
+          if (ehat < 0.0) {
+            // every speculative attempt was rejected: continue in order
+            const double k = 1.5 * (double)(nc - 1u);
+            const double d = k - 1.0 / 3.0;
+            const double c = 1.0 / sqrt(9.0 * d);
+            for (uint32_t j = TPC; j < (uint32_t)GAMMA_MAX_ATTEMPTS && ehat < 0.0; ++j) {
+              const U4 w = philox4x32_10(U4{gcell, A.step, TAG_THERMO, j}, B.k0, B.k1);
+              const double u0 = u01(w.x), u1 = u01(w.y), u2 = u01(w.z);
+              const double gn = sqrt(-2.0 * log(u0)) * cos((2.0 * M_PI) * u1);
+              const double t = 1.0 + c * gn;
+              if (t <= 0.0) continue;
+              const double V = t * t * t;
+              if (log(u2) < 0.5 * gn * gn + d - d * V + d * log(V)) ehat = d * V * B.kT;
+            }
+            if (ehat < 0.0) {
+              cap = true;
+              ehat = k * B.kT;
+            }
+          }
+          xi = sqrt(ehat / ek);
+        }
+      }
+      if constexpr (MODE == MODE_DIAG) {
+        if (cell_ok) {
+          A.d_mass[gcell] = nc > 0u ? (EMB ? acc_val(IM, l) : (double)nc * B.mass) : 0.0;
+          A.d_mom[3u * gcell] = acc_val(1, l);
+          A.d_mom[3u * gcell + 1u] = acc_val(3, l);
+          A.d_mom[3u * gcell + 2u] = acc_val(5, l);
+          A.d_ek[gcell] = ek;
+          A.d_axis[3u * gcell] = n[0];
+          A.d_axis[3u * gcell + 1u] = n[1];
+          A.d_axis[3u * gcell + 2u] = n[2];
+          A.d_xi[gcell] = xi;
+        }
+      } else {
+        double R[9];
+        rotation_matrix(n, B.ca, B.sa, B.omc, xi, R);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) s_R[q][l] = R[q];
+      }
+    }
+
+    if constexpr (MODE != MODE_DIAG) {
+      __syncthreads();
+      // ---- rotate (Alg. 1): v <- u + xi R (v - u), FP64 registers
+      auto rotate = [&](uint32_t lc, const double vv[3], double w[3]) {
+        const double ux = s_u[0][lc], uy = s_u[1][lc], uz = s_u[2][lc];
+        const double dx = vv[0] - ux, dy = vv[1] - uy, dz = vv[2] - uz;
+        w[0] = ux + (s_R[0][lc] * dx + s_R[1][lc] * dy + s_R[2][lc] * dz);
+        w[1] = uy + (s_R[3][lc] * dx + s_R[4][lc] * dy + s_R[5][lc] * dz);
+        w[2] = uz + (s_R[6][lc] * dx + s_R[7][lc] * dy + s_R[8][lc] * dz);
+        if constexpr (FORM == 1) {
+          w[0] = (double)(float)w[0];
+          w[1] = (double)(float)w[1];
+          w[2] = (double)(float)w[2];
+        }
+      };
+      double w[TQ][3];
+#pragma unroll
+      for (int q = 0; q < TQ; ++q) {
+        const uint32_t k = tid + (uint32_t)(q * TT);
+        if (k < nreg) {
+          const double vv[3] = {(double)v[q][0], (double)v[q][1], (double)v[q][2]};
+          rotate(lcs[q], vv, w[q]);
+          if constexpr (MODE == MODE_COLLIDE) {
+            const size_t j = base_in + k;
+            store_vel<FORM>(A.out, j, w[q]);
+            A.out.tag[j] = tg[q];
+            r[q].store(A.out, j);
+          } else {
+            r[q].stream(B, w[q], err);
+          }
+        }
+      }
+      if constexpr (MODE == MODE_COLLIDE_SCATTER) scatter(A.sn, A.sn32, w);
+      for (uint32_t k = TREG + tid; k < cnt; k += TT) {
+        const size_t i = base_in + k;
+        double vv[3], ww[3];
+        load_vel<FORM>(A.in, i, vv);
+        Pos<FORM> rr;
+        rr.load(A.in, i);
+        rotate(local_cell(rr), vv, ww);
+        if constexpr (MODE == MODE_COLLIDE) {
+          store_vel<FORM>(A.out, i, ww);
+          A.out.tag[i] = A.in.tag[i];
+          rr.store(A.out, i);
+        } else {
+          rr.stream(B, ww, err);
+          scatter_one(rr, A.sn, A.sn32, ww, A.in.tag[i]);
+        }
+      }
+    }
   }
-  axis[3 * c] = n[0];
-  axis[3 * c + 1] = n[1];
-  axis[3 * c + 2] = n[2];
-  xi_out[c] = xi;
-  uint32_t e = (bad ? ERR_FIXED_RANGE : 0u) | (cap ? ERR_GAMMA_CAP : 0u);
-  if (e) atomicOr(err, e);
+  if (bad) err |= ERR_FIXED_RANGE;
+  if (cap) err |= ERR_GAMMA_CAP;
+  if (err) atomicOr(&A.status[0], err);
 }
 
-// Cell momentum for the diagnostics: the fixed-point sum itself.
-template <int FORM, bool EMB>
-__global__ __launch_bounds__(256) void k_cell_momentum(Particles P, Box B,
-                                                       const uint32_t* __restrict__ off,
-                                                       const uint32_t* __restrict__ perm,
-                                                       const double* __restrict__ emb_mass,
-                                                       double* mom, uint32_t* err) {
-  const uint32_t c = blockIdx.x * 256u + threadIdx.x;
-  if (c >= B.ncells) return;
-  const uint32_t b = off[c], cnt = off[c + 1] - b;
-  Fx S[3] = {{0, 0}, {0, 0}, {0, 0}};
-  bool bad = false;
-  for (uint32_t k = 0; k < cnt; ++k) {
-    const uint32_t i = perm[b + k];
-    double v[3];
-    load_vel<FORM>(P, i, v);
-    double m = B.mass;
-    if constexpr (EMB) {
-      const uint32_t tg = P.tag[i];
-      if (tg >= B.n_solvent) m = emb_mass[tg - B.n_solvent];
-    }
-    fx_add(S[0], m * v[0], bad);
-    fx_add(S[1], m * v[1], bad);
-    fx_add(S[2], m * v[2], bad);
-  }
-  mom[3 * c] = fx_value(S[0]);
-  mom[3 * c + 1] = fx_value(S[1]);
-  mom[3 * c + 2] = fx_value(S[2]);
-  if (bad) atomicOr(err, ERR_FIXED_RANGE);
+// ------------------------------------------------- elementwise over slabs
+// Valid slot k of tile T: k < cnt[T]. Grid: ntiles * ceil(cap / 256) blocks.
+struct SlabIter {
+  uint32_t T, k;
+  size_t i;
+  bool valid;
+};
+__device__ inline SlabIter slab_slot(const Box& B, const uint32_t* cnt) {
+  const uint32_t per = (B.cap + 255u) / 256u;
+  SlabIter s;
+  s.T = blockIdx.x / per;
+  s.k = (blockIdx.x % per) * 256u + threadIdx.x;
+  s.i = (size_t)s.T * B.cap + s.k;
+  s.valid = s.T < B.ntiles && s.k < min(cnt[s.T], B.cap);
+  return s;
+}
+
+template <int FORM>
+__global__ __launch_bounds__(256) void k_stream(Particles P, Box B, const uint32_t* cnt,
+                                                uint32_t* status) {
+  const SlabIter s = slab_slot(B, cnt);
+  if (!s.valid) return;
+  double v[3];
+  load_vel<FORM>(P, s.i, v);
+  Pos<FORM> r;
+  r.load(P, s.i);
+  uint32_t e = 0;
+  r.stream(B, v, e);
+  r.store(P, s.i);
+  if (e) atomicOr(&status[0], e);
+}
+
+// Cell of every particle for shift s, in tag order, and the occupancy.
+template <int FORM>
+__global__ __launch_bounds__(256) void k_cells(Particles P, Box B, const uint32_t* cnt,
+                                               double s0, double s1, double s2, float t0,
+                                               float t1, float t2, int32_t* cell_of_tag,
+                                               uint32_t* counts) {
+  const SlabIter s = slab_slot(B, cnt);
+  if (!s.valid) return;
+  Pos<FORM> r;
+  r.load(P, s.i);
+  const double sd[3] = {s0, s1, s2};
+  const float s32[3] = {t0, t1, t2};
+  int c[3];
+  r.cell3(B, sd, s32, c);
+  const uint32_t cell = cell_index(B, c);
+  if (cell_of_tag) cell_of_tag[P.tag[s.i]] = (int32_t)cell;
+  if (counts) atomicAdd(&counts[cell], 1u);
 }
 
 // Net momentum, kinetic energy and mass in fixed point: block sums in LDS
 // (integer, so exact), then 64-bit atomics, which commute.
 template <int FORM, bool EMB>
-__global__ __launch_bounds__(256) void k_totals(Particles P, Box B, uint32_t N,
+__global__ __launch_bounds__(256) void k_totals(Particles P, Box B, const uint32_t* cnt,
                                                 const double* __restrict__ emb_mass,
-                                                long long* tot, uint32_t* err) {
+                                                long long* tot, uint32_t* status) {
   __shared__ long long red[10][256];
   Fx acc[5] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}, {0, 0}};
   bool bad = false;
-  for (uint32_t j = blockIdx.x * 256u + threadIdx.x; j < N; j += gridDim.x * 256u) {
+  const SlabIter s = slab_slot(B, cnt);
+  if (s.valid) {
     double v[3];
-    load_vel<FORM>(P, j, v);
+    load_vel<FORM>(P, s.i, v);
     double m = B.mass;
     if constexpr (EMB) {
-      const uint32_t tg = P.tag[j];
+      const uint32_t tg = P.tag[s.i];
       if (tg >= B.n_solvent) m = emb_mass[tg - B.n_solvent];
     }
     fx_add(acc[0], m * v[0], bad);
@@ -610,28 +739,29 @@ __global__ __launch_bounds__(256) void k_totals(Particles P, Box B, uint32_t N,
     red[2 * q + 1][threadIdx.x] = acc[q].lo;
   }
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s)
-      for (int q = 0; q < 10; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + s];
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int q = 0; q < 10; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + st];
     __syncthreads();
   }
   if (threadIdx.x < 10)
     atomicAdd(reinterpret_cast<unsigned long long*>(&tot[threadIdx.x]),
               (unsigned long long)red[threadIdx.x][0]);
-  if (bad) atomicOr(err, ERR_FIXED_RANGE);
+  if (bad) atomicOr(&status[0], ERR_FIXED_RANGE);
 }
 
 // ------------------------------------------------------------ state I/O
-// Row-major N x 3 doubles (tag order) -> internal layout; checks the box.
-template <int FORM>
+// Row-major N x 3 doubles (tag order) -> internal form, placed in the slab of
+// the tile of the particle's home cell. Pass 1 (PLACE == false) only counts
+// per tile and checks the box; pass 2 writes.
+template <int FORM, bool PLACE>
 __global__ __launch_bounds__(256) void k_import(Particles P, Box B,
                                                 const double* __restrict__ pos,
                                                 const double* __restrict__ vel,
-                                                uint32_t n, uint32_t tag0,
+                                                uint32_t n, uint32_t tag0, uint32_t* cnt,
                                                 uint32_t* bad_pos) {
   const uint32_t t = blockIdx.x * 256u + threadIdx.x;
   if (t >= n) return;
-  const uint32_t j = tag0 + t;
   double x[3], v[3];
   bool bad = false;
 #pragma unroll
@@ -640,15 +770,17 @@ __global__ __launch_bounds__(256) void k_import(Particles P, Box B,
     v[d] = vel[3ull * t + d];
     bad |= !(x[d] >= 0.0 && x[d] < B.L[d]);
   }
-  if (bad) atomicOr(bad_pos, 1u);
+  if (bad) {
+    atomicOr(bad_pos, 1u);
+    return;
+  }
+  Pos<FORM> r;
+  const double w[3] = {v[0], v[1], v[2]};
   if constexpr (FORM == 0) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      P.x[d][j] = x[d];
-      P.v[d][j] = v[d];
-    }
+    r.x[0] = x[0];
+    r.x[1] = x[1];
+    r.x[2] = x[2];
   } else {
-    int h[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       int hd = (int)floor(x[d] * B.inv_a);
@@ -659,60 +791,68 @@ __global__ __launch_bounds__(256) void k_import(Particles P, Box B,
         hd = hd + 1 == B.n[d] ? 0 : hd + 1;
       }
       if (o < 0.0f) o = 0.0f;
-      h[d] = hd;
-      P.o[d][j] = o;
-      P.vf[d][j] = (float)v[d];
+      r.h[d] = hd;
+      r.o[d] = o;
     }
-    P.h[j] = pack_home(h[0], h[1], h[2]);
   }
-  P.tag[j] = j;
+  int c[3];
+  r.home3(B, c);
+  const uint32_t T = tile_index(B, c);
+  const uint32_t slot = atomicAdd(&cnt[T], 1u);
+  if constexpr (PLACE) {
+    if (slot < B.cap) {
+      const size_t j = (size_t)T * B.cap + slot;
+      store_vel<FORM>(P, j, w);
+      P.tag[j] = tag0 + t;
+      r.store(P, j);
+    } else {
+      atomicOr(bad_pos, 2u);
+    }
+  }
 }
 
-// Internal layout -> row-major N x 3 doubles in tag order.
+// Internal form -> row-major N x 3 doubles in tag order.
 template <int FORM>
-__global__ __launch_bounds__(256) void k_export(Particles P, Box B, uint32_t N,
+__global__ __launch_bounds__(256) void k_export(Particles P, Box B, const uint32_t* cnt,
                                                 double* __restrict__ pos,
                                                 double* __restrict__ vel) {
-  const uint32_t j = blockIdx.x * 256u + threadIdx.x;
-  if (j >= N) return;
-  const uint32_t t = P.tag[j];
+  const SlabIter s = slab_slot(B, cnt);
+  if (!s.valid) return;
+  const uint32_t t = P.tag[s.i];
   if constexpr (FORM == 0) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      pos[3ull * t + d] = P.x[d][j];
-      vel[3ull * t + d] = P.v[d][j];
+      pos[3ull * t + d] = P.x[d][s.i];
+      vel[3ull * t + d] = P.v[d][s.i];
     }
   } else {
     int h[3];
-    unpack_home(P.h[j], h[0], h[1], h[2]);
+    unpack_home(P.h[s.i], h[0], h[1], h[2]);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      pos[3ull * t + d] = (double)h[d] * B.a + (double)P.o[d][j];
-      vel[3ull * t + d] = (double)P.vf[d][j];
+      pos[3ull * t + d] = (double)h[d] * B.a + (double)P.o[d][s.i];
+      vel[3ull * t + d] = (double)P.vf[d][s.i];
     }
   }
 }
 
-// Cells of the last binning in tag order: from (cell, rank) of the current
-// order, or, after a collide, from the cell-ordered layout itself.
-__global__ __launch_bounds__(256) void k_cells_from_cr(const uint32_t* __restrict__ tag,
-                                                       const uint2* __restrict__ cr,
-                                                       uint32_t N, int32_t* out) {
-  const uint32_t j = blockIdx.x * 256u + threadIdx.x;
-  if (j >= N) return;
-  out[tag[j]] = (int32_t)cr[j].x;
-}
-
-__global__ __launch_bounds__(256) void k_cells_from_order(const uint32_t* __restrict__ tag,
-                                                          const uint32_t* __restrict__ off,
-                                                          uint32_t ncells, int32_t* out,
-                                                          int32_t* counts) {
-  const uint32_t c = blockIdx.x * 256u + threadIdx.x;
-  if (c >= ncells) return;
-  const uint32_t b = off[c], e = off[c + 1];
-  if (counts) counts[c] = (int32_t)(e - b);
-  if (out)
-    for (uint32_t j = b; j < e; ++j) out[tag[j]] = (int32_t)c;
+// Copy the valid slots of every tile from slabs of capacity old_cap to slabs
+// of capacity B.cap (B.cap >= old_cap); used when slabs are enlarged.
+template <int FORM>
+__global__ __launch_bounds__(256) void k_repack(Particles src, Particles dst, Box B,
+                                                uint32_t old_cap, const uint32_t* cnt) {
+  const uint32_t per = (old_cap + 255u) / 256u;
+  const uint32_t T = blockIdx.x / per;
+  const uint32_t k = (blockIdx.x % per) * 256u + threadIdx.x;
+  if (T >= B.ntiles || k >= min(cnt[T], old_cap)) return;
+  const size_t i = (size_t)T * old_cap + k, j = (size_t)T * B.cap + k;
+  double v[3];
+  load_vel<FORM>(src, i, v);
+  store_vel<FORM>(dst, j, v);
+  Pos<FORM> r;
+  r.load(src, i);
+  r.store(dst, j);
+  dst.tag[j] = src.tag[i];
 }
 
 // --------------------------------------------------------- test kernels
