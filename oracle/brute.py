@@ -38,6 +38,9 @@ def _gamma(k, cell, step, p):
         if t <= 0.0:
             continue
         V = t * t * t
+        sq = g * g
+        if u2 < 1.0 - 0.0331 * (sq * sq):
+            return d * V * p.kT
         if math.log(u2) < 0.5 * g * g + d - d * V + d * math.log(V):
             return d * V * p.kT
     raise RuntimeError("Gamma sampler exceeded its attempt cap")

@@ -17,8 +17,8 @@ Readings of points the paper leaves open (each is listed in the design doc):
 * Philox4x32-10 counters: (cell, step, purpose, attempt), key = seed;
 * axis by the cylindrical (Archimedes) projection z = 2u1 - 1, phi = 2 pi u2;
 * thermostat draws E ~ Gamma(3(Nc-1)/2, kT) (centre-of-mass motion removed)
-  by Marsaglia-Tsang with a Box-Muller normal (cos branch), at most 64
-  attempts; xi = 1 for Nc < 2 or E_k = 0;
+  by Marsaglia-Tsang (with its squeeze test) and a Box-Muller normal (cos
+  branch), at most 64 attempts; xi = 1 for Nc < 2 or E_k = 0;
 * rotation by +alpha, right-handed (Rodrigues' formula).
 """
 from dataclasses import dataclass, field
@@ -148,8 +148,11 @@ def cell_axes(cells, step, p):
 def gamma_marsaglia_tsang(shape_k, cells, step, p, theta):
     """Gamma(shape_k, scale theta) by Marsaglia and Tsang's rejection method
     with a Box-Muller normal (sec. 3.6, thermostat). Attempt j of a cell uses
-    Philox counter (cell, step, TAG_THERMO, j): words 0 and 1 make the normal,
-    word 2 the acceptance uniform. Valid for shape_k >= 1 (here >= 1.5).
+    Philox counter (cell, step, TAG_THERMO, j): words 0 and 1 make the normal
+    g, word 2 the acceptance uniform U. With t = 1 + c g > 0 and V = t^3 the
+    attempt is accepted if U < 1 - 0.0331 g^4 (the method's squeeze, a subset
+    of the acceptance region) or log U < g^2/2 + d - d V + d log V; the draw is
+    d V theta. Valid for shape_k >= 1 (here >= 1.5).
     Returns (draw, attempts); a cell still rejected after 64 attempts gets
     NaN, which callers treat as an error."""
     shape_k = np.asarray(shape_k, dtype=np.float64)
@@ -177,9 +180,11 @@ def gamma_marsaglia_tsang(shape_k, cells, step, p, theta):
         pos = t > 0.0
         V = t * t * t
         dd = d[todo]
+        sq = g * g
+        squeeze = u2 < 1.0 - 0.0331 * (sq * sq)
         with np.errstate(invalid="ignore", divide="ignore"):
             rhs = 0.5 * g * g + dd - dd * V + dd * np.log(np.where(pos, V, 1.0))
-        acc = pos & (np.log(u2) < rhs)
+        acc = pos & (squeeze | (np.log(u2) < rhs))
         attempts[todo] = j + 1
         hit = todo[acc]
         out[hit] = dd[acc] * V[acc] * theta

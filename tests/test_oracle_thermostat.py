@@ -76,3 +76,24 @@ def test_maxwell_boltzmann_relaxation_from_equal_speeds():
     vx = vel[:, 0]
     assert stats.kstest(vx, stats.norm(scale=1.0).cdf).pvalue > 1e-4
     assert abs(stats.kurtosis(vx, fisher=False) - 3.0) < 0.1
+
+
+@pytest.mark.parametrize("k", [1.5, 3.0, 13.5, 60.0])
+def test_squeeze_is_inside_the_acceptance_region(k):
+    """Marsaglia and Tsang's squeeze U < 1 - 0.0331 g^4 only accepts points
+    the full test log U < g^2/2 + d - dV + d log V accepts too, so using it
+    changes no decision (checked in FP64 on 10^6 random points)."""
+    rng = np.random.default_rng(int(k * 10))
+    d = k - 1.0 / 3.0
+    c = 1.0 / math.sqrt(9.0 * d)
+    g = rng.normal(size=1_000_000)
+    u = rng.random(1_000_000)
+    t = 1.0 + c * g
+    ok = t > 0
+    g, u, t = g[ok], u[ok], t[ok]
+    V = t * t * t
+    sq = g * g
+    squeeze = u < 1.0 - 0.0331 * (sq * sq)
+    full = np.log(u) < 0.5 * g * g + d - d * V + d * np.log(V)
+    assert squeeze.mean() > 0.9
+    assert not np.any(squeeze & ~full)
