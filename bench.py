@@ -43,6 +43,22 @@ def floor_bytes_per_update(form, rho):
     return 2 * STATE_BYTES[form] + 8.0 / rho
 
 
+def measured_traffic(form):
+    """HBM bytes per launch of the step kernel from the rocprofv3 FETCH_SIZE
+    / WRITE_SIZE runs recorded in profiles/traffic.json, scaled by the copy
+    calibration stated there; None unless they were taken on the current
+    kernel sources."""
+    from paper_1801_10187_amd.build import source_hash
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != source_hash():
+        return None
+    return rec.get("bytes_per_launch", {}).get(WORKLOAD, {}).get(form)
+
+
 def run_form(m, pos, vel, cfg, precision, steps, warmup):
     import torch
     sim = m.Sim(pos, vel, cfg["n_cells"], kT=cfg["kT"], seed=cfg["seed"],
@@ -67,6 +83,29 @@ def run_form(m, pos, vel, cfg, precision, steps, warmup):
                 net_momentum=float(np.abs(P).max()), kT=kT)
 
 
+def copy_ceiling(m, nbytes=1 << 30, reps=20):
+    """Bandwidth of the library's plain streaming copy kernel (read + write
+    bytes per second) on two device buffers of `nbytes`: the practical HBM
+    ceiling the step kernel is compared with."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    stream = torch.cuda.current_stream().cuda_stream
+    for _ in range(3):
+        m.copy_kernel(src.data_ptr(), dst.data_ptr(), nbytes, stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        m.copy_kernel(src.data_ptr(), dst.data_ptr(), nbytes, stream)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    return 2.0 * nbytes / sec / 1e9
+
+
 def cpu_baseline(pos, vel, cfg, nsteps):
     from oracle import srd
     p = srd.Params(cfg["n_cells"], seed=cfg["seed"], thermostat=cfg["thermostat"],
@@ -89,6 +128,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fp32,fp64")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="only run the streaming copy kernel (1 GiB, 20 times)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -99,6 +140,10 @@ def main():
     import paper_1801_10187_amd as m
     import workloads
 
+    if args.copy_only:
+        torch.cuda.init()
+        print(json.dumps({"copy_GBs": copy_ceiling(m)}), flush=True)
+        return
     cfg = workloads.CONFIGS[WORKLOAD]
     pos, vel = workloads.fluid(cfg["n_cells"], cfg["density"], kT=cfg["kT"],
                                seed=cfg["seed"])
@@ -147,7 +192,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": head["collide_GBs"] / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(head_form),
             "kernel": "k_tile (collide + stream + bin + scatter)",
             "kernel_avg_us": head["collide_avg_us"],
             "bytes_per_particle": collide_bytes_per_particle(head_form, rho),
@@ -158,6 +203,8 @@ def main():
                       "step_floor_frac": r["step_floor_frac"], "kT_end": r["kT"],
                       "net_momentum_end": r["net_momentum"]} for f, r in res.items()},
     }
+    out["copy_ceiling_GBs"] = copy_ceiling(m)
+    out["roofline"]["frac_of_copy_ceiling"] = head["collide_GBs"] / out["copy_ceiling_GBs"]
     if "fp32" in res and "fp64" in res:
         out["fp32_over_fp64"] = res["fp32"]["updates_per_s"] / res["fp64"]["updates_per_s"]
     if not args.no_cpu_baseline:

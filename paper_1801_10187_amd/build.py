@@ -32,6 +32,17 @@ FLAGS = [
 ]
 
 
+def source_hash():
+    """SHA-256 over the library sources and header (identifies the kernels a
+    measurement was taken on)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in DEPS:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose=False):
     """Compile the library (always; a fresh build each call)."""
     tmp = LIB + ".tmp"

@@ -134,7 +134,13 @@ __device__ inline void stream_axis32(float& o, int& h, float v, float dt32,
   }
   if (o2 < 0.0f) o2 = 0.0f;
   o = o2;
-  h = wrap_index(h + (k % n), n);
+  // periodic home cell; a move of a whole box or more (never for
+  // |v dt| < L) takes the general modulo
+  int hn = h + k;
+  hn += hn < 0 ? n : 0;
+  hn -= hn >= n ? n : 0;
+  if (hn < 0 || hn >= n) hn = wrap_index(hn, n);
+  h = hn;
 }
 
 __device__ inline int bin_axis32(float o, int h, float s32, float inv_a32,
@@ -159,34 +165,52 @@ __device__ inline void unpack_home(uint32_t h, int& hx, int& hy, int& hz) {
 
 // ------------------------------------------------------- per-cell draws
 // Rotation axis by the cylindrical projection (sec. 3.6): z = 2 u1 - 1,
-// phi = 2 pi u2, n = (r cos phi, r sin phi, z), r = sqrt(1 - z^2).
+// phi = 2 pi u2, n = (r cos phi, r sin phi, z), r = sqrt(1 - z^2). The
+// angle functions are evaluated as sincospi(2 u2), which needs no argument
+// reduction.
 __device__ inline void cell_axis(uint32_t cell, uint32_t step, uint32_t k0,
                                  uint32_t k1, double n[3]) {
   const U4 w = philox4x32_10(U4{cell, step, TAG_AXIS, 0u}, k0, k1);
   const double z = 2.0 * u01(w.x) - 1.0;
-  const double phi = (2.0 * M_PI) * u01(w.y);
   const double r = sqrt(fmax(0.0, 1.0 - z * z));
-  n[0] = r * cos(phi);
-  n[1] = r * sin(phi);
+  double sp, cp;
+  sincospi(2.0 * u01(w.y), &sp, &cp);
+  n[0] = r * cp;
+  n[1] = r * sp;
   n[2] = z;
 }
 
-// Gamma(k, theta) for k >= 1 by Marsaglia and Tsang's rejection method with a
-// Box-Muller normal (cos branch), attempt j drawn from counter
-// (cell, step, TAG_THERMO, j): words 0, 1 -> normal, word 2 -> acceptance.
+// Attempt j of Marsaglia and Tsang's Gamma(k, theta) sampler (k >= 1;
+// d = k - 1/3, c = 1/sqrt(9 d)), drawn from counter (cell, step,
+// TAG_THERMO, j): words 0, 1 give a Box-Muller normal g (cos branch), word 2
+// the uniform U. With t = 1 + c g > 0 and V = t^3, accept if
+// U < 1 - 0.0331 g^4 (squeeze) or log U < g^2/2 + d - d V + d log V.
+// Returns d V theta, or -1 when the attempt is rejected.
+__device__ inline double gamma_attempt(uint32_t cell, uint32_t step, uint32_t j,
+                                       double d, double c, double theta,
+                                       uint32_t k0, uint32_t k1) {
+  const U4 w = philox4x32_10(U4{cell, step, TAG_THERMO, j}, k0, k1);
+  const double u0 = u01(w.x), u1 = u01(w.y), u2 = u01(w.z);
+  const double g = sqrt(-2.0 * log(u0)) * cospi(2.0 * u1);
+  const double t = 1.0 + c * g;
+  if (t <= 0.0) return -1.0;
+  const double V = t * t * t;
+  const double sq = g * g;
+  if (u2 < 1.0 - 0.0331 * (sq * sq)) return d * V * theta;
+  if (log(u2) < 0.5 * g * g + d - d * V + d * log(V)) return d * V * theta;
+  return -1.0;
+}
+
+// The sampler run attempt after attempt from attempt j0 on; cap_hit is set
+// if GAMMA_MAX_ATTEMPTS attempts are all rejected.
 __device__ inline double gamma_mt(double k, uint32_t cell, uint32_t step,
                                   uint32_t k0, uint32_t k1, double theta,
-                                  bool& cap_hit) {
+                                  bool& cap_hit, uint32_t j0 = 0u) {
   const double d = k - 1.0 / 3.0;
   const double c = 1.0 / sqrt(9.0 * d);
-  for (uint32_t j = 0; j < (uint32_t)GAMMA_MAX_ATTEMPTS; ++j) {
-    const U4 w = philox4x32_10(U4{cell, step, TAG_THERMO, j}, k0, k1);
-    const double u0 = u01(w.x), u1 = u01(w.y), u2 = u01(w.z);
-    const double g = sqrt(-2.0 * log(u0)) * cos((2.0 * M_PI) * u1);
-    const double t = 1.0 + c * g;
-    if (t <= 0.0) continue;
-    const double V = t * t * t;
-    if (log(u2) < 0.5 * g * g + d - d * V + d * log(V)) return d * V * theta;
+  for (uint32_t j = j0; j < (uint32_t)GAMMA_MAX_ATTEMPTS; ++j) {
+    const double e = gamma_attempt(cell, step, j, d, c, theta, k0, k1);
+    if (e >= 0.0) return e;
   }
   cap_hit = true;
   return k * theta;

@@ -347,6 +347,16 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
     return fx_value(f);
   };
 
+  // per-cell work is done by TPC threads per cell: cell l, sub-thread sub
+  const uint32_t l = tid / (uint32_t)TPC, sub = tid % (uint32_t)TPC;
+  int lc3[3];
+  lc3[0] = (int)(l % (uint32_t)B.td[0]);
+  lc3[1] = (int)((l / (uint32_t)B.td[0]) % (uint32_t)B.td[1]);
+  lc3[2] = (int)(l / ((uint32_t)B.td[0] * (uint32_t)B.td[1]));
+  const bool cell_ok = l < (uint32_t)CPT && lc3[0] < ext[0] && lc3[1] < ext[1] && lc3[2] < ext[2];
+  const int gc3[3] = {org[0] + lc3[0], org[1] + lc3[1], org[2] + lc3[2]};
+  const uint32_t gcell = cell_ok ? cell_index(B, gc3) : 0u;
+
   // ---- gather this tile's particles (register-resident part)
   VT v[TQ][3];
   uint32_t tg[TQ];
@@ -373,6 +383,12 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
     }
   }
 
+  // the cell's rotation axis needs only (cell, step): draw it while the
+  // gathers are in flight
+  double n[3] = {0.0, 0.0, 0.0};
+  if constexpr (COLL)
+    if (sub == 0u && cell_ok) cell_axis(gcell, A.step, B.k0, B.k1, n);
+
   // ---- scatter: bin for the destination shift, reserve slots, write
   auto scatter = [&](const double* sd, const float* sd32, const double (*w)[3]) {
     // w[q]: velocity to store (already rounded to the storage precision)
@@ -390,7 +406,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
         dest[q] = b < 27u ? bin_tile(B, t3, b) : tile_index(B, c);
       }
       bins[q] = b;
-      ranks[q] = wave_rank(b, act && b < 27u, s_bincnt);
+      ranks[q] = (act && b < 27u) ? atomicAdd(&s_bincnt[b], 1u) : 0u;
     }
     __syncthreads();
     if (tid < 27u && s_bincnt[tid] > 0u)
@@ -479,19 +495,11 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
     }
     __syncthreads();
 
-    // ---- per cell: TPC threads per cell. u and axis on sub-thread 0;
-    // Gamma attempts in parallel (attempt j on sub-thread j; the first
-    // accepted one in attempt order is the draw)
-    const uint32_t l = tid / (uint32_t)TPC, sub = tid % (uint32_t)TPC;
-    int lc3[3];
-    lc3[0] = (int)(l % (uint32_t)B.td[0]);
-    lc3[1] = (int)((l / (uint32_t)B.td[0]) % (uint32_t)B.td[1]);
-    lc3[2] = (int)(l / ((uint32_t)B.td[0] * (uint32_t)B.td[1]));
-    const bool cell_ok = l < (uint32_t)CPT && lc3[0] < ext[0] && lc3[1] < ext[1] && lc3[2] < ext[2];
-    const int gc3[3] = {org[0] + lc3[0], org[1] + lc3[1], org[2] + lc3[2]};
-    const uint32_t gcell = cell_ok ? cell_index(B, gc3) : 0u;
+    // ---- per cell: u on sub-thread 0; Gamma attempts in parallel
+    // (attempt j on sub-thread j; the first accepted one in attempt order is
+    // the draw, exactly as when the attempts are made one after another)
     const uint32_t nc = cell_ok ? (uint32_t)s_acc[0][l] : 0u;
-    double n[3] = {0.0, 0.0, 0.0};
+    if (nc == 0u) n[0] = n[1] = n[2] = 0.0;
     if (sub == 0u) {
       double u[3] = {0.0, 0.0, 0.0};
       if (nc > 0u) {
@@ -499,7 +507,6 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
         u[0] = acc_val(1, l) / M;
         u[1] = acc_val(3, l) / M;
         u[2] = acc_val(5, l) / M;
-        cell_axis(gcell, A.step, B.k0, B.k1, n);
       }
       if (l < (uint32_t)CPT) {
         s_u[0][l] = u[0];
@@ -513,15 +520,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
         if (nc >= 2u) {
           const double k = 1.5 * (double)(nc - 1u);
           const double d = k - 1.0 / 3.0;
-          const double c = 1.0 / sqrt(9.0 * d);
-          const U4 w = philox4x32_10(U4{gcell, A.step, TAG_THERMO, sub}, B.k0, B.k1);
-          const double u0 = u01(w.x), u1 = u01(w.y), u2 = u01(w.z);
-          const double gn = sqrt(-2.0 * log(u0)) * cos((2.0 * M_PI) * u1);
-          const double t = 1.0 + c * gn;
-          if (t > 0.0) {
-            const double V = t * t * t;
-            if (log(u2) < 0.5 * gn * gn + d - d * V + d * log(V)) g = d * V * B.kT;
-          }
+          g = gamma_attempt(gcell, A.step, sub, d, 1.0 / sqrt(9.0 * d), B.kT, B.k0, B.k1);
         }
         s_g[sub][l] = g;
       }
@@ -561,25 +560,8 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
         if (nc >= 2u && ek > 0.0) {
           double ehat = -1.0;
           for (uint32_t j = 0; j < (uint32_t)TPC && ehat < 0.0; ++j) ehat = s_g[j][l];
-          if (ehat < 0.0) {
-            // every speculative attempt was rejected: continue in order
-            const double k = 1.5 * (double)(nc - 1u);
-            const double d = k - 1.0 / 3.0;
-            const double c = 1.0 / sqrt(9.0 * d);
-            for (uint32_t j = TPC; j < (uint32_t)GAMMA_MAX_ATTEMPTS && ehat < 0.0; ++j) {
-              const U4 w = philox4x32_10(U4{gcell, A.step, TAG_THERMO, j}, B.k0, B.k1);
-              const double u0 = u01(w.x), u1 = u01(w.y), u2 = u01(w.z);
-              const double gn = sqrt(-2.0 * log(u0)) * cos((2.0 * M_PI) * u1);
-              const double t = 1.0 + c * gn;
-              if (t <= 0.0) continue;
-              const double V = t * t * t;
-              if (log(u2) < 0.5 * gn * gn + d - d * V + d * log(V)) ehat = d * V * B.kT;
-            }
-            if (ehat < 0.0) {
-              cap = true;
-              ehat = k * B.kT;
-            }
-          }
+          if (ehat < 0.0)  // every speculative attempt was rejected
+            ehat = gamma_mt(1.5 * (double)(nc - 1u), gcell, A.step, B.k0, B.k1, B.kT, cap, TPC);
           xi = sqrt(ehat / ek);
         }
       }
