@@ -30,7 +30,9 @@ WORKLOAD = "srd_100c_rho10_mbthermo"
 
 # Algorithmic bytes per particle of one step kernel (what its contract reads
 # once and writes once): the particle state and its 4-byte tag in, the same
-# out. The per-tile counters (a few bytes per ~640 particles) are left out.
+# out. Left out: the per-tile counters (a few bytes per ~640 particles) and
+# the one-byte local cell the kernel keeps beside each particle (an
+# implementation cache, 2 bytes per particle per step moved on top).
 STATE_BYTES = {"fp32": 28, "fp64": 48}
 
 

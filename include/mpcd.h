@@ -171,7 +171,9 @@ mpcd_status mpcd_get_layout(mpcd_ctx ctx, int32_t tile[3], int64_t* n_tiles,
 
 /* Kernel timing with HIP events on the context's stream. which: 0 the
  * collision kernel (collide, stream and bin of the next step), 1 the
- * stream / stream+bin kernels, 2 unused (always 0 launches). While enabled,
+ * stream / stream+bin kernels, 2 the thermostat draw kernel (Gamma draws of
+ * every cell, launched before each collision when the thermostat is on;
+ * sec. 3.6). While enabled,
  * each launch is bracketed by two events; mpcd_profile_read synchronises,
  * returns the summed milliseconds and launch count since the last read,
  * and clears them. */

@@ -52,13 +52,16 @@ mpcd_status fail(mpcd_status st, const char* fmt, ...) {
 enum class Phase { Idle, Streamed, Binned };
 
 // One queued kernel of a stepping call.
-enum class Op { BinStream, Bin, CollideScatter, Collide };
+enum class Op { BinStream, Bin, Draw, CollideScatter, Collide };
 struct Launch {
   Op op;
   uint64_t step;
 };
 
 constexpr uint32_t kGrid = 256;  // threads per block of the elementwise kernels
+// slots per tile stay below 2^28: a slot's byte offset inside its tile's
+// slab then fits 32 bits for every element size
+constexpr uint32_t kMaxCap = 1u << 28;
 
 inline uint32_t blocks_for(uint64_t n, uint32_t per) {
   return (uint32_t)((n + per - 1) / per);
@@ -85,6 +88,7 @@ struct mpcd_ctx_s {
   int ci = 0;                      // cnt[ci] describes buf[cur]
   double* emb_mass = nullptr;
   uint32_t* status = nullptr;      // [0] errors, [1] overflow, [2] failing launch
+  double* ehat = nullptr;          // thermostat draws of the next collision, [tile][cpt]
   long long* tot = nullptr;
 
   uint64_t step = 0;
@@ -119,11 +123,10 @@ mpcd_status take_err(mpcd_ctx c) {
   HIP_TRY(hipStreamSynchronize(c->stream));
   if (e) {
     HIP_TRY(hipMemsetAsync(c->status, 0, sizeof e, c->stream));
-    return fail(MPCD_ERANGE, "kernel range check failed (flags 0x%x: %s%s%s%s)", e,
+    return fail(MPCD_ERANGE, "kernel range check failed (flags 0x%x: %s%s%s)", e,
                 (e & ERR_STREAM_RANGE) ? "displacement >= box length; " : "",
                 (e & ERR_FIXED_RANGE) ? "value outside fixed-point range; " : "",
-                (e & ERR_GAMMA_CAP) ? "Gamma sampler attempt cap; " : "",
-                (e & ERR_TILE) ? "particle outside its tile; " : "");
+                (e & ERR_GAMMA_CAP) ? "Gamma sampler attempt cap; " : "");
   }
   return MPCD_OK;
 }
@@ -217,10 +220,31 @@ TileArgs tile_args(mpcd_ctx c) {
   a.cnt_clear = c->cnt[(c->ci + 2) % 3];
   a.emb_mass = c->emb_mass;
   a.status = c->status;
+  a.ehat = c->ehat;
   return a;
 }
 
+template <int CPT>
+void draw_inst(mpcd_ctx c, uint64_t n, uint32_t seq) {
+  k_draw<CPT><<<c->box.ntiles, DrawShape<CPT>::THREADS, 0, c->stream>>>(
+      c->buf[c->cur], c->box, c->cnt[c->ci], (uint32_t)n, c->ehat, c->status, seq);
+}
+
+// Thermostat draws for the collision of step n on the current slabs.
+mpcd_status launch_draw(mpcd_ctx c, uint64_t n, uint32_t seq) {
+  if (!c->p.thermostat || c->box.ntiles == 0) return MPCD_OK;
+  ProfScope ps(c, 2);
+  switch (c->cpt) {
+    case 64: draw_inst<64>(c, n, seq); break;
+    case 128: draw_inst<128>(c, n, seq); break;
+    default: draw_inst<256>(c, n, seq); break;
+  }
+  HIP_TRY(hipGetLastError());
+  return MPCD_OK;
+}
+
 mpcd_status launch_tile(mpcd_ctx c, Op op, uint64_t n, uint32_t seq) {
+  if (op == Op::Draw) return launch_draw(c, n, seq);
   TileArgs a = tile_args(c);
   a.step = (uint32_t)n;
   a.seq = seq;
@@ -272,7 +296,8 @@ mpcd_status alloc_slabs(mpcd_ctx c, uint32_t cap, Particles out[2], std::vector<
       }
     }
     P.tag = (uint32_t*)get(S * 4);
-    if (!P.tag) return fail(MPCD_ENOMEM, "device allocation of the slabs failed");
+    P.lc = (uint8_t*)get(S);
+    if (!P.tag || !P.lc) return fail(MPCD_ENOMEM, "device allocation of the slabs failed");
   }
   return MPCD_OK;
 }
@@ -294,7 +319,8 @@ mpcd_status regrow(mpcd_ctx c, int in_cur, int in_ci) {
   const uint32_t old_cap = c->box.cap;
   const uint64_t target = std::max<uint64_t>((uint64_t)mx + mx / 4 + 64, (uint64_t)old_cap + old_cap / 2);
   const uint32_t new_cap = round_up(target, 64);
-  if ((uint64_t)new_cap * nt >= (1ull << 32)) return fail(MPCD_ENOMEM, "slab storage beyond 2^32 slots");
+  if ((uint64_t)new_cap * nt >= (1ull << 32) || new_cap >= kMaxCap)
+    return fail(MPCD_ENOMEM, "slab storage beyond 2^32 slots or 2^28 per tile");
   Particles nb[2];
   std::vector<void*> owned;
   mpcd_status st = alloc_slabs(c, new_cap, nb, owned);
@@ -393,12 +419,14 @@ void choose_tiles(mpcd_ctx c) {
       B.td[d] = B.n[d];
       B.nt[d] = 1;
       B.tsh[d] = 0;
+      B.lm[d] = 0xFFFFFFFFu;
     } else {
       B.td[d] = td[d];
       B.nt[d] = (B.n[d] + td[d] - 1) / td[d];
       int sh = 0;
       while ((1 << sh) < td[d]) ++sh;
       B.tsh[d] = sh;
+      B.lm[d] = (uint32_t)td[d] - 1u;
     }
     B.ntiles *= (uint32_t)B.nt[d];
   }
@@ -476,6 +504,10 @@ mpcd_status mpcd_create(const mpcd_params* params, int64_t n_solvent, const doub
   c->status = (uint32_t*)c->dalloc(256);
   c->tot = (long long*)c->dalloc(10 * 8);
   c->emb_mass = (double*)c->dalloc((size_t)c->n_emb * 8);
+  if (params->thermostat) {
+    c->ehat = (double*)c->dalloc(NT * (size_t)c->cpt * 8);
+    if (!c->ehat) return cleanup(fail(MPCD_ENOMEM, "device allocation failed"));
+  }
   uint32_t* bad = (uint32_t*)c->dalloc(256);
   if (!c->cnt[0] || !c->cnt[1] || !c->cnt[2] || !c->status || !c->tot || !c->emb_mass || !bad)
     return cleanup(fail(MPCD_ENOMEM, "device allocation failed"));
@@ -546,9 +578,9 @@ mpcd_status mpcd_create(const mpcd_params* params, int64_t n_solvent, const doub
     const uint64_t cap = std::max<uint64_t>((uint64_t)mx + mx / 5, (uint64_t)(mean + 8.0 * std::sqrt(mean) + 64.0));
     B.cap = round_up(cap, 32);
   }
-  if ((uint64_t)B.cap * NT >= (1ull << 32)) {
+  if ((uint64_t)B.cap * NT >= (1ull << 32) || B.cap >= kMaxCap) {
     free_tmp();
-    return cleanup(fail(MPCD_ENOMEM, "slab storage beyond 2^32 slots"));
+    return cleanup(fail(MPCD_ENOMEM, "slab storage beyond 2^32 slots or 2^28 per tile"));
   }
   if ((st = alloc_slabs(c, B.cap, c->buf, c->slab_allocs)) != MPCD_OK) {
     free_tmp();
@@ -633,6 +665,7 @@ mpcd_status mpcd_bin(mpcd_ctx c) {
 mpcd_status mpcd_collide(mpcd_ctx c) {
   ST_TRY(check_ctx(c));
   if (c->phase != Phase::Binned) return fail(MPCD_ESTATE, "mpcd_collide: expected a preceding mpcd_bin");
+  ST_TRY(launch_draw(c, c->step, 0));
   ST_TRY(launch_tile(c, Op::Collide, c->step, 0));
   c->step += 1;
   c->phase = Phase::Idle;
@@ -648,8 +681,10 @@ mpcd_status mpcd_step(mpcd_ctx c, int64_t nsteps) {
   std::vector<Launch> L;
   L.reserve((size_t)nsteps + 1);
   L.push_back({Op::BinStream, c->step});
-  for (int64_t k = 0; k < nsteps; ++k)
+  for (int64_t k = 0; k < nsteps; ++k) {
+    if (c->p.thermostat) L.push_back({Op::Draw, c->step + (uint64_t)k});
     L.push_back({k + 1 < nsteps ? Op::CollideScatter : Op::Collide, c->step + (uint64_t)k});
+  }
   ST_TRY(run_launches(c, L));
   c->step += (uint64_t)nsteps;
   c->last_bin_step = c->step - 1;
@@ -740,6 +775,7 @@ static mpcd_status cell_diag(mpcd_ctx c, double* mass, double* mom, double* ek, 
   a.d_axis = tmp + 5 * C;
   a.d_xi = tmp + 8 * C;
   hipError_t e = hipMemsetAsync(tmp, 0, C * 8 * 9, c->stream);
+  if (e == hipSuccess && launch_draw(c, c->step, 0) != MPCD_OK) e = hipGetLastError();
   if (e == hipSuccess) {
     if (c->form == 0) tile_dispatch<0>(c, a, MODE_DIAG, false);
     else tile_dispatch<1>(c, a, MODE_DIAG, false);

@@ -91,6 +91,19 @@ __device__ inline double fx_value(const Fx& a) {
   return (double)a.hi * 0x1p-20 + (double)a.lo * 0x1p-72;
 }
 
+// One-limb variant used by the FP32 storage form: round(x 2^40) in one int64,
+// range |x| < 2^11, resolution 2^-40. A term's rounding error (<= 2^-41) is
+// far below the FP32 precision of the stored velocities; sums stay exact
+// integer sums, so they remain independent of the order of the terms.
+__device__ inline long long fx1_split(double x, bool& bad) {
+  const double C = 6755399441055744.0;  // 1.5 * 2^52
+  bad |= !(fabs(x) < 0x1p11);
+  const double t = x * 0x1p40 + C;  // x 2^40 is exact: one rounding
+  return __double_as_longlong(t) - 0x4338000000000000LL;
+}
+
+__device__ inline double fx1_value(long long a) { return (double)a * 0x1p-40; }
+
 // ------------------------------------------------------ wrap and binning
 // w in (-L, 2L) -> [0, L); the subtraction is exact (Sterbenz), an addition
 // that rounds up to L gives 0.

@@ -9,7 +9,9 @@
 //   FP64 form: x[3][S], v[3][S] double;
 //   FP32 form: h[S] home cell packed 10:10:10, o[3][S] float offset inside the
 //              home cell, v[3][S] float;
-//   tag[S] uint32 particle identity;            S = ntiles * cap.
+//   tag[S] uint32 particle identity;
+//   lc[S]  uint8 the particle's collision cell inside its tile, written by
+//          the launch that placed it there;      S = ntiles * cap.
 //
 // One step is one launch of k_tile: block T gathers its tile (binned for this
 // step: every particle's collision cell lies in T), sums each cell exactly in
@@ -29,7 +31,6 @@ enum : uint32_t {
   ERR_STREAM_RANGE = 1u,  // |v dt| >= L in the FP64 form
   ERR_FIXED_RANGE = 2u,   // a term outside the fixed-point range
   ERR_GAMMA_CAP = 4u,     // Gamma sampler reached its attempt cap
-  ERR_TILE = 8u,          // a particle was found outside its tile (a bug)
 };
 
 // status[0]: error flags above; status[1]: nonzero once a slab overflowed;
@@ -48,6 +49,7 @@ struct Box {
   int td[3];           // tile size in cells
   int tsh[3];          // log2(td) (td is a power of two whenever nt > 1)
   int nt[3];           // tiles per axis
+  uint32_t lm[3];      // cell -> cell inside its tile: c & lm (td - 1, or all ones if nt == 1)
   uint32_t ntiles;
   uint32_t cap;        // slots per tile
 };
@@ -59,7 +61,60 @@ struct Particles {
   float* o[3];
   float* vf[3];
   uint32_t* tag;
+  uint8_t* lc;   // local cell of the particle inside its tile (set by a scatter)
 };
+
+template <int FORM>
+struct VelT {
+  using T = double;
+};
+template <>
+struct VelT<1> {
+  using T = float;
+};
+
+// Slab element access. Inside one tile a 32-bit index k < cap addresses an
+// element as a 32-bit byte offset from the tile's base pointer, which is
+// uniform over the block (kept in scalar registers); a 64-bit index j is a
+// position in the whole slab array (scatter to another tile, elementwise
+// kernels). The tile capacity is below 2^28, so k * sizeof(T) fits 32 bits.
+template <class T>
+__device__ inline T ld(const T* base, uint32_t k) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) +
+                                     (uint32_t)(k * (uint32_t)sizeof(T)));
+}
+template <class T>
+__device__ inline void st(T* base, uint32_t k, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)(k * (uint32_t)sizeof(T))) = v;
+}
+template <class T>
+__device__ inline T ld(const T* base, size_t j) {
+  return base[j];
+}
+template <class T>
+__device__ inline void st(T* base, size_t j, T v) {
+  base[j] = v;
+}
+
+// The arrays of one form advanced to slot `off` (the first slot of a tile).
+template <int FORM>
+__device__ inline Particles tile_view(const Particles& P, size_t off) {
+  Particles Q = P;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if constexpr (FORM == 0) {
+      Q.x[d] = P.x[d] + off;
+      Q.v[d] = P.v[d] + off;
+    } else {
+      Q.o[d] = P.o[d] + off;
+      Q.vf[d] = P.vf[d] + off;
+    }
+  }
+  if constexpr (FORM == 1) Q.h = P.h + off;
+  Q.tag = P.tag + off;
+  Q.lc = P.lc + off;
+  return Q;
+}
 
 // Blocks are handed to the 8 XCDs round-robin; remapping makes XCD k work on
 // one contiguous range of tiles, so neighbouring tiles share its L2.
@@ -73,38 +128,29 @@ __device__ inline int tile_coord(int c, const Box& B, int d) {
   return B.nt[d] == 1 ? 0 : (c >> B.tsh[d]);
 }
 
-template <int FORM>
-struct VelT {
-  using T = double;
-};
-template <>
-struct VelT<1> {
-  using T = float;
-};
-
-template <int FORM>
-__device__ inline void load_vel(const Particles& P, size_t i, double v[3]) {
+template <int FORM, class I>
+__device__ inline void load_vel(const Particles& P, I i, typename VelT<FORM>::T v[3]) {
   if constexpr (FORM == 0) {
-    v[0] = P.v[0][i];
-    v[1] = P.v[1][i];
-    v[2] = P.v[2][i];
+    v[0] = ld(P.v[0], i);
+    v[1] = ld(P.v[1], i);
+    v[2] = ld(P.v[2], i);
   } else {
-    v[0] = (double)P.vf[0][i];
-    v[1] = (double)P.vf[1][i];
-    v[2] = (double)P.vf[2][i];
+    v[0] = ld(P.vf[0], i);
+    v[1] = ld(P.vf[1], i);
+    v[2] = ld(P.vf[2], i);
   }
 }
 
-template <int FORM>
-__device__ inline void store_vel(const Particles& P, size_t j, const double w[3]) {
+template <int FORM, class I>
+__device__ inline void store_vel(const Particles& P, I j, const typename VelT<FORM>::T w[3]) {
   if constexpr (FORM == 0) {
-    P.v[0][j] = w[0];
-    P.v[1][j] = w[1];
-    P.v[2][j] = w[2];
+    st(P.v[0], j, w[0]);
+    st(P.v[1], j, w[1]);
+    st(P.v[2], j, w[2]);
   } else {
-    P.vf[0][j] = (float)w[0];
-    P.vf[1][j] = (float)w[1];
-    P.vf[2][j] = (float)w[2];
+    st(P.vf[0], j, w[0]);
+    st(P.vf[1], j, w[1]);
+    st(P.vf[2], j, w[2]);
   }
 }
 
@@ -114,15 +160,17 @@ struct Pos;
 template <>
 struct Pos<0> {
   double x[3];
-  __device__ void load(const Particles& P, size_t i) {
-    x[0] = P.x[0][i];
-    x[1] = P.x[1][i];
-    x[2] = P.x[2][i];
+  template <class I>
+  __device__ void load(const Particles& P, I i) {
+    x[0] = ld(P.x[0], i);
+    x[1] = ld(P.x[1], i);
+    x[2] = ld(P.x[2], i);
   }
-  __device__ void store(const Particles& P, size_t j) const {
-    P.x[0][j] = x[0];
-    P.x[1][j] = x[1];
-    P.x[2][j] = x[2];
+  template <class I>
+  __device__ void store(const Particles& P, I j) const {
+    st(P.x[0], j, x[0]);
+    st(P.x[1], j, x[1]);
+    st(P.x[2], j, x[2]);
   }
   __device__ void stream(const Box& B, const double v[3], uint32_t& err) {
 #pragma unroll
@@ -145,23 +193,23 @@ template <>
 struct Pos<1> {
   int h[3];
   float o[3];
-  __device__ void load(const Particles& P, size_t i) {
-    unpack_home(P.h[i], h[0], h[1], h[2]);
-    o[0] = P.o[0][i];
-    o[1] = P.o[1][i];
-    o[2] = P.o[2][i];
+  template <class I>
+  __device__ void load(const Particles& P, I i) {
+    unpack_home(ld(P.h, i), h[0], h[1], h[2]);
+    o[0] = ld(P.o[0], i);
+    o[1] = ld(P.o[1], i);
+    o[2] = ld(P.o[2], i);
   }
-  __device__ void store(const Particles& P, size_t j) const {
-    P.h[j] = pack_home(h[0], h[1], h[2]);
-    P.o[0][j] = o[0];
-    P.o[1][j] = o[1];
-    P.o[2][j] = o[2];
+  template <class I>
+  __device__ void store(const Particles& P, I j) const {
+    st(P.h, j, pack_home(h[0], h[1], h[2]));
+    st(P.o[0], j, o[0]);
+    st(P.o[1], j, o[1]);
+    st(P.o[2], j, o[2]);
   }
-  // v holds the velocity as stored (FP32 values)
-  __device__ void stream(const Box& B, const double v[3], uint32_t&) {
+  __device__ void stream(const Box& B, const float v[3], uint32_t&) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
-      stream_axis32(o[d], h[d], (float)v[d], B.dt32, B.a32, B.inv_a32, B.n[d]);
+    for (int d = 0; d < 3; ++d) stream_axis32(o[d], h[d], v[d], B.dt32, B.a32, B.inv_a32, B.n[d]);
   }
   __device__ void cell3(const Box& B, const double*, const float s32[3], int c[3]) const {
 #pragma unroll
@@ -184,25 +232,8 @@ __device__ inline uint32_t tile_index(const Box& B, const int c[3]) {
 }
 
 // ------------------------------------------------------- scatter helpers
-// Destination bin of a particle leaving tile t for the tile of cell c:
-// 0..26 for the 27 neighbours (periodic wrap), 27 for any other tile.
-__device__ inline uint32_t dest_bin(const Box& B, const int t[3], const int c[3]) {
-  uint32_t bin = 0, mul = 1;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const int nt = B.nt[d];
-    const int ct = tile_coord(c[d], B, d);
-    int o;
-    if (ct == t[d]) o = 1;
-    else if (ct == (t[d] + 1 == nt ? 0 : t[d] + 1)) o = 2;
-    else if (ct == (t[d] == 0 ? nt - 1 : t[d] - 1)) o = 0;
-    else return 27u;
-    bin += (uint32_t)o * mul;
-    mul *= 3u;
-  }
-  return bin;
-}
-
+// Tile at offset (bin % 3 - 1, bin / 3 % 3 - 1, bin / 9 - 1) from tile t,
+// periodic.
 __device__ inline uint32_t bin_tile(const Box& B, const int t[3], uint32_t bin) {
   int c[3];
 #pragma unroll
@@ -217,24 +248,25 @@ __device__ inline uint32_t bin_tile(const Box& B, const int t[3], uint32_t bin) 
   return (uint32_t)c[0] + (uint32_t)B.nt[0] * ((uint32_t)c[1] + (uint32_t)B.nt[1] * (uint32_t)c[2]);
 }
 
-// Rank of each active lane among the block's particles with the same bin:
-// lanes of one wave are ranked in lane order (ballot), waves take
-// consecutive ranges through one LDS atomic per (wave, bin).
-__device__ inline uint32_t wave_rank(uint32_t bin, bool active, uint32_t* s_bincnt) {
-  const uint32_t lane = threadIdx.x & 63u;
-  unsigned long long pending = __ballot(active);
-  uint32_t myrank = 0;
-  while (pending) {
-    const int leader = __ffsll((long long)pending) - 1;
-    const uint32_t b = __shfl(bin, leader);
-    const unsigned long long m = __ballot(active && bin == b);
-    uint32_t base = 0;
-    if ((int)lane == leader) base = atomicAdd(&s_bincnt[b], (uint32_t)__popcll(m));
-    base = __shfl(base, leader);
-    if (active && bin == b) myrank = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-    pending &= ~m;
+// Where a particle in cell c goes from tile t: its bin 0..26 among the 27
+// neighbour tiles (the +1 neighbour is preferred when it is also the -1
+// one, nt == 2), or 27 for any other tile; and its cell inside the
+// destination tile.
+__device__ inline uint32_t dest_bin(const Box& B, const int t[3], const int c[3], uint32_t& lcell) {
+  uint32_t bin = 0;
+  bool near = true;
+  constexpr uint32_t mul[3] = {1u, 3u, 9u};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int nt = B.nt[d];
+    const int diff = tile_coord(c[d], B, d) - t[d];
+    const uint32_t o = diff == 0 ? 1u : ((diff == 1 || diff == 1 - nt) ? 2u : ((diff == -1 || diff == nt - 1) ? 0u : 3u));
+    near = near && o != 3u;
+    bin += o * mul[d];
   }
-  return myrank;
+  lcell = ((uint32_t)c[0] & B.lm[0]) +
+          (uint32_t)B.td[0] * (((uint32_t)c[1] & B.lm[1]) + (uint32_t)B.td[1] * ((uint32_t)c[2] & B.lm[2]));
+  return near ? bin : 27u;
 }
 
 // ------------------------------------------------------------ tile kernel
@@ -258,6 +290,7 @@ struct TileArgs {
   float sn32[3];
   uint32_t* status;
   uint32_t seq;             // launch sequence number within one API call
+  const double* ehat;       // thermostat draws of this collision, [tile][CPT]
   double* d_mass;           // per-cell outputs of MODE_DIAG (global cell index)
   double* d_mom;
   double* d_ek;
@@ -265,97 +298,104 @@ struct TileArgs {
   double* d_xi;
 };
 
+// Fixed-point accumulator rows of one cell sum: the FP64 form keeps two limbs
+// (fx_split), the FP32 form one (fx1_split).
+template <int FORM>
+struct Acc {
+  static constexpr int NL = FORM == 0 ? 2 : 1;
+  __device__ static void add(unsigned long long* row0, unsigned long long* row1, double x, bool& bad) {
+    if constexpr (NL == 2) {
+      long long hi, lo;
+      fx_split(x, hi, lo, bad);
+      atomicAdd(row0, (unsigned long long)hi);
+      atomicAdd(row1, (unsigned long long)lo);
+    } else {
+      atomicAdd(row0, (unsigned long long)fx1_split(x, bad));
+    }
+  }
+  __device__ static double value(unsigned long long a0, unsigned long long a1) {
+    if constexpr (NL == 2) {
+      Fx f;
+      f.hi = (long long)a0;
+      f.lo = (long long)a1;
+      return fx_value(f);
+    } else {
+      return fx1_value((long long)a0);
+    }
+  }
+};
+
+// One block per tile. In the per-cell phases thread l < CPT works for cell
+// l: it draws the axis, forms u, xi and the rotation. The thermostat's Gamma
+// draws come from k_draw, launched just before.
 template <int FORM, int CPT, int MODE, bool STREAM_IN, bool THERMO, bool EMB>
 __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
   using VT = typename VelT<FORM>::T;
+  using AC = Acc<FORM>;
   constexpr bool COLL = MODE != MODE_BIN;
   constexpr bool SCAT = MODE == MODE_BIN || MODE == MODE_COLLIDE_SCATTER;
   constexpr bool EK = THERMO || MODE == MODE_DIAG;
-  constexpr int TPC = TT / CPT;  // threads per cell in the per-cell phase
-  // accumulator rows: 0 count, 1..6 momentum limbs, then energy, then mass
-  constexpr int IE = 7;
-  constexpr int IM = EK ? 9 : 7;
-  constexpr int NACC = COLL ? (IM + (EMB ? 2 : 0)) : 1;
+  constexpr int NL = AC::NL;
+  constexpr int RP = 0;                       // momentum rows: RP + NL * axis
+  constexpr int RE = 3 * NL;                  // relative kinetic energy
+  constexpr int RM = EK ? RE + NL : RE;       // mass (embedded particles)
+  constexpr int NROW = COLL ? RM + (EMB ? NL : 0) : 1;
   constexpr int CC = COLL ? CPT : 1;
-  __shared__ unsigned long long s_acc[NACC][CC];
+  static_assert(CPT <= 256 && (CPT & (CPT - 1)) == 0, "cells per tile: a power of two <= 256");
+  __shared__ unsigned long long s_acc[NROW][CC];
+  __shared__ uint32_t s_cnt[CC];
   __shared__ double s_u[3][CC];
   __shared__ double s_R[9][CC];
-  __shared__ double s_g[THERMO ? TPC : 1][THERMO ? CPT : 1];
-  __shared__ uint32_t s_bincnt[28];
-  __shared__ uint32_t s_base[28];
+  __shared__ uint32_t s_bincnt[27];
+  __shared__ uint32_t s_base[27];
+  __shared__ uint32_t s_btile[27];
   __shared__ uint32_t s_quit;
 
   const Box& B = A.B;
   const uint32_t tid = threadIdx.x;
-  // quit if an earlier launch of this call overflowed a slab (launches of
-  // the failing one itself run to the end, so its counts are complete)
-  if (tid == 0) s_quit = (A.status[1] != 0u && A.status[2] < A.seq) ? 1u : 0u;
-  if (tid < 28u) s_bincnt[tid] = 0u;
-  if constexpr (COLL)
-    for (uint32_t t = tid; t < (uint32_t)(NACC * CC); t += TT) (&s_acc[0][0])[t] = 0ull;
-  __syncthreads();
-  if (s_quit) return;
-
   const uint32_t T = xcd_remap(blockIdx.x, gridDim.x);
   int t3[3];
   t3[0] = (int)(T % (uint32_t)B.nt[0]);
   t3[1] = (int)((T / (uint32_t)B.nt[0]) % (uint32_t)B.nt[1]);
   t3[2] = (int)(T / ((uint32_t)B.nt[0] * (uint32_t)B.nt[1]));
-  int org[3], ext[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    org[d] = t3[d] * B.td[d];
-    ext[d] = min(B.td[d], B.n[d] - org[d]);
+
+  // quit if an earlier launch of this call overflowed a slab (launches of
+  // the failing one itself run to the end, so its counts are complete)
+  if (tid == 0) s_quit = (A.status[1] != 0u && A.status[2] < A.seq) ? 1u : 0u;
+  if (tid < 27u) {
+    s_bincnt[tid] = 0u;
+    if constexpr (SCAT) s_btile[tid] = bin_tile(B, t3, tid);
   }
+  if constexpr (COLL) {
+    for (uint32_t t = tid; t < (uint32_t)(NROW * CC); t += TT) (&s_acc[0][0])[t] = 0ull;
+    if (tid < (uint32_t)CC) s_cnt[tid] = 0u;
+  }
+  __syncthreads();
+  if (s_quit) return;
+
   const uint32_t cnt = min(A.cnt_in[T], B.cap);
   const uint32_t nreg = min(cnt, (uint32_t)TREG);
-  const size_t base_in = (size_t)T * B.cap;
+  const size_t tbase = (size_t)T * B.cap;
+  const Particles In = tile_view<FORM>(A.in, tbase);
   if (SCAT && tid == 0 && A.cnt_clear) A.cnt_clear[T] = 0u;
 
   uint32_t err = 0;
-  bool bad = false, cap = false;
+  bool bad = false;
 
   auto mass_of = [&](uint32_t tag) -> double {
     if constexpr (EMB) return tag >= B.n_solvent ? A.emb_mass[tag - B.n_solvent] : B.mass;
     else return B.mass;
   };
-  // local cell (inside this tile) of a particle binned with the input shift
-  auto local_cell = [&](const Pos<FORM>& r) -> uint32_t {
-    int c[3];
-    r.cell3(B, A.s, A.s32, c);
-    int l[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      l[d] = c[d] - org[d];
-      if (l[d] < 0 || l[d] >= ext[d]) {
-        err |= ERR_TILE;
-        l[d] = l[d] < 0 ? 0 : ext[d] - 1;
-      }
-    }
-    return (uint32_t)l[0] + (uint32_t)B.td[0] * ((uint32_t)l[1] + (uint32_t)B.td[1] * (uint32_t)l[2]);
+  // global index of local cell l, and whether the cell exists (the last
+  // tile along an axis may be partial)
+  auto cell_of = [&](uint32_t l, bool& ok) -> uint32_t {
+    const uint32_t lx = l % (uint32_t)B.td[0];
+    const uint32_t ly = (l / (uint32_t)B.td[0]) % (uint32_t)B.td[1];
+    const uint32_t lz = l / ((uint32_t)B.td[0] * (uint32_t)B.td[1]);
+    const int g[3] = {t3[0] * B.td[0] + (int)lx, t3[1] * B.td[1] + (int)ly, t3[2] * B.td[2] + (int)lz};
+    ok = l < (uint32_t)CPT && lz < (uint32_t)B.td[2] && g[0] < B.n[0] && g[1] < B.n[1] && g[2] < B.n[2];
+    return ok ? cell_index(B, g) : 0u;
   };
-  auto add2 = [&](int j, uint32_t lc, double x) {
-    long long hi, lo;
-    fx_split(x, hi, lo, bad);
-    atomicAdd(&s_acc[j][lc], (unsigned long long)hi);
-    atomicAdd(&s_acc[j + 1][lc], (unsigned long long)lo);
-  };
-  auto acc_val = [&](int j, uint32_t lc) {
-    Fx f;
-    f.hi = (long long)s_acc[j][lc];
-    f.lo = (long long)s_acc[j + 1][lc];
-    return fx_value(f);
-  };
-
-  // per-cell work is done by TPC threads per cell: cell l, sub-thread sub
-  const uint32_t l = tid / (uint32_t)TPC, sub = tid % (uint32_t)TPC;
-  int lc3[3];
-  lc3[0] = (int)(l % (uint32_t)B.td[0]);
-  lc3[1] = (int)((l / (uint32_t)B.td[0]) % (uint32_t)B.td[1]);
-  lc3[2] = (int)(l / ((uint32_t)B.td[0] * (uint32_t)B.td[1]));
-  const bool cell_ok = l < (uint32_t)CPT && lc3[0] < ext[0] && lc3[1] < ext[1] && lc3[2] < ext[2];
-  const int gc3[3] = {org[0] + lc3[0], org[1] + lc3[1], org[2] + lc3[2]};
-  const uint32_t gcell = cell_ok ? cell_index(B, gc3) : 0u;
 
   // ---- gather this tile's particles (register-resident part)
   VT v[TQ][3];
@@ -368,277 +408,312 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
     lcs[q] = 0u;
     tg[q] = 0u;
     if (k < nreg) {
-      const size_t i = base_in + k;
-      if constexpr (FORM == 0) {
-        v[q][0] = A.in.v[0][i];
-        v[q][1] = A.in.v[1][i];
-        v[q][2] = A.in.v[2][i];
-      } else {
-        v[q][0] = A.in.vf[0][i];
-        v[q][1] = A.in.vf[1][i];
-        v[q][2] = A.in.vf[2][i];
-      }
-      tg[q] = A.in.tag[i];
-      r[q].load(A.in, i);
+      load_vel<FORM>(In, k, v[q]);
+      tg[q] = ld(In.tag, k);
+      r[q].load(In, k);
+      if constexpr (COLL) lcs[q] = (uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1);
     }
   }
 
-  // the cell's rotation axis needs only (cell, step): draw it while the
-  // gathers are in flight
-  double n[3] = {0.0, 0.0, 0.0};
-  if constexpr (COLL)
-    if (sub == 0u && cell_ok) cell_axis(gcell, A.step, B.k0, B.k1, n);
+  // cell thread: the rotation axis needs only (cell, step), so it is drawn
+  // while the gathers are in flight; it waits in s_R until R is formed
+  const bool cthr = COLL && tid < (uint32_t)CPT;
+  bool cok = false;
+  const uint32_t gcell = cthr ? cell_of(tid, cok) : 0u;
+  double ehat = -1.0;
+  if constexpr (THERMO)
+    if (cthr) ehat = A.ehat[(size_t)T * CPT + tid];
+  if constexpr (COLL) {
+    if (cthr) {
+      double n[3] = {0.0, 0.0, 0.0};
+      if (cok) cell_axis(gcell, A.step, B.k0, B.k1, n);
+      s_R[0][tid] = n[0];
+      s_R[1][tid] = n[1];
+      s_R[2][tid] = n[2];
+    }
+  }
 
   // ---- scatter: bin for the destination shift, reserve slots, write
-  auto scatter = [&](const double* sd, const float* sd32, const double (*w)[3]) {
-    // w[q]: velocity to store (already rounded to the storage precision)
-    uint32_t bins[TQ], ranks[TQ], dest[TQ];
+  auto overflow = [&]() {
+    atomicMax(&A.status[1], 1u);
+    atomicMin(&A.status[2], A.seq);
+  };
+  auto put = [&](size_t j, const VT w[3], uint32_t tag, const Pos<FORM>& rr, uint32_t lcell) {
+    store_vel<FORM>(A.out, j, w);
+    st(A.out.tag, j, tag);
+    rr.store(A.out, j);
+    st(A.out.lc, j, (uint8_t)lcell);
+  };
+  auto scatter = [&](const double* sd, const float* sd32, const VT (*w)[3]) {
+    // per particle: local cell in the destination (bits 0-7), bin (8-12),
+    // rank within the bin (13-31)
+    uint32_t info[TQ];
 #pragma unroll
     for (int q = 0; q < TQ; ++q) {
       const uint32_t k = tid + (uint32_t)(q * TT);
-      const bool act = k < nreg;
-      uint32_t b = 0;
-      dest[q] = 0u;
-      if (act) {
+      info[q] = 0u;
+      if (k < nreg) {
         int c[3];
         r[q].cell3(B, sd, sd32, c);
-        b = dest_bin(B, t3, c);
-        dest[q] = b < 27u ? bin_tile(B, t3, b) : tile_index(B, c);
+        uint32_t lcell;
+        const uint32_t b = dest_bin(B, t3, c, lcell);
+        const uint32_t rank = b < 27u ? atomicAdd(&s_bincnt[b], 1u) : 0u;
+        info[q] = lcell | (b << 8) | (rank << 13);
       }
-      bins[q] = b;
-      ranks[q] = (act && b < 27u) ? atomicAdd(&s_bincnt[b], 1u) : 0u;
     }
     __syncthreads();
-    if (tid < 27u && s_bincnt[tid] > 0u)
-      s_base[tid] = atomicAdd(&A.cnt_out[bin_tile(B, t3, tid)], s_bincnt[tid]);
+    if (tid < 27u && s_bincnt[tid] > 0u) s_base[tid] = atomicAdd(&A.cnt_out[s_btile[tid]], s_bincnt[tid]);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < TQ; ++q) {
       const uint32_t k = tid + (uint32_t)(q * TT);
       if (k < nreg) {
-        const uint32_t slot = bins[q] < 27u ? s_base[bins[q]] + ranks[q]
-                                            : atomicAdd(&A.cnt_out[dest[q]], 1u);
-        if (slot < B.cap) {
-          const size_t j = (size_t)dest[q] * B.cap + slot;
-          store_vel<FORM>(A.out, j, w[q]);
-          A.out.tag[j] = tg[q];
-          r[q].store(A.out, j);
+        const uint32_t b = (info[q] >> 8) & 31u;
+        uint32_t dt, slot;
+        if (b < 27u) {
+          dt = s_btile[b];
+          slot = s_base[b] + (info[q] >> 13);
         } else {
-          atomicMax(&A.status[1], 1u);
-          atomicMin(&A.status[2], A.seq);
+          int c[3];
+          r[q].cell3(B, sd, sd32, c);
+          dt = tile_index(B, c);
+          slot = atomicAdd(&A.cnt_out[dt], 1u);
         }
+        if (slot < B.cap) put((size_t)dt * B.cap + slot, w[q], tg[q], r[q], info[q] & 255u);
+        else overflow();
       }
     }
   };
   // particles beyond the register-resident part: one global atomic each
-  auto scatter_one = [&](Pos<FORM>& rr, const double* sd, const float* sd32, const double w[3],
+  auto scatter_one = [&](const Pos<FORM>& rr, const double* sd, const float* sd32, const VT w[3],
                          uint32_t tag) {
     int c[3];
     rr.cell3(B, sd, sd32, c);
+    uint32_t lcell;
+    (void)dest_bin(B, t3, c, lcell);
     const uint32_t dt = tile_index(B, c);
     const uint32_t slot = atomicAdd(&A.cnt_out[dt], 1u);
-    if (slot < B.cap) {
-      const size_t j = (size_t)dt * B.cap + slot;
-      store_vel<FORM>(A.out, j, w);
-      A.out.tag[j] = tag;
-      rr.store(A.out, j);
-    } else {
-      atomicMax(&A.status[1], 1u);
-      atomicMin(&A.status[2], A.seq);
-    }
+    if (slot < B.cap) put((size_t)dt * B.cap + slot, w, tag, rr, lcell);
+    else overflow();
   };
 
   if constexpr (MODE == MODE_BIN) {
-    double w[TQ][3];
+    if constexpr (STREAM_IN) {
 #pragma unroll
-    for (int q = 0; q < TQ; ++q) {
-      w[q][0] = (double)v[q][0];
-      w[q][1] = (double)v[q][1];
-      w[q][2] = (double)v[q][2];
-      if (STREAM_IN && tid + (uint32_t)(q * TT) < nreg) r[q].stream(B, w[q], err);
+      for (int q = 0; q < TQ; ++q)
+        if (tid + (uint32_t)(q * TT) < nreg) r[q].stream(B, v[q], err);
     }
-    scatter(A.s, A.s32, w);
+    scatter(A.s, A.s32, v);
     for (uint32_t k = TREG + tid; k < cnt; k += TT) {
-      const size_t i = base_in + k;
-      double vv[3];
-      load_vel<FORM>(A.in, i, vv);
+      VT vv[3];
+      load_vel<FORM>(In, k, vv);
       Pos<FORM> rr;
-      rr.load(A.in, i);
+      rr.load(In, k);
       if (STREAM_IN) rr.stream(B, vv, err);
-      scatter_one(rr, A.s, A.s32, vv, A.in.tag[i]);
+      scatter_one(rr, A.s, A.s32, vv, ld(In.tag, k));
     }
   } else {
     // ---- cell sums: count, momentum (and mass) in exact fixed point
-    auto sum_mom = [&](uint32_t lc, const double vv[3], double m) {
-      atomicAdd(&s_acc[0][lc], 1ull);
-      add2(1, lc, m * vv[0]);
-      add2(3, lc, m * vv[1]);
-      add2(5, lc, m * vv[2]);
-      if constexpr (EMB) add2(IM, lc, m);
+    auto sum_mom = [&](uint32_t lc, const VT vv[3], double m) {
+      atomicAdd(&s_cnt[lc], 1u);
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        AC::add(&s_acc[RP + NL * d][lc], &s_acc[RP + NL * d + NL - 1][lc], m * (double)vv[d], bad);
+      if constexpr (EMB) AC::add(&s_acc[RM][lc], &s_acc[RM + NL - 1][lc], m, bad);
     };
 #pragma unroll
-    for (int q = 0; q < TQ; ++q) {
-      const uint32_t k = tid + (uint32_t)(q * TT);
-      if (k < nreg) {
-        lcs[q] = local_cell(r[q]);
-        const double vv[3] = {(double)v[q][0], (double)v[q][1], (double)v[q][2]};
-        sum_mom(lcs[q], vv, mass_of(tg[q]));
-      }
-    }
+    for (int q = 0; q < TQ; ++q)
+      if (tid + (uint32_t)(q * TT) < nreg) sum_mom(lcs[q], v[q], mass_of(tg[q]));
     for (uint32_t k = TREG + tid; k < cnt; k += TT) {
-      const size_t i = base_in + k;
-      double vv[3];
-      load_vel<FORM>(A.in, i, vv);
-      Pos<FORM> rr;
-      rr.load(A.in, i);
-      sum_mom(local_cell(rr), vv, mass_of(A.in.tag[i]));
+      VT vv[3];
+      load_vel<FORM>(In, k, vv);
+      sum_mom((uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1), vv, mass_of(ld(In.tag, k)));
     }
     __syncthreads();
 
-    // ---- per cell: u on sub-thread 0; Gamma attempts in parallel
-    // (attempt j on sub-thread j; the first accepted one in attempt order is
-    // the draw, exactly as when the attempts are made one after another)
-    const uint32_t nc = cell_ok ? (uint32_t)s_acc[0][l] : 0u;
-    if (nc == 0u) n[0] = n[1] = n[2] = 0.0;
-    if (sub == 0u) {
+    // ---- per cell: u (cell threads)
+    auto cell_mass = [&](uint32_t l, uint32_t nc) -> double {
+      if constexpr (EMB) return AC::value(s_acc[RM][l], s_acc[RM + NL - 1][l]);
+      else return (double)nc * B.mass;
+    };
+    const uint32_t nc = cthr && cok ? s_cnt[tid] : 0u;
+    if (cthr) {
       double u[3] = {0.0, 0.0, 0.0};
       if (nc > 0u) {
-        const double M = EMB ? acc_val(IM, l) : (double)nc * B.mass;
-        u[0] = acc_val(1, l) / M;
-        u[1] = acc_val(3, l) / M;
-        u[2] = acc_val(5, l) / M;
+        const double M = cell_mass(tid, nc);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) u[d] = AC::value(s_acc[RP + NL * d][tid], s_acc[RP + NL * d + NL - 1][tid]) / M;
       }
-      if (l < (uint32_t)CPT) {
-        s_u[0][l] = u[0];
-        s_u[1][l] = u[1];
-        s_u[2][l] = u[2];
-      }
+      s_u[0][tid] = u[0];
+      s_u[1][tid] = u[1];
+      s_u[2][tid] = u[2];
     }
-    if constexpr (THERMO) {
-      if (l < (uint32_t)CPT) {
-        double g = -1.0;  // -1: rejected or not drawn
-        if (nc >= 2u) {
-          const double k = 1.5 * (double)(nc - 1u);
-          const double d = k - 1.0 / 3.0;
-          g = gamma_attempt(gcell, A.step, sub, d, 1.0 / sqrt(9.0 * d), B.kT, B.k0, B.k1);
-        }
-        s_g[sub][l] = g;
-      }
-    }
-    __syncthreads();
 
+    double ek = 0.0;
     if constexpr (EK) {
-      auto sum_energy = [&](uint32_t lc, const double vv[3], double m) {
-        const double dx = vv[0] - s_u[0][lc], dy = vv[1] - s_u[1][lc], dz = vv[2] - s_u[2][lc];
-        add2(IE, lc, m * (dx * dx + dy * dy + dz * dz));
+      __syncthreads();
+      auto sum_energy = [&](uint32_t lc, const VT vv[3], double m) {
+        const double dx = (double)vv[0] - s_u[0][lc], dy = (double)vv[1] - s_u[1][lc],
+                     dz = (double)vv[2] - s_u[2][lc];
+        AC::add(&s_acc[RE][lc], &s_acc[RE + NL - 1][lc], m * (dx * dx + dy * dy + dz * dz), bad);
       };
 #pragma unroll
-      for (int q = 0; q < TQ; ++q) {
-        const uint32_t k = tid + (uint32_t)(q * TT);
-        if (k < nreg) {
-          const double vv[3] = {(double)v[q][0], (double)v[q][1], (double)v[q][2]};
-          sum_energy(lcs[q], vv, mass_of(tg[q]));
-        }
-      }
+      for (int q = 0; q < TQ; ++q)
+        if (tid + (uint32_t)(q * TT) < nreg) sum_energy(lcs[q], v[q], mass_of(tg[q]));
       for (uint32_t k = TREG + tid; k < cnt; k += TT) {
-        const size_t i = base_in + k;
-        double vv[3];
-        load_vel<FORM>(A.in, i, vv);
-        Pos<FORM> rr;
-        rr.load(A.in, i);
-        sum_energy(local_cell(rr), vv, mass_of(A.in.tag[i]));
+        VT vv[3];
+        load_vel<FORM>(In, k, vv);
+        sum_energy((uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1), vv, mass_of(ld(In.tag, k)));
       }
       __syncthreads();
+      if (cthr) ek = 0.5 * AC::value(s_acc[RE][tid], s_acc[RE + NL - 1][tid]);
     }
 
-    // ---- per cell: xi and the scaled rotation matrix (sub-thread 0)
-    if (sub == 0u && l < (uint32_t)CPT) {
+    // ---- per cell: xi and the scaled rotation matrix (cell threads)
+    if (cthr) {
       double xi = 1.0;
-      double ek = 0.0;
-      if constexpr (EK) ek = 0.5 * acc_val(IE, l);
-      if constexpr (THERMO) {
-        if (nc >= 2u && ek > 0.0) {
-          double ehat = -1.0;
-          for (uint32_t j = 0; j < (uint32_t)TPC && ehat < 0.0; ++j) ehat = s_g[j][l];
-          if (ehat < 0.0)  // every speculative attempt was rejected
-            ehat = gamma_mt(1.5 * (double)(nc - 1u), gcell, A.step, B.k0, B.k1, B.kT, cap, TPC);
-          xi = sqrt(ehat / ek);
-        }
-      }
+      if constexpr (THERMO)
+        if (nc >= 2u && ek > 0.0) xi = sqrt(ehat / ek);
+      const double n[3] = {nc > 0u ? s_R[0][tid] : 0.0, nc > 0u ? s_R[1][tid] : 0.0,
+                           nc > 0u ? s_R[2][tid] : 0.0};
       if constexpr (MODE == MODE_DIAG) {
-        if (cell_ok) {
-          A.d_mass[gcell] = nc > 0u ? (EMB ? acc_val(IM, l) : (double)nc * B.mass) : 0.0;
-          A.d_mom[3u * gcell] = acc_val(1, l);
-          A.d_mom[3u * gcell + 1u] = acc_val(3, l);
-          A.d_mom[3u * gcell + 2u] = acc_val(5, l);
+        if (cok) {
+          A.d_mass[gcell] = nc > 0u ? cell_mass(tid, nc) : 0.0;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            A.d_mom[3u * gcell + d] = AC::value(s_acc[RP + NL * d][tid], s_acc[RP + NL * d + NL - 1][tid]);
+            A.d_axis[3u * gcell + d] = n[d];
+          }
           A.d_ek[gcell] = ek;
-          A.d_axis[3u * gcell] = n[0];
-          A.d_axis[3u * gcell + 1u] = n[1];
-          A.d_axis[3u * gcell + 2u] = n[2];
           A.d_xi[gcell] = xi;
         }
       } else {
         double R[9];
         rotation_matrix(n, B.ca, B.sa, B.omc, xi, R);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) s_R[q][l] = R[q];
+        for (int q = 0; q < 9; ++q) s_R[q][tid] = R[q];
       }
     }
 
     if constexpr (MODE != MODE_DIAG) {
       __syncthreads();
-      // ---- rotate (Alg. 1): v <- u + xi R (v - u), FP64 registers
-      auto rotate = [&](uint32_t lc, const double vv[3], double w[3]) {
+      // ---- rotate (Alg. 1): v <- u + xi R (v - u) in FP64, rounded once to
+      // the storage precision
+      auto rotate = [&](uint32_t lc, const VT vv[3], VT w[3]) {
         const double ux = s_u[0][lc], uy = s_u[1][lc], uz = s_u[2][lc];
-        const double dx = vv[0] - ux, dy = vv[1] - uy, dz = vv[2] - uz;
-        w[0] = ux + (s_R[0][lc] * dx + s_R[1][lc] * dy + s_R[2][lc] * dz);
-        w[1] = uy + (s_R[3][lc] * dx + s_R[4][lc] * dy + s_R[5][lc] * dz);
-        w[2] = uz + (s_R[6][lc] * dx + s_R[7][lc] * dy + s_R[8][lc] * dz);
-        if constexpr (FORM == 1) {
-          w[0] = (double)(float)w[0];
-          w[1] = (double)(float)w[1];
-          w[2] = (double)(float)w[2];
-        }
+        const double dx = (double)vv[0] - ux, dy = (double)vv[1] - uy, dz = (double)vv[2] - uz;
+        w[0] = (VT)(ux + (s_R[0][lc] * dx + s_R[1][lc] * dy + s_R[2][lc] * dz));
+        w[1] = (VT)(uy + (s_R[3][lc] * dx + s_R[4][lc] * dy + s_R[5][lc] * dz));
+        w[2] = (VT)(uz + (s_R[6][lc] * dx + s_R[7][lc] * dy + s_R[8][lc] * dz));
       };
-      double w[TQ][3];
 #pragma unroll
       for (int q = 0; q < TQ; ++q) {
         const uint32_t k = tid + (uint32_t)(q * TT);
         if (k < nreg) {
-          const double vv[3] = {(double)v[q][0], (double)v[q][1], (double)v[q][2]};
-          rotate(lcs[q], vv, w[q]);
+          VT w[3];
+          rotate(lcs[q], v[q], w);
+          v[q][0] = w[0];
+          v[q][1] = w[1];
+          v[q][2] = w[2];
           if constexpr (MODE == MODE_COLLIDE) {
-            const size_t j = base_in + k;
-            store_vel<FORM>(A.out, j, w[q]);
-            A.out.tag[j] = tg[q];
-            r[q].store(A.out, j);
+            const Particles Out = tile_view<FORM>(A.out, tbase);
+            store_vel<FORM>(Out, k, v[q]);
+            st(Out.tag, k, tg[q]);
+            r[q].store(Out, k);
+            st(Out.lc, k, (uint8_t)lcs[q]);
           } else {
-            r[q].stream(B, w[q], err);
+            r[q].stream(B, v[q], err);
           }
         }
       }
-      if constexpr (MODE == MODE_COLLIDE_SCATTER) scatter(A.sn, A.sn32, w);
+      if constexpr (MODE == MODE_COLLIDE_SCATTER) scatter(A.sn, A.sn32, v);
       for (uint32_t k = TREG + tid; k < cnt; k += TT) {
-        const size_t i = base_in + k;
-        double vv[3], ww[3];
-        load_vel<FORM>(A.in, i, vv);
+        VT vv[3], ww[3];
+        load_vel<FORM>(In, k, vv);
         Pos<FORM> rr;
-        rr.load(A.in, i);
-        rotate(local_cell(rr), vv, ww);
+        rr.load(In, k);
+        const uint32_t lc = (uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1);
+        rotate(lc, vv, ww);
         if constexpr (MODE == MODE_COLLIDE) {
-          store_vel<FORM>(A.out, i, ww);
-          A.out.tag[i] = A.in.tag[i];
-          rr.store(A.out, i);
+          const Particles Out = tile_view<FORM>(A.out, tbase);
+          store_vel<FORM>(Out, k, ww);
+          st(Out.tag, k, ld(In.tag, k));
+          rr.store(Out, k);
+          st(Out.lc, k, (uint8_t)lc);
         } else {
           rr.stream(B, ww, err);
-          scatter_one(rr, A.sn, A.sn32, ww, A.in.tag[i]);
+          scatter_one(rr, A.sn, A.sn32, ww, ld(In.tag, k));
         }
       }
     }
   }
   if (bad) err |= ERR_FIXED_RANGE;
-  if (cap) err |= ERR_GAMMA_CAP;
   if (err) atomicOr(&A.status[0], err);
+}
+
+// Maxwell-Boltzmann draws of one collision (sec. 3.6), one block per tile:
+// the occupancy N_c of each of the tile's cells from the local-cell bytes of
+// its slab, then E_hat ~ Gamma(3 (N_c - 1) / 2, kT) for every cell with
+// N_c >= 2. Attempts 0 .. NGD-1 of a cell run in parallel on NGD threads and
+// the first accepted one in attempt order is the draw (the sequential
+// sampler's result); if all are rejected, the sampler continues in order.
+// Output ehat[T * CPT + l] (-1 for a cell with fewer than two particles).
+template <int CPT>
+struct DrawShape {
+  static constexpr int NGD = CPT >= 256 ? 1 : 2;
+  static constexpr int THREADS = NGD * CPT;
+};
+
+template <int CPT>
+__global__ __launch_bounds__(DrawShape<CPT>::THREADS) void k_draw(
+    Particles P, Box B, const uint32_t* __restrict__ cnt_in, uint32_t step,
+    double* __restrict__ ehat, uint32_t* status, uint32_t seq) {
+  constexpr int NGD = DrawShape<CPT>::NGD;
+  constexpr int DT = DrawShape<CPT>::THREADS;
+  __shared__ uint32_t s_n[CPT];
+  __shared__ double s_e[NGD][CPT];
+  __shared__ uint32_t s_quit;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t T = xcd_remap(blockIdx.x, gridDim.x);
+  if (tid == 0) s_quit = (status[1] != 0u && status[2] < seq) ? 1u : 0u;
+  for (uint32_t t = tid; t < (uint32_t)CPT; t += DT) s_n[t] = 0u;
+  __syncthreads();
+  if (s_quit) return;
+  const uint32_t cnt = min(cnt_in[T], B.cap);
+  const uint8_t* lc = P.lc + (size_t)T * B.cap;
+  for (uint32_t k = tid; k < cnt; k += DT) atomicAdd(&s_n[(uint32_t)ld(lc, k) & (uint32_t)(CPT - 1)], 1u);
+  __syncthreads();
+
+  const uint32_t l = tid % (uint32_t)CPT, j = tid / (uint32_t)CPT;
+  int t3[3];
+  t3[0] = (int)(T % (uint32_t)B.nt[0]);
+  t3[1] = (int)((T / (uint32_t)B.nt[0]) % (uint32_t)B.nt[1]);
+  t3[2] = (int)(T / ((uint32_t)B.nt[0] * (uint32_t)B.nt[1]));
+  const uint32_t lx = l % (uint32_t)B.td[0];
+  const uint32_t ly = (l / (uint32_t)B.td[0]) % (uint32_t)B.td[1];
+  const uint32_t lz = l / ((uint32_t)B.td[0] * (uint32_t)B.td[1]);
+  const int g[3] = {t3[0] * B.td[0] + (int)lx, t3[1] * B.td[1] + (int)ly, t3[2] * B.td[2] + (int)lz};
+  const bool ok = lz < (uint32_t)B.td[2] && g[0] < B.n[0] && g[1] < B.n[1] && g[2] < B.n[2];
+  const uint32_t gc = ok ? cell_index(B, g) : 0u;
+  const uint32_t nc = ok ? s_n[l] : 0u;
+  const double k = 1.5 * (double)(nc - 1u);
+  const double d = k - 1.0 / 3.0;
+  double e = -1.0;  // -1: rejected or not drawn
+  if (nc >= 2u) e = gamma_attempt(gc, step, j, d, 1.0 / sqrt(9.0 * d), B.kT, B.k0, B.k1);
+  s_e[j][l] = e;
+  __syncthreads();
+  if (j == 0u) {
+    bool cap = false;
+    double r = -1.0;
+    if (nc >= 2u) {
+#pragma unroll
+      for (int a = 0; a < NGD; ++a)
+        if (r < 0.0) r = s_e[a][l];
+      if (r < 0.0) r = gamma_mt(k, gc, step, B.k0, B.k1, B.kT, cap, NGD);
+    }
+    ehat[(size_t)T * CPT + l] = r;
+    if (cap) atomicOr(&status[0], ERR_GAMMA_CAP);
+  }
 }
 
 // ------------------------------------------------- elementwise over slabs
@@ -663,7 +738,7 @@ __global__ __launch_bounds__(256) void k_stream(Particles P, Box B, const uint32
                                                 uint32_t* status) {
   const SlabIter s = slab_slot(B, cnt);
   if (!s.valid) return;
-  double v[3];
+  typename VelT<FORM>::T v[3];
   load_vel<FORM>(P, s.i, v);
   Pos<FORM> r;
   r.load(P, s.i);
@@ -703,8 +778,9 @@ __global__ __launch_bounds__(256) void k_totals(Particles P, Box B, const uint32
   bool bad = false;
   const SlabIter s = slab_slot(B, cnt);
   if (s.valid) {
-    double v[3];
-    load_vel<FORM>(P, s.i, v);
+    typename VelT<FORM>::T vs[3];
+    load_vel<FORM>(P, s.i, vs);
+    const double v[3] = {(double)vs[0], (double)vs[1], (double)vs[2]};
     double m = B.mass;
     if constexpr (EMB) {
       const uint32_t tg = P.tag[s.i];
@@ -757,7 +833,8 @@ __global__ __launch_bounds__(256) void k_import(Particles P, Box B,
     return;
   }
   Pos<FORM> r;
-  const double w[3] = {v[0], v[1], v[2]};
+  using VT = typename VelT<FORM>::T;
+  const VT w[3] = {(VT)v[0], (VT)v[1], (VT)v[2]};
   if constexpr (FORM == 0) {
     r.x[0] = x[0];
     r.x[1] = x[1];
@@ -828,13 +905,14 @@ __global__ __launch_bounds__(256) void k_repack(Particles src, Particles dst, Bo
   const uint32_t k = (blockIdx.x % per) * 256u + threadIdx.x;
   if (T >= B.ntiles || k >= min(cnt[T], old_cap)) return;
   const size_t i = (size_t)T * old_cap + k, j = (size_t)T * B.cap + k;
-  double v[3];
+  typename VelT<FORM>::T v[3];
   load_vel<FORM>(src, i, v);
   store_vel<FORM>(dst, j, v);
   Pos<FORM> r;
   r.load(src, i);
   r.store(dst, j);
   dst.tag[j] = src.tag[i];
+  dst.lc[j] = src.lc[i];
 }
 
 // --------------------------------------------------------- test kernels

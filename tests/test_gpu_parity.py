@@ -93,28 +93,48 @@ def test_stream_and_bin_bitexact(n_cells, rho, a):
         assert np.array_equal(counts, np.bincount(ocells, minlength=p.ncells))
 
 
-def test_cell_props_and_draws():
-    banner("cell props and draws")
-    p = srd.Params((9, 8, 7), seed=11, thermostat=True, kT=1.3)
-    pos, vel = workloads.fluid(p.n_cells, 7, seed=5, kT=0.7)
+@pytest.mark.parametrize("form,n_cells,rho", [
+    ("fp64", (9, 8, 7), 7), ("fp64", (3, 9, 10), 7), ("fp64", (5, 6, 9), 4),
+    ("fp32", (9, 8, 7), 7), ("fp32", (3, 9, 10), 4)])
+def test_cell_props_and_draws(form, n_cells, rho):
+    """Per-cell mass, momentum, relative kinetic energy, axis and thermostat
+    factor after stream + bin. Boxes with an axis shorter than a tile and
+    partial tiles at the far faces included. FP64 form: exact sums, so the
+    mass is bit-exact; FP32 form: each term of the momentum and energy sums
+    is rounded to 2^-40 (one-limb fixed point), so the cell sums are within
+    N_c 2^-41 of the exact ones."""
+    banner(f"cell props and draws {form} {n_cells} rho={rho}")
+    p = srd.Params(n_cells, seed=11, thermostat=True, kT=1.3)
+    pos, vel = workloads.fluid(p.n_cells, rho, seed=5, kT=0.7)
     mass = np.ones(pos.shape[0])
-    with _sim(pos, vel, p) as s:
+    prec = m.FP64 if form == "fp64" else m.FP32
+    with _sim(pos, vel, p, precision=prec) as s:
         s.stream()
         s.bin()
         gm, gP, gek = s.get_cell_props()
         gax, gxi = s.get_cell_draws()
-    opos = srd.stream(pos, vel, p)
-    cell = srd.bin_cells(opos, srd.grid_shift(p, 0), p)
-    count, M, P, u, ek = srd.cell_sums(cell, vel, mass, p.ncells)
+    if form == "fp64":
+        opos = srd.stream(pos, vel, p)
+        cell = srd.bin_cells(opos, srd.grid_shift(p, 0), p)
+        v64 = vel
+        ptol = 1e-13
+    else:
+        h, o, v = fp32form.from_double(pos, vel, p)
+        h, o = fp32form.stream32(h, o, v, p)
+        cell = fp32form.bin32(h, o, srd.grid_shift(p, 0), p)
+        v64 = v.astype(np.float64)
+    count, M, P, u, ek = srd.cell_sums(cell, v64, mass, p.ncells)
     assert np.array_equal(gm, M)
-    assert np.max(np.abs(gP - P)) < 1e-13
-    assert np.allclose(gek, ek, rtol=1e-12, atol=1e-14)
+    if form == "fp32":
+        ptol = count.max() * 2.0 ** -41 + 1e-13
+    assert np.max(np.abs(gP - P)) < ptol
+    assert np.allclose(gek, ek, rtol=1e-12 if form == "fp64" else 1e-9, atol=1e-14)
     occ = count > 0
     ax = srd.cell_axes(np.arange(p.ncells), 0, p)
     assert np.max(np.abs(gax[occ] - ax[occ])) < 1e-15
     assert np.all(gax[~occ] == 0.0)
     xi = srd.thermostat_xi(count, ek, np.arange(p.ncells, dtype=np.uint64), 0, p)
-    assert np.allclose(gxi, xi, rtol=1e-12, atol=0)
+    assert np.allclose(gxi, xi, rtol=1e-12 if form == "fp64" else 1e-9, atol=0)
 
 
 # ------------------------------------------------------------ collisions
