@@ -2,12 +2,18 @@
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 
-Workload: the 100^3-cell fluid at 10 particles per cell (10^7 particles),
-alpha = 130 deg, dt = 0.1, kT = 1, random grid shift, Maxwell-Boltzmann
-cell thermostat, synthetic positions/velocities (seed 1). The headline value
-is the FP32 cell-relative form; the plain FP64 form runs on the same input
-and is reported beside it. A step is one whole pass of the hot path: stream,
-grid shift, binning (count sort), cell reduction, draws and rotation.
+Workload (default): the 100^3-cell fluid at 10 particles per cell (10^7
+particles), alpha = 130 deg, dt = 0.1, kT = 1, random grid shift,
+Maxwell-Boltzmann cell thermostat, synthetic positions/velocities (seed 1).
+The headline value is the FP32 cell-relative form; the plain FP64 form runs on
+the same input and is reported beside it. A step is one whole pass of the hot
+path: stream, grid shift, binning, cell reduction, draws and rotation.
+
+    python bench.py --workload srd_400c_rho5_beads
+
+times the largest single-GPU machine instead: 400^3 cells at 5 particles per cell
+(3.2 x 10^8) plus 20 000 chains of 50 mass-5 beads, FP32, no thermostat, 200
+steps.
 
 Prints one JSON line. `roofline` is for the dominant kernel (the collide
 kernel), timed with HIP events on the library's own stream during the timed
@@ -45,7 +51,7 @@ def floor_bytes_per_update(form, rho):
     return 2 * STATE_BYTES[form] + 8.0 / rho
 
 
-def measured_traffic(form):
+def measured_traffic(form, workload=WORKLOAD):
     """HBM bytes per launch of the step kernel from the rocprofv3 FETCH_SIZE
     / WRITE_SIZE runs recorded in profiles/traffic.json, scaled by the copy
     calibration stated there; None unless they were taken on the current
@@ -58,18 +64,21 @@ def measured_traffic(form):
         return None
     if rec.get("source_hash") != source_hash():
         return None
-    return rec.get("bytes_per_launch", {}).get(WORKLOAD, {}).get(form)
+    return rec.get("bytes_per_launch", {}).get(workload, {}).get(form)
 
 
-def run_form(m, pos, vel, cfg, precision, steps, warmup):
+def run_form(m, inp, cfg, precision, steps, warmup):
     import torch
+    pos, vel, bpos, bvel, bmass = inp
     sim = m.Sim(pos, vel, cfg["n_cells"], kT=cfg["kT"], seed=cfg["seed"],
-                precision=precision, thermostat=cfg["thermostat"])
+                precision=precision, thermostat=cfg["thermostat"],
+                emb_pos=bpos, emb_vel=bvel, emb_mass=bmass)
     try:
         sim.step(warmup)
         sim.sync()
         sim.profile(True)
-        sim.profile_read(0)
+        for w in (0, 1, 2):
+            sim.profile_read(w)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sim.step(steps)
@@ -77,12 +86,29 @@ def run_form(m, pos, vel, cfg, precision, steps, warmup):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         coll_ms, coll_n = sim.profile_read(0)
+        draw_ms, draw_n = sim.profile_read(2)
         sim.profile(False)
         P, ke, kT = sim.totals()
     finally:
         sim.close()
     return dict(seconds=t1 - t0, collide_ms=coll_ms, collide_launches=coll_n,
+                draw_us=1e3 * draw_ms / max(draw_n, 1),
                 net_momentum=float(np.abs(P).max()), kT=kT)
+
+
+def make_input(cfg, scale=None):
+    """Fluid (and beads, if the workload has them) of the workload's recipe;
+    `scale` shrinks the box edge to `scale` cells for a CPU sample."""
+    import workloads
+    n_cells = cfg["n_cells"] if scale is None else (scale, scale, scale)
+    pos, vel = workloads.fluid(n_cells, cfg["density"], kT=cfg["kT"], seed=cfg["seed"])
+    bpos = bvel = bmass = None
+    if cfg.get("chains"):
+        frac = np.prod(n_cells) / np.prod(cfg["n_cells"])
+        chains = max(1, int(round(cfg["chains"] * frac)))
+        bpos, bvel, bmass = workloads.beads(n_cells, chains, cfg["chain_len"], kT=cfg["kT"],
+                                            mass=cfg["bead_mass"], seed=cfg["seed"] + 1)
+    return pos, vel, bpos, bvel, bmass
 
 
 def copy_ceiling(m, nbytes=1 << 30, reps=20):
@@ -108,18 +134,21 @@ def copy_ceiling(m, nbytes=1 << 30, reps=20):
     return 2.0 * nbytes / sec / 1e9
 
 
-def cpu_baseline(pos, vel, cfg, nsteps):
+def cpu_baseline(inp, n_cells, cfg, nsteps, what):
     from oracle import srd
-    p = srd.Params(cfg["n_cells"], seed=cfg["seed"], thermostat=cfg["thermostat"],
-                   kT=cfg["kT"])
+    pos, vel, bpos, bvel, bmass = inp
+    p = srd.Params(n_cells, seed=cfg["seed"], thermostat=cfg["thermostat"], kT=cfg["kT"])
     mass = np.ones(pos.shape[0])
+    if bpos is not None:
+        pos, vel = np.concatenate([pos, bpos]), np.concatenate([vel, bvel])
+        mass = np.concatenate([mass, bmass])
     t0 = time.perf_counter()
     srd.run(pos, vel, mass, p, 0, nsteps)
     dt = time.perf_counter() - t0
     return dict(value=pos.shape[0] * nsteps / dt, unit="particle-updates/s", cores=1,
                 kind="oracle",
-                sample=f"{nsteps} FP64 oracle steps of the full {pos.shape[0]}-particle "
-                       f"workload ({dt:.1f} s, numpy, single thread)")
+                sample=f"{nsteps} FP64 oracle steps of {what} ({pos.shape[0]} particles, "
+                       f"{dt:.1f} s, numpy, single thread)")
 
 
 def main():
@@ -129,7 +158,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="fp32,fp64")
+    ap.add_argument("--forms", default=None,
+                    help="storage forms to time (default fp32,fp64; fp32 for the large box)")
+    ap.add_argument("--workload", default=WORKLOAD,
+                    choices=["srd_100c_rho10_mbthermo", "srd_400c_rho5_beads"])
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the streaming copy kernel (1 GiB, 20 times)")
     args = ap.parse_args()
@@ -146,17 +178,21 @@ def main():
         torch.cuda.init()
         print(json.dumps({"copy_GBs": copy_ceiling(m)}), flush=True)
         return
-    cfg = workloads.CONFIGS[WORKLOAD]
-    pos, vel = workloads.fluid(cfg["n_cells"], cfg["density"], kT=cfg["kT"],
-                               seed=cfg["seed"])
-    N = pos.shape[0]
+    wl = args.workload
+    cfg = workloads.CONFIGS[wl]
+    big = wl != WORKLOAD
+    if big and args.steps == 1000:
+        args.steps = cfg["steps"]
+    inp = make_input(cfg)
+    N = inp[0].shape[0] + (0 if inp[2] is None else inp[2].shape[0])
     rho = cfg["density"]
     torch.cuda.init()
-    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    forms = [f.strip() for f in (args.forms or ("fp32" if big else "fp32,fp64")).split(",")
+             if f.strip()]
     res = {}
     for form in forms:
         prec = m.FP32 if form == "fp32" else m.FP64
-        r = run_form(m, pos, vel, cfg, prec, args.steps, args.warmup)
+        r = run_form(m, inp, cfg, prec, args.steps, args.warmup)
         r["updates_per_s"] = N * args.steps / r["seconds"]
         r["ms_per_step"] = 1e3 * r["seconds"] / args.steps
         avg_us = 1e3 * r["collide_ms"] / max(r["collide_launches"], 1)
@@ -167,7 +203,8 @@ def main():
         res[form] = r
         print(f"[bench] {form}: {r['updates_per_s']:.4g} updates/s, "
               f"{r['ms_per_step']:.4f} ms/step, collide {avg_us:.1f} us "
-              f"({r['collide_GBs']:.0f} GB/s)", file=sys.stderr, flush=True)
+              f"({r['collide_GBs']:.0f} GB/s), draws {r['draw_us']:.1f} us",
+              file=sys.stderr, flush=True)
 
     head = res.get("fp32") or res[forms[0]]
     head_form = "fp32" if "fp32" in res else forms[0]
@@ -184,9 +221,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if head_form == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "n_cells": list(cfg["n_cells"]),
+        "config": {"workload": wl, "n_cells": list(cfg["n_cells"]),
                    "particles": N, "density": rho, "alpha_deg": 130, "dt": 0.1,
-                   "kT": cfg["kT"], "thermostat": "maxwell-boltzmann",
+                   "kT": cfg["kT"],
+                   "thermostat": "maxwell-boltzmann" if cfg["thermostat"] else "none",
+                   "embedded_beads": 0 if inp[2] is None else int(inp[2].shape[0]),
                    "grid_shift": True, "form": head_form},
         "roofline": {
             "bound": "hbm",
@@ -194,7 +233,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": head["collide_GBs"] / HBM_PEAK_GBS,
-            "traffic": measured_traffic(head_form),
+            "traffic": measured_traffic(head_form, wl),
             "kernel": "k_tile (collide + stream + bin + scatter)",
             "kernel_avg_us": head["collide_avg_us"],
             "bytes_per_particle": collide_bytes_per_particle(head_form, rho),
@@ -202,6 +241,7 @@ def main():
         "step_floor_frac": head["step_floor_frac"],
         "forms": {f: {"updates_per_s": r["updates_per_s"], "ms_per_step": r["ms_per_step"],
                       "collide_avg_us": r["collide_avg_us"], "collide_GBs": r["collide_GBs"],
+                      "draw_avg_us": r["draw_us"],
                       "step_floor_frac": r["step_floor_frac"], "kT_end": r["kT"],
                       "net_momentum_end": r["net_momentum"]} for f, r in res.items()},
     }
@@ -210,7 +250,13 @@ def main():
     if "fp32" in res and "fp64" in res:
         out["fp32_over_fp64"] = res["fp32"]["updates_per_s"] / res["fp64"]["updates_per_s"]
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(pos, vel, cfg, args.cpu_steps)
+        if big:
+            out["cpu_baseline"] = cpu_baseline(make_input(cfg, scale=60), (60, 60, 60), cfg,
+                                               args.cpu_steps,
+                                               "a 60^3-cell sample box of the same recipe")
+        else:
+            out["cpu_baseline"] = cpu_baseline(inp, cfg["n_cells"], cfg, args.cpu_steps,
+                                               "the full workload")
     print(json.dumps(out), flush=True)
 
 

@@ -87,8 +87,9 @@ struct mpcd_ctx_s {
   uint32_t* cnt[3] = {nullptr, nullptr, nullptr};
   int ci = 0;                      // cnt[ci] describes buf[cur]
   double* emb_mass = nullptr;
-  uint32_t* status = nullptr;      // [0] errors, [1] overflow, [2] failing launch
+  uint32_t* status = nullptr;      // [0] errors, [1] overflow, [2] failing launch, [4] draw queue
   double* ehat = nullptr;          // thermostat draws of the next collision, [tile][cpt]
+  uint32_t* dqueue = nullptr;      // cells whose draw needs more than the quick test
   long long* tot = nullptr;
 
   uint64_t step = 0;
@@ -226,8 +227,11 @@ TileArgs tile_args(mpcd_ctx c) {
 
 template <int CPT>
 void draw_inst(mpcd_ctx c, uint64_t n, uint32_t seq) {
-  k_draw<CPT><<<c->box.ntiles, DrawShape<CPT>::THREADS, 0, c->stream>>>(
-      c->buf[c->cur], c->box, c->cnt[c->ci], (uint32_t)n, c->ehat, c->status, seq);
+  constexpr uint32_t tpb = DT / CPT;
+  k_draw<CPT><<<(c->box.ntiles + tpb - 1) / tpb, DT, 0, c->stream>>>(
+      c->buf[c->cur], c->box, c->cnt[c->ci], (uint32_t)n, c->ehat, c->dqueue, c->status, seq);
+  k_draw_rest<<<blocks_for((uint64_t)c->box.ntiles * CPT, 256), 256, 0, c->stream>>>(
+      c->box, (uint32_t)n, c->ehat, c->dqueue, c->status, seq);
 }
 
 // Thermostat draws for the collision of step n on the current slabs.
@@ -401,12 +405,16 @@ mpcd_status validate(const mpcd_params* p, int64_t ns, int64_t ne) {
   return MPCD_OK;
 }
 
-// Tile shape: about 640 particles per tile at the system's mean density.
+// Tile shape: about 350-770 particles per tile at the system's mean density
+// (the kernels hold up to 768 particles of a 64-cell tile and 1024 of a
+// larger one in registers).
 void choose_tiles(mpcd_ctx c) {
   Box& B = c->box;
   const double rho = B.ncells ? (double)c->N / (double)B.ncells : 0.0;
   int td[3];
-  if (rho >= 7.0) {
+  if (rho >= 11.0) {
+    td[0] = 4; td[1] = 4; td[2] = 2; c->cpt = 64;
+  } else if (rho >= 7.0) {
     td[0] = 4; td[1] = 4; td[2] = 4; c->cpt = 64;
   } else if (rho >= 3.5) {
     td[0] = 8; td[1] = 4; td[2] = 4; c->cpt = 128;
@@ -430,6 +438,10 @@ void choose_tiles(mpcd_ctx c) {
     }
     B.ntiles *= (uint32_t)B.nt[d];
   }
+  B.m_td0 = (uint32_t)(((1u << 24) + B.td[0] - 1) / B.td[0]);
+  B.m_td01 = (uint32_t)(((1u << 24) + B.td[0] * B.td[1] - 1) / (B.td[0] * B.td[1]));
+  B.inv_nt0 = 1.0 / (double)B.nt[0];
+  B.inv_nt01 = 1.0 / ((double)B.nt[0] * (double)B.nt[1]);
 }
 
 }  // namespace
@@ -506,17 +518,18 @@ mpcd_status mpcd_create(const mpcd_params* params, int64_t n_solvent, const doub
   c->emb_mass = (double*)c->dalloc((size_t)c->n_emb * 8);
   if (params->thermostat) {
     c->ehat = (double*)c->dalloc(NT * (size_t)c->cpt * 8);
-    if (!c->ehat) return cleanup(fail(MPCD_ENOMEM, "device allocation failed"));
+    c->dqueue = (uint32_t*)c->dalloc(NT * (size_t)c->cpt * 12);
+    if (!c->ehat || !c->dqueue) return cleanup(fail(MPCD_ENOMEM, "device allocation failed"));
   }
   uint32_t* bad = (uint32_t*)c->dalloc(256);
   if (!c->cnt[0] || !c->cnt[1] || !c->cnt[2] || !c->status || !c->tot || !c->emb_mass || !bad)
     return cleanup(fail(MPCD_ENOMEM, "device allocation failed"));
-  const uint32_t st_init[3] = {0u, 0u, 0xFFFFFFFFu};
+  const uint32_t st_init[8] = {0u, 0u, 0xFFFFFFFFu, 0u, 0u, 0u, 0u, 0u};
   if (hipMemsetAsync(c->cnt[0], 0, NT * 4, c->stream) != hipSuccess ||
       hipMemsetAsync(c->cnt[1], 0, NT * 4, c->stream) != hipSuccess ||
       hipMemsetAsync(c->cnt[2], 0, NT * 4, c->stream) != hipSuccess ||
       hipMemsetAsync(bad, 0, 256, c->stream) != hipSuccess ||
-      hipMemcpyAsync(c->status, st_init, 12, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+      hipMemcpyAsync(c->status, st_init, sizeof st_init, hipMemcpyHostToDevice, c->stream) != hipSuccess)
     return cleanup(fail(MPCD_EHIP, "hipMemset failed"));
 
   // upload: host arrays are staged through temporary device buffers

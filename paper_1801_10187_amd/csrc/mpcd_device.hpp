@@ -199,18 +199,37 @@ __device__ inline void cell_axis(uint32_t cell, uint32_t step, uint32_t k0,
 // the uniform U. With t = 1 + c g > 0 and V = t^3, accept if
 // U < 1 - 0.0331 g^4 (squeeze) or log U < g^2/2 + d - d V + d log V.
 // Returns d V theta, or -1 when the attempt is rejected.
+// The attempt in two parts. gamma_quick draws the attempt's numbers and
+// decides what needs no logarithm of U: returns GQ_ACCEPT (squeeze),
+// GQ_REJECT (t <= 0), or GQ_FULL with g, V, U kept for gamma_full, the full
+// test. Splitting lets a kernel run the full test only for the few attempts
+// that reach it.
+enum { GQ_ACCEPT = 0, GQ_REJECT = 1, GQ_FULL = 2 };
+
+__device__ inline int gamma_quick(uint32_t cell, uint32_t step, uint32_t j, double c,
+                                  uint32_t k0, uint32_t k1, double& g, double& V,
+                                  double& u2) {
+  const U4 w = philox4x32_10(U4{cell, step, TAG_THERMO, j}, k0, k1);
+  const double u0 = u01(w.x), u1 = u01(w.y);
+  u2 = u01(w.z);
+  g = sqrt(-2.0 * log(u0)) * cospi(2.0 * u1);
+  const double t = 1.0 + c * g;
+  V = t * t * t;
+  if (t <= 0.0) return GQ_REJECT;
+  const double sq = g * g;
+  return u2 < 1.0 - 0.0331 * (sq * sq) ? GQ_ACCEPT : GQ_FULL;
+}
+
+__device__ inline bool gamma_full(double g, double V, double u2, double d) {
+  return log(u2) < 0.5 * g * g + d - d * V + d * log(V);
+}
+
 __device__ inline double gamma_attempt(uint32_t cell, uint32_t step, uint32_t j,
                                        double d, double c, double theta,
                                        uint32_t k0, uint32_t k1) {
-  const U4 w = philox4x32_10(U4{cell, step, TAG_THERMO, j}, k0, k1);
-  const double u0 = u01(w.x), u1 = u01(w.y), u2 = u01(w.z);
-  const double g = sqrt(-2.0 * log(u0)) * cospi(2.0 * u1);
-  const double t = 1.0 + c * g;
-  if (t <= 0.0) return -1.0;
-  const double V = t * t * t;
-  const double sq = g * g;
-  if (u2 < 1.0 - 0.0331 * (sq * sq)) return d * V * theta;
-  if (log(u2) < 0.5 * g * g + d - d * V + d * log(V)) return d * V * theta;
+  double g, V, u2;
+  const int q = gamma_quick(cell, step, j, c, k0, k1, g, V, u2);
+  if (q == GQ_ACCEPT || (q == GQ_FULL && gamma_full(g, V, u2, d))) return d * V * theta;
   return -1.0;
 }
 

@@ -35,7 +35,9 @@ enum : uint32_t {
 
 // status[0]: error flags above; status[1]: nonzero once a slab overflowed;
 // status[2]: smallest launch sequence number that overflowed (tile kernels
-// with a larger sequence number return at once).
+// with a larger sequence number return at once); status[ST_QUEUE]: length of
+// the thermostat draw queue.
+constexpr uint32_t ST_QUEUE = 4u;
 struct Box {
   int n[3];
   double L[3];
@@ -50,6 +52,8 @@ struct Box {
   int tsh[3];          // log2(td) (td is a power of two whenever nt > 1)
   int nt[3];           // tiles per axis
   uint32_t lm[3];      // cell -> cell inside its tile: c & lm (td - 1, or all ones if nt == 1)
+  uint32_t m_td0, m_td01;   // ceil(2^24 / td[0]), ceil(2^24 / (td[0] td[1]))
+  double inv_nt0, inv_nt01; // 1 / nt[0], 1 / (nt[0] nt[1])
   uint32_t ntiles;
   uint32_t cap;        // slots per tile
 };
@@ -124,6 +128,38 @@ __device__ inline uint32_t xcd_remap(uint32_t b, uint32_t nb) {
   return x < r ? x * (q + 1u) + i : r * (q + 1u) + (x - r) * q + i;
 }
 
+// Division without the integer divide sequence. l / d for l < 256 and
+// d <= 64 (tile sizes are at most 8 cells per axis): with m = ceil(2^24 / d),
+// floor(l m / 2^24) is exact whenever l d < 2^24.
+__device__ inline uint32_t div_small(uint32_t l, uint32_t m24) { return (l * m24) >> 24; }
+
+// T / d for any 32-bit T: an FP64 estimate, corrected by one step.
+__device__ inline uint32_t div_tile(uint32_t T, uint32_t d, double inv) {
+  uint32_t q = (uint32_t)((double)T * inv);
+  if (q * d > T) --q;
+  else if ((q + 1u) * d <= T) ++q;
+  return q;
+}
+
+// Tile coordinates of tile T (x fastest).
+__device__ inline void tile_coords(const Box& B, uint32_t T, int t3[3]) {
+  const uint32_t n0 = (uint32_t)B.nt[0], n1 = (uint32_t)B.nt[1];
+  const uint32_t a = div_tile(T, n0, B.inv_nt0);
+  const uint32_t z = div_tile(T, n0 * n1, B.inv_nt01);
+  t3[0] = (int)(T - a * n0);
+  t3[1] = (int)(a - z * n1);
+  t3[2] = (int)z;
+}
+
+// Coordinates of local cell l inside a tile (x fastest).
+__device__ inline void local_coords(const Box& B, uint32_t l, uint32_t l3[3]) {
+  const uint32_t a = div_small(l, B.m_td0);
+  const uint32_t z = div_small(l, B.m_td01);
+  l3[0] = l - a * (uint32_t)B.td[0];
+  l3[1] = a - z * (uint32_t)B.td[1];
+  l3[2] = z;
+}
+
 __device__ inline int tile_coord(int c, const Box& B, int d) {
   return B.nt[d] == 1 ? 0 : (c >> B.tsh[d]);
 }
@@ -191,35 +227,36 @@ struct Pos<0> {
 };
 template <>
 struct Pos<1> {
-  int h[3];
+  uint32_t hp;  // home cell, packed 10:10:10
   float o[3];
   template <class I>
   __device__ void load(const Particles& P, I i) {
-    unpack_home(ld(P.h, i), h[0], h[1], h[2]);
+    hp = ld(P.h, i);
     o[0] = ld(P.o[0], i);
     o[1] = ld(P.o[1], i);
     o[2] = ld(P.o[2], i);
   }
   template <class I>
   __device__ void store(const Particles& P, I j) const {
-    st(P.h, j, pack_home(h[0], h[1], h[2]));
+    st(P.h, j, hp);
     st(P.o[0], j, o[0]);
     st(P.o[1], j, o[1]);
     st(P.o[2], j, o[2]);
   }
   __device__ void stream(const Box& B, const float v[3], uint32_t&) {
+    int h[3];
+    unpack_home(hp, h[0], h[1], h[2]);
 #pragma unroll
     for (int d = 0; d < 3; ++d) stream_axis32(o[d], h[d], v[d], B.dt32, B.a32, B.inv_a32, B.n[d]);
+    hp = pack_home(h[0], h[1], h[2]);
   }
   __device__ void cell3(const Box& B, const double*, const float s32[3], int c[3]) const {
+    int h[3];
+    unpack_home(hp, h[0], h[1], h[2]);
 #pragma unroll
     for (int d = 0; d < 3; ++d) c[d] = bin_axis32(o[d], h[d], s32[d], B.inv_a32, B.n[d]);
   }
-  __device__ void home3(const Box&, int c[3]) const {
-    c[0] = h[0];
-    c[1] = h[1];
-    c[2] = h[2];
-  }
+  __device__ void home3(const Box&, int c[3]) const { unpack_home(hp, c[0], c[1], c[2]); }
 };
 
 __device__ inline uint32_t cell_index(const Box& B, const int c[3]) {
@@ -273,8 +310,10 @@ __device__ inline uint32_t dest_bin(const Box& B, const int t[3], const int c[3]
 enum { MODE_BIN = 0, MODE_COLLIDE = 1, MODE_COLLIDE_SCATTER = 2, MODE_DIAG = 3 };
 
 constexpr int TT = 256;         // threads per tile block
-constexpr int TQ = 4;           // particles per thread held in registers
-constexpr int TREG = TT * TQ;   // beyond this a tile's particles are re-read
+// particles per thread held in registers (beyond TT * TQ a tile's particles
+// are re-read from memory): 3 for 64-cell tiles (up to 768 particles, used
+// at densities 7..11), 4 otherwise
+constexpr int tq_for(int cpt) { return cpt == 64 ? 3 : 4; }
 
 struct TileArgs {
   Particles in, out;
@@ -336,6 +375,8 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
   constexpr bool SCAT = MODE == MODE_BIN || MODE == MODE_COLLIDE_SCATTER;
   constexpr bool EK = THERMO || MODE == MODE_DIAG;
   constexpr int NL = AC::NL;
+  constexpr int TQ = tq_for(CPT);
+  constexpr int TREG = TT * TQ;
   constexpr int RP = 0;                       // momentum rows: RP + NL * axis
   constexpr int RE = 3 * NL;                  // relative kinetic energy
   constexpr int RM = EK ? RE + NL : RE;       // mass (embedded particles)
@@ -355,13 +396,18 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
   const uint32_t tid = threadIdx.x;
   const uint32_t T = xcd_remap(blockIdx.x, gridDim.x);
   int t3[3];
-  t3[0] = (int)(T % (uint32_t)B.nt[0]);
-  t3[1] = (int)((T / (uint32_t)B.nt[0]) % (uint32_t)B.nt[1]);
-  t3[2] = (int)(T / ((uint32_t)B.nt[0] * (uint32_t)B.nt[1]));
+  tile_coords(B, T, t3);
 
-  // quit if an earlier launch of this call overflowed a slab (launches of
-  // the failing one itself run to the end, so its counts are complete)
+  // The status word, the occupancy and then the tile's particles are loaded
+  // before the first barrier, so their latencies overlap. A block quits
+  // after it if an earlier launch of this call overflowed a slab (launches
+  // of the failing one itself run to the end, so its counts are complete).
   if (tid == 0) s_quit = (A.status[1] != 0u && A.status[2] < A.seq) ? 1u : 0u;
+  if (tid == 0 && T == 0u) A.status[ST_QUEUE] = 0u;  // draw queue of this collision consumed
+  const uint32_t cnt = min(A.cnt_in[T], B.cap);
+  const uint32_t nreg = min(cnt, (uint32_t)TREG);
+  const size_t tbase = (size_t)T * B.cap;
+  const Particles In = tile_view<FORM>(A.in, tbase);
   if (tid < 27u) {
     s_bincnt[tid] = 0u;
     if constexpr (SCAT) s_btile[tid] = bin_tile(B, t3, tid);
@@ -370,14 +416,6 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
     for (uint32_t t = tid; t < (uint32_t)(NROW * CC); t += TT) (&s_acc[0][0])[t] = 0ull;
     if (tid < (uint32_t)CC) s_cnt[tid] = 0u;
   }
-  __syncthreads();
-  if (s_quit) return;
-
-  const uint32_t cnt = min(A.cnt_in[T], B.cap);
-  const uint32_t nreg = min(cnt, (uint32_t)TREG);
-  const size_t tbase = (size_t)T * B.cap;
-  const Particles In = tile_view<FORM>(A.in, tbase);
-  if (SCAT && tid == 0 && A.cnt_clear) A.cnt_clear[T] = 0u;
 
   uint32_t err = 0;
   bool bad = false;
@@ -389,11 +427,10 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
   // global index of local cell l, and whether the cell exists (the last
   // tile along an axis may be partial)
   auto cell_of = [&](uint32_t l, bool& ok) -> uint32_t {
-    const uint32_t lx = l % (uint32_t)B.td[0];
-    const uint32_t ly = (l / (uint32_t)B.td[0]) % (uint32_t)B.td[1];
-    const uint32_t lz = l / ((uint32_t)B.td[0] * (uint32_t)B.td[1]);
-    const int g[3] = {t3[0] * B.td[0] + (int)lx, t3[1] * B.td[1] + (int)ly, t3[2] * B.td[2] + (int)lz};
-    ok = l < (uint32_t)CPT && lz < (uint32_t)B.td[2] && g[0] < B.n[0] && g[1] < B.n[1] && g[2] < B.n[2];
+    uint32_t l3[3];
+    local_coords(B, l, l3);
+    const int g[3] = {t3[0] * B.td[0] + (int)l3[0], t3[1] * B.td[1] + (int)l3[1], t3[2] * B.td[2] + (int)l3[2]};
+    ok = l < (uint32_t)CPT && l3[2] < (uint32_t)B.td[2] && g[0] < B.n[0] && g[1] < B.n[1] && g[2] < B.n[2];
     return ok ? cell_index(B, g) : 0u;
   };
 
@@ -432,6 +469,9 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
       s_R[2][tid] = n[2];
     }
   }
+  __syncthreads();
+  if (s_quit) return;
+  if (SCAT && tid == 0 && A.cnt_clear) A.cnt_clear[T] = 0u;
 
   // ---- scatter: bin for the destination shift, reserve slots, write
   auto overflow = [&]() {
@@ -651,69 +691,110 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
   if (err) atomicOr(&A.status[0], err);
 }
 
-// Maxwell-Boltzmann draws of one collision (sec. 3.6), one block per tile:
-// the occupancy N_c of each of the tile's cells from the local-cell bytes of
-// its slab, then E_hat ~ Gamma(3 (N_c - 1) / 2, kT) for every cell with
-// N_c >= 2. Attempts 0 .. NGD-1 of a cell run in parallel on NGD threads and
-// the first accepted one in attempt order is the draw (the sequential
-// sampler's result); if all are rejected, the sampler continues in order.
-// Output ehat[T * CPT + l] (-1 for a cell with fewer than two particles).
-template <int CPT>
-struct DrawShape {
-  static constexpr int NGD = CPT >= 256 ? 1 : 2;
-  static constexpr int THREADS = NGD * CPT;
-};
+// Maxwell-Boltzmann draws of one collision (sec. 3.6), in two kernels.
+// k_draw: a block of DT = 256 threads takes 256 / CPT consecutive tiles, one
+// thread per cell. It counts the occupancy N_c of each cell from the
+// local-cell bytes of the tiles' slabs and makes attempt 0 of the draw
+// E_hat ~ Gamma(3 (N_c - 1) / 2, kT) for every cell with N_c >= 2, up to the
+// squeeze test. Accepted draws are written to ehat[T * CPT + l]; a cell whose
+// attempt 0 needs the full test or is rejected (a few per cent) goes to a
+// queue in global memory, {slot, cell, N_c}. k_draw_rest runs the sampler for
+// the queued cells from attempt 0 on, one thread per cell; the result is the
+// sequential sampler's either way. Cells with fewer than two particles get -1.
+// The queue length lives in status[4]; every k_tile launch clears it, so it
+// is zero again when the next collision's k_draw runs.
+constexpr int DT = 256;
 
 template <int CPT>
-__global__ __launch_bounds__(DrawShape<CPT>::THREADS) void k_draw(
-    Particles P, Box B, const uint32_t* __restrict__ cnt_in, uint32_t step,
-    double* __restrict__ ehat, uint32_t* status, uint32_t seq) {
-  constexpr int NGD = DrawShape<CPT>::NGD;
-  constexpr int DT = DrawShape<CPT>::THREADS;
-  __shared__ uint32_t s_n[CPT];
-  __shared__ double s_e[NGD][CPT];
+__global__ __launch_bounds__(DT) void k_draw(Particles P, Box B, const uint32_t* __restrict__ cnt_in,
+                                             uint32_t step, double* __restrict__ ehat,
+                                             uint32_t* __restrict__ queue, uint32_t* status,
+                                             uint32_t seq) {
+  constexpr int TPB = DT / CPT;  // tiles per block
+  constexpr int LQ = 4;          // local-cell bytes per tile and thread loaded at once
+  __shared__ uint32_t s_n[DT];
   __shared__ uint32_t s_quit;
   const uint32_t tid = threadIdx.x;
-  const uint32_t T = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
   if (tid == 0) s_quit = (status[1] != 0u && status[2] < seq) ? 1u : 0u;
-  for (uint32_t t = tid; t < (uint32_t)CPT; t += DT) s_n[t] = 0u;
+  s_n[tid] = 0u;
+
+  // occupancies: all loads of the block issued together, then the counts
+  uint32_t cnt[TPB];
+  uint32_t v[TPB][LQ];
+#pragma unroll
+  for (int i = 0; i < TPB; ++i) {
+    const uint32_t T = b * TPB + i;
+    cnt[i] = T < B.ntiles ? min(cnt_in[T], B.cap) : 0u;
+    const uint8_t* lc = P.lc + (size_t)T * B.cap;
+#pragma unroll
+    for (int q = 0; q < LQ; ++q) {
+      const uint32_t k = tid + (uint32_t)(q * DT);
+      v[i][q] = k < cnt[i] ? (uint32_t)ld(lc, k) : 0u;
+    }
+  }
   __syncthreads();
   if (s_quit) return;
-  const uint32_t cnt = min(cnt_in[T], B.cap);
-  const uint8_t* lc = P.lc + (size_t)T * B.cap;
-  for (uint32_t k = tid; k < cnt; k += DT) atomicAdd(&s_n[(uint32_t)ld(lc, k) & (uint32_t)(CPT - 1)], 1u);
+#pragma unroll
+  for (int i = 0; i < TPB; ++i) {
+#pragma unroll
+    for (int q = 0; q < LQ; ++q)
+      if (tid + (uint32_t)(q * DT) < cnt[i]) atomicAdd(&s_n[i * CPT + (v[i][q] & (uint32_t)(CPT - 1))], 1u);
+    const uint8_t* lc = P.lc + (size_t)(b * TPB + i) * B.cap;
+    for (uint32_t k = tid + (uint32_t)(LQ * DT); k < cnt[i]; k += DT)
+      atomicAdd(&s_n[i * CPT + ((uint32_t)ld(lc, k) & (uint32_t)(CPT - 1))], 1u);
+  }
   __syncthreads();
 
-  const uint32_t l = tid % (uint32_t)CPT, j = tid / (uint32_t)CPT;
+  // this thread's cell
+  const uint32_t T = b * TPB + tid / (uint32_t)CPT, l = tid % (uint32_t)CPT;
   int t3[3];
-  t3[0] = (int)(T % (uint32_t)B.nt[0]);
-  t3[1] = (int)((T / (uint32_t)B.nt[0]) % (uint32_t)B.nt[1]);
-  t3[2] = (int)(T / ((uint32_t)B.nt[0] * (uint32_t)B.nt[1]));
-  const uint32_t lx = l % (uint32_t)B.td[0];
-  const uint32_t ly = (l / (uint32_t)B.td[0]) % (uint32_t)B.td[1];
-  const uint32_t lz = l / ((uint32_t)B.td[0] * (uint32_t)B.td[1]);
-  const int g[3] = {t3[0] * B.td[0] + (int)lx, t3[1] * B.td[1] + (int)ly, t3[2] * B.td[2] + (int)lz};
-  const bool ok = lz < (uint32_t)B.td[2] && g[0] < B.n[0] && g[1] < B.n[1] && g[2] < B.n[2];
-  const uint32_t gc = ok ? cell_index(B, g) : 0u;
-  const uint32_t nc = ok ? s_n[l] : 0u;
-  const double k = 1.5 * (double)(nc - 1u);
-  const double d = k - 1.0 / 3.0;
-  double e = -1.0;  // -1: rejected or not drawn
-  if (nc >= 2u) e = gamma_attempt(gc, step, j, d, 1.0 / sqrt(9.0 * d), B.kT, B.k0, B.k1);
-  s_e[j][l] = e;
-  __syncthreads();
-  if (j == 0u) {
-    bool cap = false;
-    double r = -1.0;
-    if (nc >= 2u) {
-#pragma unroll
-      for (int a = 0; a < NGD; ++a)
-        if (r < 0.0) r = s_e[a][l];
-      if (r < 0.0) r = gamma_mt(k, gc, step, B.k0, B.k1, B.kT, cap, NGD);
-    }
-    ehat[(size_t)T * CPT + l] = r;
-    if (cap) atomicOr(&status[0], ERR_GAMMA_CAP);
+  tile_coords(B, T, t3);
+  uint32_t l3[3];
+  local_coords(B, l, l3);
+  const int g3[3] = {t3[0] * B.td[0] + (int)l3[0], t3[1] * B.td[1] + (int)l3[1], t3[2] * B.td[2] + (int)l3[2]};
+  const bool ok = T < B.ntiles && l3[2] < (uint32_t)B.td[2] && g3[0] < B.n[0] && g3[1] < B.n[1] &&
+                  g3[2] < B.n[2];
+  const uint32_t nc = ok ? s_n[tid] : 0u;
+  const uint32_t gc = ok ? cell_index(B, g3) : 0u;
+  double e = -1.0;
+  bool pend = false;
+  if (nc >= 2u) {
+    const double d = 1.5 * (double)(nc - 1u) - 1.0 / 3.0;
+    double g, V, u2;
+    const int r = gamma_quick(gc, step, 0u, 1.0 / sqrt(9.0 * d), B.k0, B.k1, g, V, u2);
+    if (r == GQ_ACCEPT) e = d * V * B.kT;
+    else pend = true;
   }
+  // queue the pending cells: one global atomic per wave
+  const unsigned long long m = __ballot(pend);
+  if (m) {
+    const uint32_t lane = tid & 63u;
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    const uint32_t leader = (uint32_t)__ffsll((long long)m) - 1u;
+    uint32_t base = 0u;
+    if (lane == leader) base = atomicAdd(&status[ST_QUEUE], (uint32_t)__popcll(m));
+    base = (uint32_t)__builtin_amdgcn_readlane((int)base, (int)leader);
+    if (pend) {
+      const size_t i = (size_t)(base + below) * 3u;
+      queue[i] = T * (uint32_t)CPT + l;
+      queue[i + 1] = gc;
+      queue[i + 2] = nc;
+    }
+  }
+  if (ok && !pend) ehat[(size_t)T * CPT + l] = e;
+}
+
+__global__ __launch_bounds__(256) void k_draw_rest(Box B, uint32_t step, double* __restrict__ ehat,
+                                                   const uint32_t* __restrict__ queue,
+                                                   uint32_t* status, uint32_t seq) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (status[1] != 0u && status[2] < seq) return;
+  if (i >= status[ST_QUEUE]) return;
+  const uint32_t slot = queue[3u * (size_t)i], gc = queue[3u * (size_t)i + 1], nc = queue[3u * (size_t)i + 2];
+  bool cap = false;
+  ehat[slot] = gamma_mt(1.5 * (double)(nc - 1u), gc, step, B.k0, B.k1, B.kT, cap, 0u);
+  if (cap) atomicOr(&status[0], ERR_GAMMA_CAP);
 }
 
 // ------------------------------------------------- elementwise over slabs
@@ -840,6 +921,7 @@ __global__ __launch_bounds__(256) void k_import(Particles P, Box B,
     r.x[1] = x[1];
     r.x[2] = x[2];
   } else {
+    int hh[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       int hd = (int)floor(x[d] * B.inv_a);
@@ -850,9 +932,10 @@ __global__ __launch_bounds__(256) void k_import(Particles P, Box B,
         hd = hd + 1 == B.n[d] ? 0 : hd + 1;
       }
       if (o < 0.0f) o = 0.0f;
-      r.h[d] = hd;
+      hh[d] = hd;
       r.o[d] = o;
     }
+    r.hp = pack_home(hh[0], hh[1], hh[2]);
   }
   int c[3];
   r.home3(B, c);
