@@ -15,6 +15,13 @@ times the largest single-GPU machine instead: 400^3 cells at 5 particles per cell
 (3.2 x 10^8) plus 20 000 chains of 50 mass-5 beads, FP32, no thermostat, 200
 steps.
 
+    python bench.py --workload srd_batch256_fp32
+
+times a batch of 256 independent boxes (sides 8..64 cells, densities 5..10,
+kT 0.5..2, thermostat, FP32; 1.44 x 10^8 particles in all) stepped together:
+throughput over 500 steps in one call, and the latency of single batch steps
+(p50/p99 over 100 calls of mpcd_step(1), each waited for).
+
 Prints one JSON line. `roofline` is for the dominant kernel (the collide
 kernel), timed with HIP events on the library's own stream during the timed
 region; `cpu_baseline` is the FP64 numpy oracle on a bounded sample.
@@ -151,6 +158,64 @@ def cpu_baseline(inp, n_cells, cfg, nsteps, what):
                        f"{dt:.1f} s, numpy, single thread)")
 
 
+def bench_batch(m, workloads, cfg, args):
+    """Throughput and single-step latency of a batch of independent boxes."""
+    import torch
+    steps = cfg["steps"] if args.steps == 1000 else args.steps
+    boxes = workloads.replica_inputs(workloads.replica_boxes(cfg["n_rep"], seed=cfg["seed"]))
+    N = sum(b["pos"].shape[0] for b in boxes)
+    torch.cuda.init()
+    bt = m.Batch(boxes, precision=m.FP32, thermostat=cfg["thermostat"])
+    del boxes
+    try:
+        bt.step(args.warmup)
+        bt.sync()
+        bt.profile(True)
+        for w in (0, 1, 2):
+            bt.profile_read(w)
+        t0 = time.perf_counter()
+        bt.step(steps)
+        bt.sync()
+        t1 = time.perf_counter()
+        coll_ms, coll_n = bt.profile_read(0)
+        draw_ms, draw_n = bt.profile_read(2)
+        bt.profile(False)
+        lat = []
+        for _ in range(100):
+            a = time.perf_counter()
+            bt.step(1)
+            bt.sync()
+            lat.append(time.perf_counter() - a)
+        P, ke, kT = bt.box_totals()
+    finally:
+        bt.close()
+    ups = N * steps / (t1 - t0)
+    avg_us = 1e3 * coll_ms / max(coll_n, 1)
+    gbs = collide_bytes_per_particle("fp32", 7.5) * N / (avg_us * 1e-6) / 1e9
+    lat_ms = 1e3 * np.array(lat)
+    out = {
+        "metric": "particle-updates/s (stream+bin+SRD collide) FP32 vs FP64; p99 batch latency",
+        "value": ups, "unit": "particle-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * (t1 - t0) / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "srd_batch256_fp32", "boxes": cfg["n_rep"], "particles": N,
+                   "sides": [8, 64], "density": [5, 10], "kT": [0.5, 2.0],
+                   "thermostat": "maxwell-boltzmann", "alpha_deg": 130, "dt": 0.1,
+                   "form": "fp32"},
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
+                       "p99": float(np.percentile(lat_ms, 99)),
+                       "what": "one mpcd_step(1) call on the whole batch, waited for"},
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic("fp32", "srd_batch256_fp32"),
+                     "kernel": "k_tile (collide + stream + bin + scatter)",
+                     "kernel_avg_us": avg_us, "bytes_per_particle": collide_bytes_per_particle("fp32", 7.5)},
+        "draw_avg_us": 1e3 * draw_ms / max(draw_n, 1),
+        "kT_range_end": [float(kT.min()), float(kT.max())],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,7 +226,8 @@ def main():
     ap.add_argument("--forms", default=None,
                     help="storage forms to time (default fp32,fp64; fp32 for the large box)")
     ap.add_argument("--workload", default=WORKLOAD,
-                    choices=["srd_100c_rho10_mbthermo", "srd_400c_rho5_beads"])
+                    choices=["srd_100c_rho10_mbthermo", "srd_400c_rho5_beads",
+                             "srd_batch256_fp32"])
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the streaming copy kernel (1 GiB, 20 times)")
     args = ap.parse_args()
@@ -180,6 +246,8 @@ def main():
         return
     wl = args.workload
     cfg = workloads.CONFIGS[wl]
+    if wl == "srd_batch256_fp32":
+        return bench_batch(m, workloads, cfg, args)
     big = wl != WORKLOAD
     if big and args.steps == 1000:
         args.steps = cfg["steps"]

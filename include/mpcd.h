@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define MPCD_ABI_VERSION 1
+#define MPCD_ABI_VERSION 2
 
 typedef struct mpcd_ctx_s* mpcd_ctx;
 
@@ -93,6 +93,35 @@ mpcd_status mpcd_create(const mpcd_params* params, int64_t n_solvent,
                         int32_t pointers_on_device, void* hip_stream,
                         mpcd_ctx* out);
 
+/* Create a context of n_boxes independent boxes (a batch) that every entry
+ * point below advances together, one kernel launch for all of them. Box b
+ * has its own parameters params[b] (cells, cell size, angle, dt, kT, seed,
+ * solvent mass) and n_particles[b] solvent particles, rows
+ * [first_b, first_b + n_particles[b]) of the row-major pos/vel arrays
+ * (first_b = the sum of the earlier counts). precision, thermostat,
+ * grid_shift and flags must be the same in every params[b]. No embedded
+ * particles. Tags run over the boxes in order (box b's particle i has tag
+ * first_b + i); per-cell outputs (counts, cell properties, draws) are the
+ * boxes' cell arrays one after the other, and cell_of_tag holds the cell
+ * index inside the particle's box. mpcd_create is the batch of one box.
+ * Errors as mpcd_create; the text names the first bad box. */
+mpcd_status mpcd_create_batch(int32_t n_boxes, const mpcd_params* params,
+                              const int64_t* n_particles, const double* pos,
+                              const double* vel, int32_t pointers_on_device,
+                              void* hip_stream, mpcd_ctx* out);
+
+/* Number of boxes of a context (1 for mpcd_create). */
+mpcd_status mpcd_get_n_boxes(mpcd_ctx ctx, int32_t* n_boxes);
+
+/* Where box `box` lives in the batch: its first tag and particle count, its
+ * first cell in per-cell outputs and cell count, and (if shift_of_step is
+ * not NULL) its grid shift for step counter `step`. Any pointer may be NULL.
+ * MPCD_EINVAL for a box out of range. */
+mpcd_status mpcd_get_box(mpcd_ctx ctx, int32_t box, int64_t* first_tag,
+                         int64_t* n_particles, int64_t* first_cell,
+                         int64_t* n_cells, double shift_of_step[3],
+                         uint64_t step);
+
 /* Streaming (eq. 1): r <- r + v dt, wrapped into the box. Needs the state
  * after create or after a collide. */
 mpcd_status mpcd_stream(mpcd_ctx ctx);
@@ -123,7 +152,8 @@ mpcd_status mpcd_get_state(mpcd_ctx ctx, double* pos, double* vel,
 
 /* Cells of the most recent mpcd_bin (or binning inside mpcd_step):
  * cell_of_tag[n_total] the x-fastest cell index ix + nx*(iy + ny*iz) on the
- * shifted grid, counts[n_cells] the occupancy. Either pointer may be NULL.
+ * shifted grid (inside the particle's box), counts[n_cells] the occupancy
+ * (n_cells: all boxes). Either pointer may be NULL.
  * MPCD_ESTATE if nothing has been binned yet. Synchronises. */
 mpcd_status mpcd_get_cells(mpcd_ctx ctx, int32_t* cell_of_tag, int32_t* counts,
                            int32_t pointers_on_device);
@@ -143,8 +173,19 @@ mpcd_status mpcd_get_cell_props(mpcd_ctx ctx, double* mass, double* momentum,
 mpcd_status mpcd_get_cell_draws(mpcd_ctx ctx, double* axis, double* xi,
                                 int32_t pointers_on_device);
 
+/* Cell-averaged velocity field of the current state on the unshifted grid
+ * (each particle in its home cell floor(r / a)): u[n_cells x 3] the
+ * mass-weighted mean velocity sum(m v) / sum(m) of the cell's particles (0
+ * for an empty cell, sec. 3.5 cell properties), mass[n_cells] the cell's
+ * mass. n_cells covers all boxes, one after the other. The sums are exact
+ * (fixed point), so the result does not depend on the particles' order.
+ * Either pointer may be NULL. Any state. Synchronises. */
+mpcd_status mpcd_get_velocity_field(mpcd_ctx ctx, double* u, double* mass,
+                                    int32_t pointers_on_device);
+
 /* Grid shift drawn for step counter n, s[3] in (-a/2, a/2) (zero when the
- * shift is off). Host-only computation; any state. */
+ * shift is off), of box 0 (mpcd_get_box gives any box's). Host-only
+ * computation; any state. */
 mpcd_status mpcd_get_shift(mpcd_ctx ctx, uint64_t n, double s[3]);
 
 /* Step counter: read, or set (to resume from a checkpoint; only in the
@@ -154,8 +195,12 @@ mpcd_status mpcd_set_step(mpcd_ctx ctx, uint64_t n);
 
 /* Net properties (sec. 3.5): total momentum p[3], kinetic energy ke and the
  * kinetic temperature of the motion relative to the centre of mass,
- * 2 (ke - |p|^2 / 2M) / (3 (n_total - 1)). Synchronises. */
+ * 2 (ke - |p|^2 / 2M) / (3 (n_total - 1)), over all boxes. Synchronises. */
 mpcd_status mpcd_totals(mpcd_ctx ctx, double p[3], double* ke, double* kT);
+
+/* The same per box: p[3 * n_boxes], ke[n_boxes], kT[n_boxes] (any may be
+ * NULL). Synchronises. */
+mpcd_status mpcd_box_totals(mpcd_ctx ctx, double* p, double* ke, double* kT);
 
 /* Wait for the context's work and report kernel range errors. */
 mpcd_status mpcd_sync(mpcd_ctx ctx);

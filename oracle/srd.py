@@ -257,6 +257,16 @@ def run(pos, vel, mass, p, step0, nsteps):
 
 
 # ------------------------------------------------------------ diagnostics
+def velocity_field(pos, vel, mass, p):
+    """Cell-averaged velocity of a state on the unshifted grid: every particle
+    counts in its home cell (the binning of sec. 3.4 with zero shift); per
+    cell the mass-weighted mean velocity sum(m v) / sum(m), 0 where the cell
+    is empty, and the cell's mass (sec. 3.5 cell properties)."""
+    cell = bin_cells(pos, np.zeros(3), p)
+    _, M, P, u, _ = cell_sums(cell, vel, mass, p.ncells)
+    return u, M
+
+
 def totals(vel, mass):
     """Net momentum, kinetic energy, and the kinetic temperature of the
     motion relative to the centre of mass, 2 (KE - |P|^2 / 2M) / (3 (N - 1))

@@ -83,6 +83,14 @@ def load():
         "mpcd_last_error": (ctypes.c_char_p, []),
         "mpcd_philox4x32_10": (st, [_P, ctypes.c_int64, ctypes.c_uint64, _P]),
         "mpcd_copy_kernel": (st, [_P, _P, ctypes.c_int64, _P]),
+        "mpcd_create_batch": (st, [ctypes.c_int32, ctypes.POINTER(Params), _P, _P, _P,
+                                   ctypes.c_int32, _P, ctypes.POINTER(_P)]),
+        "mpcd_get_n_boxes": (st, [_P, ctypes.POINTER(ctypes.c_int32)]),
+        "mpcd_get_box": (st, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                              ctypes.POINTER(ctypes.c_int64), _P, ctypes.c_uint64]),
+        "mpcd_box_totals": (st, [_P, _P, _P, _P]),
+        "mpcd_get_velocity_field": (st, [_P, _P, _P, ctypes.c_int32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -196,6 +204,14 @@ class Sim:
         _check(load().mpcd_get_cell_draws(self._ctx, _ptr(axis), _ptr(xi), 0))
         return axis, xi
 
+    def velocity_field(self):
+        """Mass-weighted mean velocity (n_cells, 3) and mass (n_cells) per
+        cell of the unshifted grid."""
+        u = np.empty((self.ncells, 3))
+        mass = np.empty(self.ncells)
+        _check(load().mpcd_get_velocity_field(self._ctx, _ptr(u), _ptr(mass), 0))
+        return u, mass
+
     def shift(self, n):
         s = np.empty(3)
         _check(load().mpcd_get_shift(self._ctx, int(n), _ptr(s)))
@@ -252,6 +268,64 @@ class Sim:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Batch(Sim):
+    """Several independent SRD boxes stepped together (one mpcd_ctx made by
+    mpcd_create_batch). `boxes` is a list of dicts with the keys pos, vel,
+    n_cells and optionally a, alpha, dt, kT, seed, solvent_mass; precision,
+    thermostat, grid_shift and flags are common to all boxes. Every method of
+    Sim works on all boxes at once; get_state/get_cells return the boxes one
+    after the other (see box())."""
+
+    def __init__(self, boxes, precision=FP64, thermostat=False, grid_shift=True,
+                 hip_stream=None, flags=0):
+        lib = load()
+        nb = len(boxes)
+        arr = (Params * nb)()
+        counts = np.empty(nb, dtype=np.int64)
+        pos_l, vel_l = [], []
+        for b, bx in enumerate(boxes):
+            arr[b] = make_params(bx["n_cells"], bx.get("a", 1.0),
+                                 bx.get("alpha", 130.0 * math.pi / 180.0), bx.get("dt", 0.1),
+                                 bx.get("kT", 1.0), bx.get("seed", 1 + b),
+                                 bx.get("solvent_mass", 1.0), precision, thermostat,
+                                 grid_shift, flags)
+            pos_l.append(np.asarray(bx["pos"], dtype=np.float64).reshape(-1, 3))
+            vel_l.append(np.asarray(bx["vel"], dtype=np.float64).reshape(-1, 3))
+            counts[b] = pos_l[-1].shape[0]
+        pos = np.ascontiguousarray(np.concatenate(pos_l)) if nb else np.empty((0, 3))
+        vel = np.ascontiguousarray(np.concatenate(vel_l)) if nb else np.empty((0, 3))
+        ctx = ctypes.c_void_p()
+        _check(lib.mpcd_create_batch(nb, arr, _ptr(counts), _ptr(pos), _ptr(vel), 0,
+                                     None if hip_stream is None else ctypes.c_void_p(hip_stream),
+                                     ctypes.byref(ctx)))
+        self._ctx = ctx
+        self.params = arr[0]
+        self.box_params = arr
+        self.n_boxes = nb
+        self.n_solvent = int(counts.sum())
+        self.n_embedded = 0
+        self.n_total = self.n_solvent
+        nt, nc = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.mpcd_get_sizes(ctx, ctypes.byref(nt), ctypes.byref(nc)))
+        self.ncells = nc.value
+
+    def box(self, b, step=0):
+        """(first tag, particles, first cell, cells, shift of `step`) of box b."""
+        t, n, c, nc = (ctypes.c_int64() for _ in range(4))
+        s = np.empty(3)
+        _check(load().mpcd_get_box(self._ctx, int(b), ctypes.byref(t), ctypes.byref(n),
+                                   ctypes.byref(c), ctypes.byref(nc), _ptr(s), int(step)))
+        return t.value, n.value, c.value, nc.value, s
+
+    def box_totals(self):
+        """Per box: momentum (n_boxes, 3), kinetic energy, temperature."""
+        p = np.empty((self.n_boxes, 3))
+        ke = np.empty(self.n_boxes)
+        kT = np.empty(self.n_boxes)
+        _check(load().mpcd_box_totals(self._ctx, _ptr(p), _ptr(ke), _ptr(kT)))
+        return p, ke, kT
 
 
 def philox(ctr, key):

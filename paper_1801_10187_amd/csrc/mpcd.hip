@@ -1,12 +1,15 @@
 // libmpcd: host side of the C ABI declared in include/mpcd.h.
 //
-// The context owns every device buffer (hipMalloc at create, hipFree at
+// A context holds one box, or several independent boxes stepped together
+// (a batch). It owns every device buffer (hipMalloc at create, hipFree at
 // destroy) and enqueues all work on one HIP stream. Particles live in
-// fixed-capacity per-tile slabs (see mpcd_kernels.hpp). A call to mpcd_step
-// launches one stream+bin kernel and then one tile kernel per step; it waits
-// for the stream at its end to confirm that no slab overflowed. If one did,
-// the input of the failing launch is still intact: the slabs are enlarged,
-// that input is repacked, and the launches are replayed from there.
+// fixed-capacity per-tile slabs (see mpcd_kernels.hpp); the tiles of all
+// boxes share the slab arrays, and every launch covers all of them. A call
+// to mpcd_step launches one stream+bin kernel and then, per step, the
+// thermostat draws (if on) and one tile kernel; it waits for the stream at
+// its end to confirm that no slab overflowed. If one did, the input of the
+// failing launch is still intact: the slabs are enlarged, that input is
+// repacked, and the launches are replayed from there.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -62,6 +65,9 @@ constexpr uint32_t kGrid = 256;  // threads per block of the elementwise kernels
 // slots per tile stay below 2^28: a slot's byte offset inside its tile's
 // slab then fits 32 bits for every element size
 constexpr uint32_t kMaxCap = 1u << 28;
+// every box starts at a multiple of this many tiles (k_draw takes up to 4
+// consecutive tiles per block, all of one box)
+constexpr uint32_t kTileAlign = 4;
 
 inline uint32_t blocks_for(uint64_t n, uint32_t per) {
   return (uint32_t)((n + per - 1) / per);
@@ -72,25 +78,33 @@ inline uint32_t round_up(uint64_t x, uint32_t m) { return (uint32_t)(((x + m - 1
 }  // namespace
 
 struct mpcd_ctx_s {
-  mpcd_params p{};
+  mpcd_params p{};                 // settings shared by all boxes (box 0's parameters)
   int form = 0;
-  uint32_t n_solv = 0, n_emb = 0, N = 0;
-  Box box{};
+  uint32_t nbox = 0;
+  uint32_t n_emb = 0, N = 0;       // embedded particles (box 0 only), all particles
+  std::vector<Box> boxes;          // host copies of the per-box constants
+  std::vector<uint32_t> box_n;     // particles per box
+  Slabs S{};                       // device view of the layout
+  uint64_t ncells = 0;             // cells of all boxes
   int cpt = 64;  // cells per tile rounded up to 64/128/256 (kernel template)
   hipStream_t stream = nullptr;
   bool own_stream = false;
 
-  std::vector<void*> allocs;       // everything but the slabs
+  std::vector<void*> allocs;       // everything but the slabs and the shift table
   std::vector<void*> slab_allocs;  // the two particle buffers
   Particles buf[2]{};
   int cur = 0;
   uint32_t* cnt[3] = {nullptr, nullptr, nullptr};
   int ci = 0;                      // cnt[ci] describes buf[cur]
   double* emb_mass = nullptr;
-  uint32_t* status = nullptr;      // [0] errors, [1] overflow, [2] failing launch, [4] draw queue
+  uint32_t* status = nullptr;      // [0] errors, [1] overflow, [2] failing launch
   double* ehat = nullptr;          // thermostat draws of the next collision, [tile][cpt]
   uint32_t* dqueue = nullptr;      // cells whose draw needs more than the quick test
-  long long* tot = nullptr;
+  uint32_t* qcount = nullptr;      // queue segment length per draw block
+  long long* tot = nullptr;        // fixed-point totals, 10 words per box
+
+  ShiftEntry* shifts = nullptr;    // grid shifts of steps shift_n0 .., [step][box]
+  uint64_t shift_cap = 0, shift_n0 = 0, shift_count = 0;
 
   uint64_t step = 0;
   uint64_t last_bin_step = 0;
@@ -132,13 +146,39 @@ mpcd_status take_err(mpcd_ctx c) {
   return MPCD_OK;
 }
 
-void shift_for(const mpcd_ctx c, uint64_t n, double s[3], float s32[3]) {
+// Host copy of box b's shift for step n (the kernels read the device table).
+void shift_for(const mpcd_ctx c, uint32_t b, uint64_t n, double s[3]) {
   if (c->p.grid_shift) {
-    grid_shift(c->box.k0, c->box.k1, (uint32_t)n, c->p.a, s);
+    grid_shift(c->boxes[b].k0, c->boxes[b].k1, (uint32_t)n, c->boxes[b].a, s);
   } else {
     s[0] = s[1] = s[2] = 0.0;
   }
-  for (int d = 0; d < 3; ++d) s32[d] = (float)s[d];
+}
+
+// Fill the device shift table with steps n0 .. n0 + count - 1 of every box.
+mpcd_status ensure_shifts(mpcd_ctx c, uint64_t n0, uint64_t count) {
+  const uint64_t need = count * c->nbox;
+  if (need > c->shift_cap) {
+    if (c->shifts) {
+      HIP_TRY(hipStreamSynchronize(c->stream));
+      (void)hipFree(c->shifts);
+      c->shifts = nullptr;
+      c->shift_cap = 0;
+    }
+    const uint64_t cap = std::max<uint64_t>(need, 64);
+    HIP_TRY(hipMalloc(&c->shifts, cap * sizeof(ShiftEntry)));
+    c->shift_cap = cap;
+  }
+  k_shifts<<<blocks_for(need, 256), 256, 0, c->stream>>>(c->S.boxes, c->nbox, (uint32_t)n0,
+                                                          (uint32_t)count, c->p.grid_shift, c->shifts);
+  HIP_TRY(hipGetLastError());
+  c->shift_n0 = n0;
+  c->shift_count = count;
+  return MPCD_OK;
+}
+
+const ShiftEntry* shift_at(const mpcd_ctx c, uint64_t n) {
+  return c->shifts + (n - c->shift_n0) * c->nbox;
 }
 
 // --- profiling helpers
@@ -171,13 +211,13 @@ struct ProfScope {
 };
 
 uint32_t slab_blocks(const mpcd_ctx c, uint32_t cap) {
-  return c->box.ntiles * ((cap + 255u) / 256u);
+  return c->S.ntiles * ((cap + 255u) / 256u);
 }
 
 // --- tile kernel dispatch
 template <int F, int CPT, int MODE, bool SI>
 void tile_inst2(mpcd_ctx c, const TileArgs& a, bool th, bool em) {
-  const uint32_t nb = c->box.ntiles;
+  const uint32_t nb = c->S.ntiles;
   if (th) {
     if (em) k_tile<F, CPT, MODE, SI, true, true><<<nb, TT, 0, c->stream>>>(a);
     else k_tile<F, CPT, MODE, SI, true, false><<<nb, TT, 0, c->stream>>>(a);
@@ -215,7 +255,7 @@ TileArgs tile_args(mpcd_ctx c) {
   TileArgs a{};
   a.in = c->buf[c->cur];
   a.out = c->buf[1 - c->cur];
-  a.B = c->box;
+  a.S = c->S;
   a.cnt_in = c->cnt[c->ci];
   a.cnt_out = c->cnt[(c->ci + 1) % 3];
   a.cnt_clear = c->cnt[(c->ci + 2) % 3];
@@ -228,15 +268,16 @@ TileArgs tile_args(mpcd_ctx c) {
 template <int CPT>
 void draw_inst(mpcd_ctx c, uint64_t n, uint32_t seq) {
   constexpr uint32_t tpb = DT / CPT;
-  k_draw<CPT><<<(c->box.ntiles + tpb - 1) / tpb, DT, 0, c->stream>>>(
-      c->buf[c->cur], c->box, c->cnt[c->ci], (uint32_t)n, c->ehat, c->dqueue, c->status, seq);
-  k_draw_rest<<<blocks_for((uint64_t)c->box.ntiles * CPT, 256), 256, 0, c->stream>>>(
-      c->box, (uint32_t)n, c->ehat, c->dqueue, c->status, seq);
+  const uint32_t nb = (c->S.ntiles + tpb - 1) / tpb;
+  k_draw<CPT><<<nb, DT, 0, c->stream>>>(c->buf[c->cur], c->S, c->cnt[c->ci], (uint32_t)n, c->ehat,
+                                        c->dqueue, c->qcount, c->status, seq);
+  k_draw_rest<<<nb, DT, 0, c->stream>>>(c->S.boxes, (uint32_t)n, c->ehat, c->dqueue, c->qcount,
+                                        c->status, seq);
 }
 
 // Thermostat draws for the collision of step n on the current slabs.
 mpcd_status launch_draw(mpcd_ctx c, uint64_t n, uint32_t seq) {
-  if (!c->p.thermostat || c->box.ntiles == 0) return MPCD_OK;
+  if (!c->p.thermostat || c->S.ntiles == 0) return MPCD_OK;
   ProfScope ps(c, 2);
   switch (c->cpt) {
     case 64: draw_inst<64>(c, n, seq); break;
@@ -247,18 +288,20 @@ mpcd_status launch_draw(mpcd_ctx c, uint64_t n, uint32_t seq) {
   return MPCD_OK;
 }
 
+// One tile-kernel launch for step n. The shift table must hold step n (and
+// n + 1 for a collision fused with the next binning).
 mpcd_status launch_tile(mpcd_ctx c, Op op, uint64_t n, uint32_t seq) {
   if (op == Op::Draw) return launch_draw(c, n, seq);
   TileArgs a = tile_args(c);
   a.step = (uint32_t)n;
   a.seq = seq;
-  shift_for(c, n, a.s, a.s32);
+  a.sh = shift_at(c, n);
   int mode;
   bool stream_in = false;
   switch (op) {
     case Op::BinStream: mode = MODE_BIN; stream_in = true; break;
     case Op::Bin: mode = MODE_BIN; break;
-    case Op::CollideScatter: mode = MODE_COLLIDE_SCATTER; shift_for(c, n + 1, a.sn, a.sn32); break;
+    case Op::CollideScatter: mode = MODE_COLLIDE_SCATTER; a.shn = shift_at(c, n + 1); break;
     default: mode = MODE_COLLIDE; break;
   }
   {
@@ -274,7 +317,7 @@ mpcd_status launch_tile(mpcd_ctx c, Op op, uint64_t n, uint32_t seq) {
 
 // --- slabs
 mpcd_status alloc_slabs(mpcd_ctx c, uint32_t cap, Particles out[2], std::vector<void*>& owned) {
-  const size_t S = (size_t)c->box.ntiles * cap;
+  const size_t S = (size_t)c->S.ntiles * cap;
   auto get = [&](size_t bytes) -> void* {
     void* q = nullptr;
     if (hipMalloc(&q, bytes ? bytes : 256) != hipSuccess) return nullptr;
@@ -315,12 +358,12 @@ void free_all(std::vector<void*>& v) {
 // the slabs to hold the largest count the failed launch tried to place (plus
 // headroom), repack that intact input and reset the counters.
 mpcd_status regrow(mpcd_ctx c, int in_cur, int in_ci) {
-  const uint32_t nt = c->box.ntiles;
+  const uint32_t nt = c->S.ntiles;
   std::vector<uint32_t> want(nt);
   HIP_TRY(hipMemcpy(want.data(), c->cnt[(in_ci + 1) % 3], (size_t)nt * 4, hipMemcpyDeviceToHost));
   uint32_t mx = 0;
   for (uint32_t v : want) mx = std::max(mx, v);
-  const uint32_t old_cap = c->box.cap;
+  const uint32_t old_cap = c->S.cap;
   const uint64_t target = std::max<uint64_t>((uint64_t)mx + mx / 4 + 64, (uint64_t)old_cap + old_cap / 2);
   const uint32_t new_cap = round_up(target, 64);
   if ((uint64_t)new_cap * nt >= (1ull << 32) || new_cap >= kMaxCap)
@@ -332,13 +375,13 @@ mpcd_status regrow(mpcd_ctx c, int in_cur, int in_ci) {
     free_all(owned);
     return st;
   }
-  Box B = c->box;
-  B.cap = new_cap;
+  Slabs S = c->S;
+  S.cap = new_cap;
   const uint32_t blocks = nt * ((old_cap + 255u) / 256u);
   if (c->form == 0)
-    k_repack<0><<<blocks, 256, 0, c->stream>>>(c->buf[in_cur], nb[0], B, old_cap, c->cnt[in_ci]);
+    k_repack<0><<<blocks, 256, 0, c->stream>>>(c->buf[in_cur], nb[0], S, old_cap, c->cnt[in_ci]);
   else
-    k_repack<1><<<blocks, 256, 0, c->stream>>>(c->buf[in_cur], nb[0], B, old_cap, c->cnt[in_ci]);
+    k_repack<1><<<blocks, 256, 0, c->stream>>>(c->buf[in_cur], nb[0], S, old_cap, c->cnt[in_ci]);
   HIP_TRY(hipGetLastError());
   if (in_ci != 0)
     HIP_TRY(hipMemcpyAsync(c->cnt[0], c->cnt[in_ci], (size_t)nt * 4, hipMemcpyDeviceToDevice, c->stream));
@@ -351,7 +394,7 @@ mpcd_status regrow(mpcd_ctx c, int in_cur, int in_ci) {
   c->slab_allocs = owned;
   c->buf[0] = nb[0];
   c->buf[1] = nb[1];
-  c->box.cap = new_cap;
+  c->S.cap = new_cap;
   c->cur = 0;
   c->ci = 0;
   c->regrows += 1;
@@ -405,21 +448,20 @@ mpcd_status validate(const mpcd_params* p, int64_t ns, int64_t ne) {
   return MPCD_OK;
 }
 
-// Tile shape: about 350-770 particles per tile at the system's mean density
-// (the kernels hold up to 768 particles of a 64-cell tile and 1024 of a
-// larger one in registers).
-void choose_tiles(mpcd_ctx c) {
-  Box& B = c->box;
-  const double rho = B.ncells ? (double)c->N / (double)B.ncells : 0.0;
-  int td[3];
+// Tile shape of one box: about 350-770 particles per tile at the box's mean
+// density (the kernels hold up to 768 particles of a 64-cell tile and 1024
+// of a larger one in registers). Returns the cells per tile, rounded up to
+// the kernel sizes 64/128/256.
+int choose_tiles(Box& B, double rho) {
+  int td[3], cpt;
   if (rho >= 11.0) {
-    td[0] = 4; td[1] = 4; td[2] = 2; c->cpt = 64;
+    td[0] = 4; td[1] = 4; td[2] = 2; cpt = 64;
   } else if (rho >= 7.0) {
-    td[0] = 4; td[1] = 4; td[2] = 4; c->cpt = 64;
+    td[0] = 4; td[1] = 4; td[2] = 4; cpt = 64;
   } else if (rho >= 3.5) {
-    td[0] = 8; td[1] = 4; td[2] = 4; c->cpt = 128;
+    td[0] = 8; td[1] = 4; td[2] = 4; cpt = 128;
   } else {
-    td[0] = 8; td[1] = 8; td[2] = 4; c->cpt = 256;
+    td[0] = 8; td[1] = 8; td[2] = 4; cpt = 256;
   }
   B.ntiles = 1;
   for (int d = 0; d < 3; ++d) {
@@ -442,25 +484,63 @@ void choose_tiles(mpcd_ctx c) {
   B.m_td01 = (uint32_t)(((1u << 24) + B.td[0] * B.td[1] - 1) / (B.td[0] * B.td[1]));
   B.inv_nt0 = 1.0 / (double)B.nt[0];
   B.inv_nt01 = 1.0 / ((double)B.nt[0] * (double)B.nt[1]);
+  return cpt;
 }
 
-}  // namespace
+// Per-box constants from the parameters (layout fields are set by the caller).
+Box make_box(const mpcd_params& p) {
+  Box B{};
+  for (int d = 0; d < 3; ++d) {
+    B.n[d] = p.n_cells[d];
+    B.L[d] = (double)p.n_cells[d] * p.a;
+  }
+  B.a = p.a;
+  B.inv_a = 1.0 / p.a;
+  B.dt = p.dt;
+  B.a32 = (float)p.a;
+  B.inv_a32 = (float)B.inv_a;
+  B.dt32 = (float)p.dt;
+  B.ncells = (uint32_t)((uint64_t)p.n_cells[0] * p.n_cells[1] * p.n_cells[2]);
+  B.ca = std::cos(p.alpha);
+  B.sa = std::sin(p.alpha);
+  B.omc = 1.0 - B.ca;
+  B.kT = p.kT;
+  B.mass = p.solvent_mass;
+  B.k0 = (uint32_t)(p.seed & 0xFFFFFFFFull);
+  B.k1 = (uint32_t)(p.seed >> 32);
+  return B;
+}
 
-// ======================================================================= ABI
-extern "C" {
-
-const char* mpcd_last_error(void) { return g_err.c_str(); }
-
-mpcd_status mpcd_create(const mpcd_params* params, int64_t n_solvent, const double* pos,
-                        const double* vel, int64_t n_embedded, const double* emb_pos,
-                        const double* emb_vel, const double* emb_mass,
+// Create a context of nbox boxes. Box b has n_solv[b] solvent particles,
+// rows [row0_b, row0_b + n_solv[b]) of pos/vel (row0 = running sum); box 0
+// may also have n_emb embedded particles.
+mpcd_status create_impl(int32_t nbox, const mpcd_params* params, const int64_t* n_solv,
+                        const double* pos, const double* vel, int64_t n_embedded,
+                        const double* emb_pos, const double* emb_vel, const double* emb_mass,
                         int32_t pointers_on_device, void* hip_stream, mpcd_ctx* out) {
   g_err.clear();
   if (!out) return fail(MPCD_EINVAL, "out is NULL");
   *out = nullptr;
-  mpcd_status st = validate(params, n_solvent, n_embedded);
-  if (st != MPCD_OK) return st;
-  if (n_solvent > 0 && (!pos || !vel)) return fail(MPCD_EINVAL, "pos/vel NULL");
+  if (nbox < 1) return fail(MPCD_EINVAL, "n_boxes must be >= 1");
+  if (!params || !n_solv) return fail(MPCD_EINVAL, "params/n_particles is NULL");
+  int64_t ns_total = 0;
+  double ncells_total = 0.0;
+  for (int32_t b = 0; b < nbox; ++b) {
+    mpcd_status st = validate(&params[b], n_solv[b], b == 0 ? n_embedded : 0);
+    if (st != MPCD_OK) {
+      if (nbox > 1) g_err = "box " + std::to_string(b) + ": " + g_err;
+      return st;
+    }
+    const mpcd_params& q = params[b];
+    if (q.precision != params[0].precision || q.thermostat != params[0].thermostat ||
+        q.grid_shift != params[0].grid_shift || q.flags != params[0].flags)
+      return fail(MPCD_EINVAL, "box %d: precision, thermostat, grid_shift and flags must match box 0", b);
+    ns_total += n_solv[b];
+    ncells_total += (double)q.n_cells[0] * q.n_cells[1] * q.n_cells[2];
+  }
+  if (ns_total + n_embedded >= (int64_t)1 << 31) return fail(MPCD_EINVAL, "at most 2^31 - 1 particles");
+  if (ncells_total > 4.0e9) return fail(MPCD_EINVAL, "too many cells (%.0f)", ncells_total);
+  if (ns_total > 0 && (!pos || !vel)) return fail(MPCD_EINVAL, "pos/vel NULL");
   if (n_embedded > 0 && (!emb_pos || !emb_vel || !emb_mass))
     return fail(MPCD_EINVAL, "embedded arrays NULL");
   if (n_embedded > 0 && !pointers_on_device) {
@@ -477,32 +557,42 @@ mpcd_status mpcd_create(const mpcd_params* params, int64_t n_solvent, const doub
     g_err = keep;
     return s;
   };
-  c->p = *params;
-  c->form = params->precision;
-  c->n_solv = (uint32_t)n_solvent;
+  c->p = params[0];
+  c->form = params[0].precision;
+  c->nbox = (uint32_t)nbox;
   c->n_emb = (uint32_t)n_embedded;
-  c->N = (uint32_t)(n_solvent + n_embedded);
-  Box& B = c->box;
-  for (int d = 0; d < 3; ++d) {
-    B.n[d] = params->n_cells[d];
-    B.L[d] = (double)params->n_cells[d] * params->a;
+  c->N = (uint32_t)(ns_total + n_embedded);
+
+  // boxes and the tile layout
+  uint32_t tile = 0, tag = 0;
+  uint64_t cell = 0;
+  int cpt = 64;
+  std::vector<uint32_t> tile_box;
+  double max_mean = 0.0;
+  for (int32_t b = 0; b < nbox; ++b) {
+    Box B = make_box(params[b]);
+    const uint32_t nb = (uint32_t)n_solv[b] + (b == 0 ? c->n_emb : 0u);
+    cpt = std::max(cpt, choose_tiles(B, B.ncells ? (double)nb / (double)B.ncells : 0.0));
+    // padding up to a multiple of kTileAlign belongs to the box before it
+    const uint32_t t0 = round_up(tile, kTileAlign);
+    tile_box.resize(t0, b == 0 ? 0u : (uint32_t)(b - 1));
+    B.tile0 = t0;
+    B.tag0 = tag;
+    B.cell0 = (uint32_t)cell;
+    B.n_solvent = (uint32_t)n_solv[b];
+    tile_box.resize(t0 + B.ntiles, (uint32_t)b);
+    max_mean = std::max(max_mean, (double)nb / (double)B.ntiles);
+    tile = t0 + B.ntiles;
+    tag += nb;
+    cell += B.ncells;
+    c->boxes.push_back(B);
+    c->box_n.push_back(nb);
   }
-  B.a = params->a;
-  B.inv_a = 1.0 / params->a;
-  B.dt = params->dt;
-  B.a32 = (float)params->a;
-  B.inv_a32 = (float)B.inv_a;
-  B.dt32 = (float)params->dt;
-  B.ncells = (uint32_t)((uint64_t)params->n_cells[0] * params->n_cells[1] * params->n_cells[2]);
-  B.ca = std::cos(params->alpha);
-  B.sa = std::sin(params->alpha);
-  B.omc = 1.0 - B.ca;
-  B.kT = params->kT;
-  B.mass = params->solvent_mass;
-  B.k0 = (uint32_t)(params->seed & 0xFFFFFFFFull);
-  B.k1 = (uint32_t)(params->seed >> 32);
-  B.n_solvent = c->n_solv;
-  choose_tiles(c);
+  const uint32_t NT = round_up(tile, kTileAlign);
+  tile_box.resize(NT, (uint32_t)(nbox - 1));
+  c->cpt = cpt;
+  c->ncells = cell;
+  c->S.ntiles = NT;
 
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
@@ -511,34 +601,45 @@ mpcd_status mpcd_create(const mpcd_params* params, int64_t n_solvent, const doub
       return cleanup(fail(MPCD_EHIP, "hipStreamCreate failed (no usable GPU?)"));
     c->own_stream = true;
   }
-  const size_t NT = B.ntiles;
-  for (int k = 0; k < 3; ++k) c->cnt[k] = (uint32_t*)c->dalloc(NT * 4);
+  for (int k = 0; k < 3; ++k) c->cnt[k] = (uint32_t*)c->dalloc((size_t)NT * 4);
   c->status = (uint32_t*)c->dalloc(256);
-  c->tot = (long long*)c->dalloc(10 * 8);
+  c->tot = (long long*)c->dalloc((size_t)nbox * 10 * 8);
   c->emb_mass = (double*)c->dalloc((size_t)c->n_emb * 8);
-  if (params->thermostat) {
-    c->ehat = (double*)c->dalloc(NT * (size_t)c->cpt * 8);
-    c->dqueue = (uint32_t*)c->dalloc(NT * (size_t)c->cpt * 12);
-    if (!c->ehat || !c->dqueue) return cleanup(fail(MPCD_ENOMEM, "device allocation failed"));
-  }
+  Box* dboxes = (Box*)c->dalloc((size_t)nbox * sizeof(Box));
+  uint32_t* dtb = (uint32_t*)c->dalloc((size_t)NT * 4);
   uint32_t* bad = (uint32_t*)c->dalloc(256);
-  if (!c->cnt[0] || !c->cnt[1] || !c->cnt[2] || !c->status || !c->tot || !c->emb_mass || !bad)
+  if (!c->cnt[0] || !c->cnt[1] || !c->cnt[2] || !c->status || !c->tot || !c->emb_mass || !dboxes ||
+      !dtb || !bad)
     return cleanup(fail(MPCD_ENOMEM, "device allocation failed"));
-  const uint32_t st_init[8] = {0u, 0u, 0xFFFFFFFFu, 0u, 0u, 0u, 0u, 0u};
-  if (hipMemsetAsync(c->cnt[0], 0, NT * 4, c->stream) != hipSuccess ||
-      hipMemsetAsync(c->cnt[1], 0, NT * 4, c->stream) != hipSuccess ||
-      hipMemsetAsync(c->cnt[2], 0, NT * 4, c->stream) != hipSuccess ||
-      hipMemsetAsync(bad, 0, 256, c->stream) != hipSuccess ||
-      hipMemcpyAsync(c->status, st_init, sizeof st_init, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+  if (params[0].thermostat) {
+    c->ehat = (double*)c->dalloc((size_t)NT * c->cpt * 8);
+    c->dqueue = (uint32_t*)c->dalloc((size_t)NT * c->cpt * 16);
+    c->qcount = (uint32_t*)c->dalloc((size_t)NT * 4);
+    if (!c->ehat || !c->dqueue || !c->qcount) return cleanup(fail(MPCD_ENOMEM, "device allocation failed"));
+  }
+  if (c->qcount && hipMemsetAsync(c->qcount, 0, (size_t)NT * 4, c->stream) != hipSuccess)
     return cleanup(fail(MPCD_EHIP, "hipMemset failed"));
+  c->S.boxes = dboxes;
+  c->S.tile_box = dtb;
+  const uint32_t st_init[8] = {0u, 0u, 0xFFFFFFFFu, 0u, 0u, 0u, 0u, 0u};
+  if (hipMemsetAsync(c->cnt[0], 0, (size_t)NT * 4, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->cnt[1], 0, (size_t)NT * 4, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->cnt[2], 0, (size_t)NT * 4, c->stream) != hipSuccess ||
+      hipMemsetAsync(bad, 0, 256, c->stream) != hipSuccess ||
+      hipMemcpyAsync(c->status, st_init, sizeof st_init, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipMemcpyAsync(dboxes, c->boxes.data(), (size_t)nbox * sizeof(Box), hipMemcpyHostToDevice,
+                     c->stream) != hipSuccess ||
+      hipMemcpyAsync(dtb, tile_box.data(), (size_t)NT * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return cleanup(fail(MPCD_EHIP, "create: upload of the layout failed"));
 
   // upload: host arrays are staged through temporary device buffers
   struct Src {
     const double* p;
     const double* v;
-    uint32_t n, tag0;
+    uint64_t n;
     double* tmp;
-  } src[2] = {{pos, vel, c->n_solv, 0u, nullptr}, {emb_pos, emb_vel, c->n_emb, c->n_solv, nullptr}};
+  } src[2] = {{pos, vel, (uint64_t)ns_total, nullptr}, {emb_pos, emb_vel, c->n_emb, nullptr}};
   auto free_tmp = [&]() {
     for (auto& s : src)
       if (s.tmp) {
@@ -561,18 +662,37 @@ mpcd_status mpcd_create(const mpcd_params* params, int64_t n_solvent, const doub
     s.p = s.tmp;
     s.v = s.tmp + 3 * (size_t)s.n;
   }
+  // one import launch per (box, particle kind)
+  auto import_all = [&](bool place, uint32_t cap, uint32_t* cnt) {
+    uint64_t row = 0;
+    for (uint32_t b = 0; b < c->nbox; ++b) {
+      const Box& B = c->boxes[b];
+      struct Part {
+        const double* p;
+        const double* v;
+        uint32_t n, tag0;
+      } parts[2] = {{src[0].p + 3 * row, src[0].v + 3 * row, B.n_solvent, B.tag0},
+                    {src[1].p, src[1].v, b == 0 ? c->n_emb : 0u, B.tag0 + B.n_solvent}};
+      row += B.n_solvent;
+      for (const Part& q : parts) {
+        if (q.n == 0) continue;
+        const uint32_t g = blocks_for(q.n, kGrid);
+        if (c->form == 0) {
+          if (place) k_import<0, true><<<g, kGrid, 0, c->stream>>>(c->buf[0], B, cap, q.p, q.v, q.n, q.tag0, cnt, bad);
+          else k_import<0, false><<<g, kGrid, 0, c->stream>>>(c->buf[0], B, cap, q.p, q.v, q.n, q.tag0, cnt, bad);
+        } else {
+          if (place) k_import<1, true><<<g, kGrid, 0, c->stream>>>(c->buf[0], B, cap, q.p, q.v, q.n, q.tag0, cnt, bad);
+          else k_import<1, false><<<g, kGrid, 0, c->stream>>>(c->buf[0], B, cap, q.p, q.v, q.n, q.tag0, cnt, bad);
+        }
+      }
+    }
+  };
   // pass 1: count per tile, check the box
-  for (auto& s : src) {
-    if (s.n == 0) continue;
-    if (c->form == 0)
-      k_import<0, false><<<blocks_for(s.n, kGrid), kGrid, 0, c->stream>>>(c->buf[0], B, s.p, s.v, s.n, s.tag0, c->cnt[1], bad);
-    else
-      k_import<1, false><<<blocks_for(s.n, kGrid), kGrid, 0, c->stream>>>(c->buf[0], B, s.p, s.v, s.n, s.tag0, c->cnt[1], bad);
-  }
+  import_all(false, 0u, c->cnt[1]);
   std::vector<uint32_t> cnt_h(NT);
   uint32_t hbad = 0;
   if (hipGetLastError() != hipSuccess ||
-      hipMemcpyAsync(cnt_h.data(), c->cnt[1], NT * 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipMemcpyAsync(cnt_h.data(), c->cnt[1], (size_t)NT * 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
       hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess) {
     free_tmp();
@@ -584,33 +704,30 @@ mpcd_status mpcd_create(const mpcd_params* params, int64_t n_solvent, const doub
   }
   uint32_t mx = 0;
   for (uint32_t v : cnt_h) mx = std::max(mx, v);
-  const double mean = NT ? (double)c->N / (double)NT : 0.0;
-  if ((uint32_t)params->flags & MPCD_FLAG_TIGHT_SLABS) {
-    B.cap = std::max<uint32_t>(mx, 1u);
+  uint32_t cap;
+  if ((uint32_t)params[0].flags & MPCD_FLAG_TIGHT_SLABS) {
+    cap = std::max<uint32_t>(mx, 1u);
   } else {
-    const uint64_t cap = std::max<uint64_t>((uint64_t)mx + mx / 5, (uint64_t)(mean + 8.0 * std::sqrt(mean) + 64.0));
-    B.cap = round_up(cap, 32);
+    const uint64_t want = std::max<uint64_t>((uint64_t)mx + mx / 5,
+                                             (uint64_t)(max_mean + 8.0 * std::sqrt(max_mean) + 64.0));
+    cap = round_up(want, 32);
   }
-  if ((uint64_t)B.cap * NT >= (1ull << 32) || B.cap >= kMaxCap) {
+  if ((uint64_t)cap * NT >= (1ull << 32) || cap >= kMaxCap) {
     free_tmp();
     return cleanup(fail(MPCD_ENOMEM, "slab storage beyond 2^32 slots or 2^28 per tile"));
   }
-  if ((st = alloc_slabs(c, B.cap, c->buf, c->slab_allocs)) != MPCD_OK) {
+  c->S.cap = cap;
+  mpcd_status st = alloc_slabs(c, cap, c->buf, c->slab_allocs);
+  if (st != MPCD_OK) {
     free_tmp();
     return cleanup(st);
   }
-  if (hipMemsetAsync(c->cnt[1], 0, NT * 4, c->stream) != hipSuccess) {
+  if (hipMemsetAsync(c->cnt[1], 0, (size_t)NT * 4, c->stream) != hipSuccess) {
     free_tmp();
     return cleanup(fail(MPCD_EHIP, "hipMemset failed"));
   }
   // pass 2: place
-  for (auto& s : src) {
-    if (s.n == 0) continue;
-    if (c->form == 0)
-      k_import<0, true><<<blocks_for(s.n, kGrid), kGrid, 0, c->stream>>>(c->buf[0], B, s.p, s.v, s.n, s.tag0, c->cnt[0], bad);
-    else
-      k_import<1, true><<<blocks_for(s.n, kGrid), kGrid, 0, c->stream>>>(c->buf[0], B, s.p, s.v, s.n, s.tag0, c->cnt[0], bad);
-  }
+  import_all(true, cap, c->cnt[0]);
   if (c->n_emb) {
     if (hipMemcpyAsync(c->emb_mass, emb_mass, (size_t)c->n_emb * 8,
                        pointers_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
@@ -635,11 +752,81 @@ mpcd_status mpcd_create(const mpcd_params* params, int64_t n_solvent, const doub
   return MPCD_OK;
 }
 
+// Totals of the boxes [b0, b1) from the fixed-point words (integer sums, so
+// exact and independent of the order of the boxes).
+void totals_of(const mpcd_ctx c, const std::vector<long long>& h, uint32_t b0, uint32_t b1,
+               double p[3], double* ke, double* kT) {
+  long long w[10] = {0};
+  uint64_t n = 0;
+  for (uint32_t b = b0; b < b1; ++b) {
+    for (int q = 0; q < 10; ++q) w[q] += h[10 * b + q];
+    n += c->box_n[b];
+  }
+  auto val = [&](int q) { return (double)w[2 * q] * 0x1p-20 + (double)w[2 * q + 1] * 0x1p-72; };
+  const double P0 = val(0), P1 = val(1), P2 = val(2), K = 0.5 * val(3), M = val(4);
+  if (p) {
+    p[0] = P0;
+    p[1] = P1;
+    p[2] = P2;
+  }
+  if (ke) *ke = K;
+  if (kT) *kT = (n > 1 && M > 0) ? 2.0 * (K - 0.5 * (P0 * P0 + P1 * P1 + P2 * P2) / M) / (3.0 * (double)(n - 1)) : 0.0;
+}
+
+mpcd_status read_totals(mpcd_ctx c, std::vector<long long>& h) {
+  h.assign((size_t)c->nbox * 10, 0);
+  if (!c->N) return MPCD_OK;
+  HIP_TRY(hipMemsetAsync(c->tot, 0, (size_t)c->nbox * 80, c->stream));
+  const uint32_t nb = slab_blocks(c, c->S.cap);
+  const bool em = c->n_emb > 0;
+  const Particles P = c->buf[c->cur];
+  const uint32_t* cn = c->cnt[c->ci];
+  if (c->form == 0) {
+    if (em) k_totals<0, true><<<nb, 256, 0, c->stream>>>(P, c->S, cn, c->emb_mass, c->tot, c->status);
+    else k_totals<0, false><<<nb, 256, 0, c->stream>>>(P, c->S, cn, c->emb_mass, c->tot, c->status);
+  } else {
+    if (em) k_totals<1, true><<<nb, 256, 0, c->stream>>>(P, c->S, cn, c->emb_mass, c->tot, c->status);
+    else k_totals<1, false><<<nb, 256, 0, c->stream>>>(P, c->S, cn, c->emb_mass, c->tot, c->status);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(h.data(), c->tot, (size_t)c->nbox * 80, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return MPCD_OK;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+extern "C" {
+
+const char* mpcd_last_error(void) { return g_err.c_str(); }
+
+mpcd_status mpcd_create(const mpcd_params* params, int64_t n_solvent, const double* pos,
+                        const double* vel, int64_t n_embedded, const double* emb_pos,
+                        const double* emb_vel, const double* emb_mass,
+                        int32_t pointers_on_device, void* hip_stream, mpcd_ctx* out) {
+  if (n_solvent < 0 || n_embedded < 0) {
+    g_err.clear();
+    if (out) *out = nullptr;
+    return fail(MPCD_EINVAL, "negative particle count");
+  }
+  return create_impl(1, params, &n_solvent, pos, vel, n_embedded, emb_pos, emb_vel, emb_mass,
+                     pointers_on_device, hip_stream, out);
+}
+
+mpcd_status mpcd_create_batch(int32_t n_boxes, const mpcd_params* params,
+                              const int64_t* n_particles, const double* pos, const double* vel,
+                              int32_t pointers_on_device, void* hip_stream, mpcd_ctx* out) {
+  return create_impl(n_boxes, params, n_particles, pos, vel, 0, nullptr, nullptr, nullptr,
+                     pointers_on_device, hip_stream, out);
+}
+
 void mpcd_destroy(mpcd_ctx c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   free_all(c->allocs);
   free_all(c->slab_allocs);
+  if (c->shifts) (void)hipFree(c->shifts);
   for (auto& v : c->ev_used)
     for (auto& pr : v) {
       (void)hipEventDestroy(pr.first);
@@ -655,9 +842,9 @@ mpcd_status mpcd_stream(mpcd_ctx c) {
   if (c->phase != Phase::Idle) return fail(MPCD_ESTATE, "mpcd_stream: expected the state after create or collide");
   if (c->N) {
     ProfScope ps(c, 1);
-    const uint32_t nb = slab_blocks(c, c->box.cap);
-    if (c->form == 0) k_stream<0><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->box, c->cnt[c->ci], c->status);
-    else k_stream<1><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->box, c->cnt[c->ci], c->status);
+    const uint32_t nb = slab_blocks(c, c->S.cap);
+    if (c->form == 0) k_stream<0><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->S, c->cnt[c->ci], c->status);
+    else k_stream<1><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->S, c->cnt[c->ci], c->status);
     HIP_TRY(hipGetLastError());
   }
   c->phase = Phase::Streamed;
@@ -668,6 +855,7 @@ mpcd_status mpcd_bin(mpcd_ctx c) {
   ST_TRY(check_ctx(c));
   if (c->phase != Phase::Streamed) return fail(MPCD_ESTATE, "mpcd_bin: expected a preceding mpcd_stream");
   if (c->step >= 0xFFFFFFFFull) return fail(MPCD_ERANGE, "step counter beyond 2^32 - 1");
+  ST_TRY(ensure_shifts(c, c->step, 1));
   ST_TRY(run_launches(c, {Launch{Op::Bin, c->step}}));
   c->phase = Phase::Binned;
   c->have_bin = true;
@@ -678,6 +866,7 @@ mpcd_status mpcd_bin(mpcd_ctx c) {
 mpcd_status mpcd_collide(mpcd_ctx c) {
   ST_TRY(check_ctx(c));
   if (c->phase != Phase::Binned) return fail(MPCD_ESTATE, "mpcd_collide: expected a preceding mpcd_bin");
+  ST_TRY(ensure_shifts(c, c->step, 1));
   ST_TRY(launch_draw(c, c->step, 0));
   ST_TRY(launch_tile(c, Op::Collide, c->step, 0));
   c->step += 1;
@@ -691,8 +880,9 @@ mpcd_status mpcd_step(mpcd_ctx c, int64_t nsteps) {
   if (c->phase != Phase::Idle) return fail(MPCD_ESTATE, "mpcd_step: expected the state after create or collide");
   if (nsteps == 0) return MPCD_OK;
   if (c->step + (uint64_t)nsteps > 0xFFFFFFFFull) return fail(MPCD_ERANGE, "step counter beyond 2^32 - 1");
+  ST_TRY(ensure_shifts(c, c->step, (uint64_t)nsteps + 1));
   std::vector<Launch> L;
-  L.reserve((size_t)nsteps + 1);
+  L.reserve(2 * (size_t)nsteps + 1);
   L.push_back({Op::BinStream, c->step});
   for (int64_t k = 0; k < nsteps; ++k) {
     if (c->p.thermostat) L.push_back({Op::Draw, c->step + (uint64_t)k});
@@ -718,11 +908,11 @@ mpcd_status mpcd_get_state(mpcd_ctx c, double* pos, double* vel, int32_t on_devi
     dp = tmp;
     dv = tmp + 3 * (size_t)c->N;
   }
-  const uint32_t nb = slab_blocks(c, c->box.cap);
+  const uint32_t nb = slab_blocks(c, c->S.cap);
   if (c->form == 0)
-    k_export<0><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->box, c->cnt[c->ci], dp, dv);
+    k_export<0><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->S, c->cnt[c->ci], dp, dv);
   else
-    k_export<1><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->box, c->cnt[c->ci], dp, dv);
+    k_export<1><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->S, c->cnt[c->ci], dp, dv);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && tmp) {
     e = hipMemcpyAsync(pos, dp, (size_t)c->N * 24, hipMemcpyDeviceToHost, c->stream);
@@ -737,7 +927,7 @@ mpcd_status mpcd_get_state(mpcd_ctx c, double* pos, double* vel, int32_t on_devi
 mpcd_status mpcd_get_cells(mpcd_ctx c, int32_t* cell_of_tag, int32_t* counts, int32_t on_device) {
   ST_TRY(check_ctx(c));
   if (!c->have_bin) return fail(MPCD_ESTATE, "mpcd_get_cells: nothing has been binned");
-  const size_t C = c->box.ncells;
+  const size_t C = c->ncells;
   int32_t* dcell = cell_of_tag;
   int32_t* dcnt = counts;
   int32_t* tmp = nullptr;
@@ -748,15 +938,17 @@ mpcd_status mpcd_get_cells(mpcd_ctx c, int32_t* cell_of_tag, int32_t* counts, in
   }
   hipError_t e = hipSuccess;
   if (dcnt && C) e = hipMemsetAsync(dcnt, 0, C * 4, c->stream);
-  double s[3];
-  float s32[3];
-  shift_for(c, c->last_bin_step, s, s32);
   if (e == hipSuccess && c->N && (dcell || dcnt)) {
-    const uint32_t nb = slab_blocks(c, c->box.cap);
+    if (ensure_shifts(c, c->last_bin_step, 1) != MPCD_OK) {
+      if (tmp) (void)hipFree(tmp);
+      return MPCD_EHIP;
+    }
+    const uint32_t nb = slab_blocks(c, c->S.cap);
+    const ShiftEntry* sh = shift_at(c, c->last_bin_step);
     if (c->form == 0)
-      k_cells<0><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->box, c->cnt[c->ci], s[0], s[1], s[2], s32[0], s32[1], s32[2], dcell, (uint32_t*)dcnt);
+      k_cells<0><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->S, c->cnt[c->ci], sh, dcell, (uint32_t*)dcnt);
     else
-      k_cells<1><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->box, c->cnt[c->ci], s[0], s[1], s[2], s32[0], s32[1], s32[2], dcell, (uint32_t*)dcnt);
+      k_cells<1><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->S, c->cnt[c->ci], sh, dcell, (uint32_t*)dcnt);
     e = hipGetLastError();
   }
   if (e == hipSuccess && tmp) {
@@ -773,15 +965,16 @@ static mpcd_status cell_diag(mpcd_ctx c, double* mass, double* mom, double* ek, 
                              double* xi, int32_t on_device) {
   ST_TRY(check_ctx(c));
   if (c->phase != Phase::Binned) return fail(MPCD_ESTATE, "cell diagnostics need the binned state");
-  const size_t C = c->box.ncells;
+  const size_t C = c->ncells;
   if (C == 0) return MPCD_OK;
+  ST_TRY(ensure_shifts(c, c->step, 1));
   double* tmp = nullptr;
   HIP_TRY(hipMalloc(&tmp, C * 8 * 9));
   TileArgs a = tile_args(c);
   a.cnt_out = nullptr;
   a.cnt_clear = nullptr;
   a.step = (uint32_t)c->step;
-  shift_for(c, c->step, a.s, a.s32);
+  a.sh = shift_at(c, c->step);
   a.d_mass = tmp;
   a.d_mom = tmp + C;
   a.d_ek = tmp + 4 * C;
@@ -820,9 +1013,59 @@ mpcd_status mpcd_get_cell_draws(mpcd_ctx c, double* axis, double* xi, int32_t on
 mpcd_status mpcd_get_shift(mpcd_ctx c, uint64_t n, double s[3]) {
   ST_TRY(check_ctx(c));
   if (!s) return fail(MPCD_EINVAL, "s is NULL");
-  float s32[3];
-  shift_for(c, n, s, s32);
+  shift_for(c, 0, n, s);
   return MPCD_OK;
+}
+
+mpcd_status mpcd_get_box(mpcd_ctx c, int32_t box, int64_t* first_tag, int64_t* n_particles,
+                         int64_t* first_cell, int64_t* n_cells, double shift_of_step[3],
+                         uint64_t step) {
+  ST_TRY(check_ctx(c));
+  if (box < 0 || (uint32_t)box >= c->nbox) return fail(MPCD_EINVAL, "box %d out of range", box);
+  const Box& B = c->boxes[box];
+  if (first_tag) *first_tag = B.tag0;
+  if (n_particles) *n_particles = c->box_n[box];
+  if (first_cell) *first_cell = B.cell0;
+  if (n_cells) *n_cells = B.ncells;
+  if (shift_of_step) shift_for(c, (uint32_t)box, step, shift_of_step);
+  return MPCD_OK;
+}
+
+mpcd_status mpcd_get_velocity_field(mpcd_ctx c, double* u, double* mass, int32_t on_device) {
+  ST_TRY(check_ctx(c));
+  const size_t C = c->ncells;
+  if (C == 0 || (!u && !mass)) return take_err(c);
+  unsigned long long* acc = nullptr;
+  HIP_TRY(hipMalloc(&acc, C * 64 + (on_device ? 0 : C * 32)));
+  double* du = on_device ? u : (u ? (double*)(acc + 8 * C) : nullptr);
+  double* dm = on_device ? mass : (mass ? (double*)(acc + 8 * C) + 3 * C : nullptr);
+  hipError_t e = hipMemsetAsync(acc, 0, C * 64, c->stream);
+  if (e == hipSuccess && c->N) {
+    const uint32_t nb = slab_blocks(c, c->S.cap);
+    const Particles P = c->buf[c->cur];
+    const uint32_t* cn = c->cnt[c->ci];
+    const bool em = c->n_emb > 0;
+    if (c->form == 0) {
+      if (em) k_field<0, true><<<nb, 256, 0, c->stream>>>(P, c->S, cn, c->emb_mass, acc, c->status);
+      else k_field<0, false><<<nb, 256, 0, c->stream>>>(P, c->S, cn, c->emb_mass, acc, c->status);
+    } else {
+      if (em) k_field<1, true><<<nb, 256, 0, c->stream>>>(P, c->S, cn, c->emb_mass, acc, c->status);
+      else k_field<1, false><<<nb, 256, 0, c->stream>>>(P, c->S, cn, c->emb_mass, acc, c->status);
+    }
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    k_field_finish<<<blocks_for(C, 256), 256, 0, c->stream>>>(acc, C, du, dm);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && !on_device) {
+    if (u) e = hipMemcpyAsync(u, du, C * 24, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && mass) e = hipMemcpyAsync(mass, dm, C * 8, hipMemcpyDeviceToHost, c->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(acc);
+  if (e != hipSuccess) return fail(MPCD_EHIP, "velocity field: %s", hipGetErrorString(e));
+  return take_err(c);
 }
 
 mpcd_status mpcd_get_step(mpcd_ctx c, uint64_t* n) {
@@ -842,33 +1085,18 @@ mpcd_status mpcd_set_step(mpcd_ctx c, uint64_t n) {
 
 mpcd_status mpcd_totals(mpcd_ctx c, double p[3], double* ke, double* kT) {
   ST_TRY(check_ctx(c));
-  long long h[10] = {0};
-  if (c->N) {
-    HIP_TRY(hipMemsetAsync(c->tot, 0, 80, c->stream));
-    const uint32_t nb = slab_blocks(c, c->box.cap);
-    const bool em = c->n_emb > 0;
-    const Particles P = c->buf[c->cur];
-    const uint32_t* cn = c->cnt[c->ci];
-    if (c->form == 0) {
-      if (em) k_totals<0, true><<<nb, 256, 0, c->stream>>>(P, c->box, cn, c->emb_mass, c->tot, c->status);
-      else k_totals<0, false><<<nb, 256, 0, c->stream>>>(P, c->box, cn, c->emb_mass, c->tot, c->status);
-    } else {
-      if (em) k_totals<1, true><<<nb, 256, 0, c->stream>>>(P, c->box, cn, c->emb_mass, c->tot, c->status);
-      else k_totals<1, false><<<nb, 256, 0, c->stream>>>(P, c->box, cn, c->emb_mass, c->tot, c->status);
-    }
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(h, c->tot, 80, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-  }
-  auto val = [&](int q) { return (double)h[2 * q] * 0x1p-20 + (double)h[2 * q + 1] * 0x1p-72; };
-  const double P0 = val(0), P1 = val(1), P2 = val(2), K = 0.5 * val(3), M = val(4);
-  if (p) {
-    p[0] = P0;
-    p[1] = P1;
-    p[2] = P2;
-  }
-  if (ke) *ke = K;
-  if (kT) *kT = (c->N > 1 && M > 0) ? 2.0 * (K - 0.5 * (P0 * P0 + P1 * P1 + P2 * P2) / M) / (3.0 * (c->N - 1)) : 0.0;
+  std::vector<long long> h;
+  ST_TRY(read_totals(c, h));
+  totals_of(c, h, 0, c->nbox, p, ke, kT);
+  return take_err(c);
+}
+
+mpcd_status mpcd_box_totals(mpcd_ctx c, double* p, double* ke, double* kT) {
+  ST_TRY(check_ctx(c));
+  std::vector<long long> h;
+  ST_TRY(read_totals(c, h));
+  for (uint32_t b = 0; b < c->nbox; ++b)
+    totals_of(c, h, b, b + 1, p ? p + 3 * b : nullptr, ke ? ke + b : nullptr, kT ? kT + b : nullptr);
   return take_err(c);
 }
 
@@ -881,7 +1109,13 @@ mpcd_status mpcd_sync(mpcd_ctx c) {
 mpcd_status mpcd_get_sizes(mpcd_ctx c, int64_t* n_total, int64_t* n_cells) {
   ST_TRY(check_ctx(c));
   if (n_total) *n_total = c->N;
-  if (n_cells) *n_cells = c->box.ncells;
+  if (n_cells) *n_cells = (int64_t)c->ncells;
+  return MPCD_OK;
+}
+
+mpcd_status mpcd_get_n_boxes(mpcd_ctx c, int32_t* n_boxes) {
+  ST_TRY(check_ctx(c));
+  if (n_boxes) *n_boxes = (int32_t)c->nbox;
   return MPCD_OK;
 }
 
@@ -889,9 +1123,9 @@ mpcd_status mpcd_get_layout(mpcd_ctx c, int32_t tile[3], int64_t* n_tiles, int64
                             int64_t* regrows) {
   ST_TRY(check_ctx(c));
   if (tile)
-    for (int d = 0; d < 3; ++d) tile[d] = c->box.td[d];
-  if (n_tiles) *n_tiles = c->box.ntiles;
-  if (capacity) *capacity = c->box.cap;
+    for (int d = 0; d < 3; ++d) tile[d] = c->boxes[0].td[d];
+  if (n_tiles) *n_tiles = c->S.ntiles;
+  if (capacity) *capacity = c->S.cap;
   if (regrows) *regrows = c->regrows;
   return MPCD_OK;
 }

@@ -35,9 +35,7 @@ enum : uint32_t {
 
 // status[0]: error flags above; status[1]: nonzero once a slab overflowed;
 // status[2]: smallest launch sequence number that overflowed (tile kernels
-// with a larger sequence number return at once); status[ST_QUEUE]: length of
-// the thermostat draw queue.
-constexpr uint32_t ST_QUEUE = 4u;
+// with a larger sequence number return at once).
 struct Box {
   int n[3];
   double L[3];
@@ -54,8 +52,27 @@ struct Box {
   uint32_t lm[3];      // cell -> cell inside its tile: c & lm (td - 1, or all ones if nt == 1)
   uint32_t m_td0, m_td01;   // ceil(2^24 / td[0]), ceil(2^24 / (td[0] td[1]))
   double inv_nt0, inv_nt01; // 1 / nt[0], 1 / (nt[0] nt[1])
-  uint32_t ntiles;
-  uint32_t cap;        // slots per tile
+  uint32_t ntiles;     // tiles of this box
+  uint32_t tile0;      // its first tile in the slab arrays
+  uint32_t tag0;       // its first particle tag
+  uint32_t cell0;      // its first cell in per-cell outputs
+};
+
+// Several independent boxes share one set of slabs: box b owns the tiles
+// [tile0, tile0 + ntiles) (padded so that every box starts at a multiple of
+// 4 tiles), its particles carry the tags [tag0, tag0 + n).
+struct Slabs {
+  const Box* boxes;          // per box, device memory
+  const uint32_t* tile_box;  // tile -> box
+  uint32_t ntiles;           // all tiles, padding included
+  uint32_t cap;              // slots per tile
+};
+
+// Grid shift of one box for one step (sec. 2), in FP64 and rounded to FP32.
+struct ShiftEntry {
+  double s[3];
+  float s32[3];
+  float pad;
 };
 
 struct Particles {
@@ -317,16 +334,14 @@ constexpr int tq_for(int cpt) { return cpt == 64 ? 3 : 4; }
 
 struct TileArgs {
   Particles in, out;
-  Box B;
+  Slabs S;
   const uint32_t* cnt_in;   // occupancy of the input slabs
   uint32_t* cnt_out;        // occupancy of the output slabs (scatter modes)
   uint32_t* cnt_clear;      // cleared for this tile (scatter modes)
   const double* emb_mass;
   uint32_t step;            // counter of the collision
-  double s[3];              // shift binning the input (collide) or output (bin)
-  float s32[3];
-  double sn[3];             // shift of the next step (collide + scatter)
-  float sn32[3];
+  const ShiftEntry* sh;     // per box: shift binning the input (collide) or output (bin)
+  const ShiftEntry* shn;    // per box: shift of the next step (collide + scatter)
   uint32_t* status;
   uint32_t seq;             // launch sequence number within one API call
   const double* ehat;       // thermostat draws of this collision, [tile][CPT]
@@ -392,25 +407,34 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
   __shared__ uint32_t s_btile[27];
   __shared__ uint32_t s_quit;
 
-  const Box& B = A.B;
   const uint32_t tid = threadIdx.x;
-  const uint32_t T = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t T = xcd_remap(blockIdx.x, gridDim.x);  // tile, all boxes
+  const uint32_t bx = A.S.tile_box[T];
+  const Box B = A.S.boxes[bx];  // a copy: loaded once, not re-read after stores
+  const uint32_t cap = A.S.cap;
   int t3[3];
-  tile_coords(B, T, t3);
+  tile_coords(B, T - B.tile0, t3);
+  const bool real_tile = T - B.tile0 < B.ntiles;  // else padding between boxes (empty)
+  // this box's shifts, copied once: binning the input (or the output in
+  // MODE_BIN), and binning the next step's input (MODE_COLLIDE_SCATTER)
+  const ShiftEntry sh0 = A.sh[bx];
+  ShiftEntry sh1{};
+  if constexpr (MODE == MODE_COLLIDE_SCATTER) sh1 = A.shn[bx];
+  const double* sd = sh0.s;
+  const float* sd32 = sh0.s32;
 
   // The status word, the occupancy and then the tile's particles are loaded
   // before the first barrier, so their latencies overlap. A block quits
   // after it if an earlier launch of this call overflowed a slab (launches
   // of the failing one itself run to the end, so its counts are complete).
   if (tid == 0) s_quit = (A.status[1] != 0u && A.status[2] < A.seq) ? 1u : 0u;
-  if (tid == 0 && T == 0u) A.status[ST_QUEUE] = 0u;  // draw queue of this collision consumed
-  const uint32_t cnt = min(A.cnt_in[T], B.cap);
+  const uint32_t cnt = min(A.cnt_in[T], cap);
   const uint32_t nreg = min(cnt, (uint32_t)TREG);
-  const size_t tbase = (size_t)T * B.cap;
+  const size_t tbase = (size_t)T * cap;
   const Particles In = tile_view<FORM>(A.in, tbase);
   if (tid < 27u) {
     s_bincnt[tid] = 0u;
-    if constexpr (SCAT) s_btile[tid] = bin_tile(B, t3, tid);
+    if constexpr (SCAT) s_btile[tid] = B.tile0 + bin_tile(B, t3, tid);
   }
   if constexpr (COLL) {
     for (uint32_t t = tid; t < (uint32_t)(NROW * CC); t += TT) (&s_acc[0][0])[t] = 0ull;
@@ -421,8 +445,12 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
   bool bad = false;
 
   auto mass_of = [&](uint32_t tag) -> double {
-    if constexpr (EMB) return tag >= B.n_solvent ? A.emb_mass[tag - B.n_solvent] : B.mass;
-    else return B.mass;
+    if constexpr (EMB) {
+      const uint32_t i = tag - B.tag0;
+      return i >= B.n_solvent ? A.emb_mass[i - B.n_solvent] : B.mass;
+    } else {
+      return B.mass;
+    }
   };
   // global index of local cell l, and whether the cell exists (the last
   // tile along an axis may be partial)
@@ -430,7 +458,8 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
     uint32_t l3[3];
     local_coords(B, l, l3);
     const int g[3] = {t3[0] * B.td[0] + (int)l3[0], t3[1] * B.td[1] + (int)l3[1], t3[2] * B.td[2] + (int)l3[2]};
-    ok = l < (uint32_t)CPT && l3[2] < (uint32_t)B.td[2] && g[0] < B.n[0] && g[1] < B.n[1] && g[2] < B.n[2];
+    ok = real_tile && l < (uint32_t)CPT && l3[2] < (uint32_t)B.td[2] && g[0] < B.n[0] && g[1] < B.n[1] &&
+         g[2] < B.n[2];
     return ok ? cell_index(B, g) : 0u;
   };
 
@@ -516,10 +545,10 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
         } else {
           int c[3];
           r[q].cell3(B, sd, sd32, c);
-          dt = tile_index(B, c);
+          dt = B.tile0 + tile_index(B, c);
           slot = atomicAdd(&A.cnt_out[dt], 1u);
         }
-        if (slot < B.cap) put((size_t)dt * B.cap + slot, w[q], tg[q], r[q], info[q] & 255u);
+        if (slot < cap) put((size_t)dt * cap + slot, w[q], tg[q], r[q], info[q] & 255u);
         else overflow();
       }
     }
@@ -531,9 +560,9 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
     rr.cell3(B, sd, sd32, c);
     uint32_t lcell;
     (void)dest_bin(B, t3, c, lcell);
-    const uint32_t dt = tile_index(B, c);
+    const uint32_t dt = B.tile0 + tile_index(B, c);
     const uint32_t slot = atomicAdd(&A.cnt_out[dt], 1u);
-    if (slot < B.cap) put((size_t)dt * B.cap + slot, w, tag, rr, lcell);
+    if (slot < cap) put((size_t)dt * cap + slot, w, tag, rr, lcell);
     else overflow();
   };
 
@@ -543,14 +572,14 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
       for (int q = 0; q < TQ; ++q)
         if (tid + (uint32_t)(q * TT) < nreg) r[q].stream(B, v[q], err);
     }
-    scatter(A.s, A.s32, v);
+    scatter(sd, sd32, v);
     for (uint32_t k = TREG + tid; k < cnt; k += TT) {
       VT vv[3];
       load_vel<FORM>(In, k, vv);
       Pos<FORM> rr;
       rr.load(In, k);
       if (STREAM_IN) rr.stream(B, vv, err);
-      scatter_one(rr, A.s, A.s32, vv, ld(In.tag, k));
+      scatter_one(rr, sd, sd32, vv, ld(In.tag, k));
     }
   } else {
     // ---- cell sums: count, momentum (and mass) in exact fixed point
@@ -618,14 +647,15 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
                            nc > 0u ? s_R[2][tid] : 0.0};
       if constexpr (MODE == MODE_DIAG) {
         if (cok) {
-          A.d_mass[gcell] = nc > 0u ? cell_mass(tid, nc) : 0.0;
+          const size_t oc = (size_t)B.cell0 + gcell;
+          A.d_mass[oc] = nc > 0u ? cell_mass(tid, nc) : 0.0;
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
-            A.d_mom[3u * gcell + d] = AC::value(s_acc[RP + NL * d][tid], s_acc[RP + NL * d + NL - 1][tid]);
-            A.d_axis[3u * gcell + d] = n[d];
+            A.d_mom[3u * oc + d] = AC::value(s_acc[RP + NL * d][tid], s_acc[RP + NL * d + NL - 1][tid]);
+            A.d_axis[3u * oc + d] = n[d];
           }
-          A.d_ek[gcell] = ek;
-          A.d_xi[gcell] = xi;
+          A.d_ek[oc] = ek;
+          A.d_xi[oc] = xi;
         }
       } else {
         double R[9];
@@ -666,7 +696,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
           }
         }
       }
-      if constexpr (MODE == MODE_COLLIDE_SCATTER) scatter(A.sn, A.sn32, v);
+      if constexpr (MODE == MODE_COLLIDE_SCATTER) scatter(sh1.s, sh1.s32, v);
       for (uint32_t k = TREG + tid; k < cnt; k += TT) {
         VT vv[3], ww[3];
         load_vel<FORM>(In, k, vv);
@@ -682,7 +712,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
           st(Out.lc, k, (uint8_t)lc);
         } else {
           rr.stream(B, ww, err);
-          scatter_one(rr, A.sn, A.sn32, ww, ld(In.tag, k));
+          scatter_one(rr, sh1.s, sh1.s32, ww, ld(In.tag, k));
         }
       }
     }
@@ -697,26 +727,32 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
 // local-cell bytes of the tiles' slabs and makes attempt 0 of the draw
 // E_hat ~ Gamma(3 (N_c - 1) / 2, kT) for every cell with N_c >= 2, up to the
 // squeeze test. Accepted draws are written to ehat[T * CPT + l]; a cell whose
-// attempt 0 needs the full test or is rejected (a few per cent) goes to a
-// queue in global memory, {slot, cell, N_c}. k_draw_rest runs the sampler for
-// the queued cells from attempt 0 on, one thread per cell; the result is the
-// sequential sampler's either way. Cells with fewer than two particles get -1.
-// The queue length lives in status[4]; every k_tile launch clears it, so it
-// is zero again when the next collision's k_draw runs.
+// attempt 0 needs the full test or is rejected (a few per cent) goes to the
+// block's own segment of a queue, {slot, cell, N_c, box}, and the segment's
+// length to qcount[block] (no global atomics). k_draw_rest, one block per
+// k_draw block, runs the sampler for the queued cells from attempt 0 on, one
+// thread per cell; the result is the sequential sampler's either way. Cells
+// with fewer than two particles get -1.
 constexpr int DT = 256;
 
 template <int CPT>
-__global__ __launch_bounds__(DT) void k_draw(Particles P, Box B, const uint32_t* __restrict__ cnt_in,
+__global__ __launch_bounds__(DT) void k_draw(Particles P, Slabs S, const uint32_t* __restrict__ cnt_in,
                                              uint32_t step, double* __restrict__ ehat,
-                                             uint32_t* __restrict__ queue, uint32_t* status,
-                                             uint32_t seq) {
-  constexpr int TPB = DT / CPT;  // tiles per block
+                                             uint32_t* __restrict__ queue, uint32_t* __restrict__ qcount,
+                                             uint32_t* status, uint32_t seq) {
+  constexpr int TPB = DT / CPT;  // tiles per block (boxes start at multiples of 4 tiles)
   constexpr int LQ = 4;          // local-cell bytes per tile and thread loaded at once
   __shared__ uint32_t s_n[DT];
+  __shared__ uint32_t s_qn;
   __shared__ uint32_t s_quit;
   const uint32_t tid = threadIdx.x;
   const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
-  if (tid == 0) s_quit = (status[1] != 0u && status[2] < seq) ? 1u : 0u;
+  const uint32_t bx = S.tile_box[min(b * TPB, S.ntiles - 1u)];
+  const Box B = S.boxes[bx];
+  if (tid == 0) {
+    s_quit = (status[1] != 0u && status[2] < seq) ? 1u : 0u;
+    s_qn = 0u;
+  }
   s_n[tid] = 0u;
 
   // occupancies: all loads of the block issued together, then the counts
@@ -725,8 +761,8 @@ __global__ __launch_bounds__(DT) void k_draw(Particles P, Box B, const uint32_t*
 #pragma unroll
   for (int i = 0; i < TPB; ++i) {
     const uint32_t T = b * TPB + i;
-    cnt[i] = T < B.ntiles ? min(cnt_in[T], B.cap) : 0u;
-    const uint8_t* lc = P.lc + (size_t)T * B.cap;
+    cnt[i] = T < S.ntiles ? min(cnt_in[T], S.cap) : 0u;
+    const uint8_t* lc = P.lc + (size_t)T * S.cap;
 #pragma unroll
     for (int q = 0; q < LQ; ++q) {
       const uint32_t k = tid + (uint32_t)(q * DT);
@@ -740,7 +776,7 @@ __global__ __launch_bounds__(DT) void k_draw(Particles P, Box B, const uint32_t*
 #pragma unroll
     for (int q = 0; q < LQ; ++q)
       if (tid + (uint32_t)(q * DT) < cnt[i]) atomicAdd(&s_n[i * CPT + (v[i][q] & (uint32_t)(CPT - 1))], 1u);
-    const uint8_t* lc = P.lc + (size_t)(b * TPB + i) * B.cap;
+    const uint8_t* lc = P.lc + (size_t)(b * TPB + i) * S.cap;
     for (uint32_t k = tid + (uint32_t)(LQ * DT); k < cnt[i]; k += DT)
       atomicAdd(&s_n[i * CPT + ((uint32_t)ld(lc, k) & (uint32_t)(CPT - 1))], 1u);
   }
@@ -748,13 +784,14 @@ __global__ __launch_bounds__(DT) void k_draw(Particles P, Box B, const uint32_t*
 
   // this thread's cell
   const uint32_t T = b * TPB + tid / (uint32_t)CPT, l = tid % (uint32_t)CPT;
+  const uint32_t Tl = T - B.tile0;  // tile within the box (pad tiles: >= B.ntiles)
   int t3[3];
-  tile_coords(B, T, t3);
+  tile_coords(B, Tl, t3);
   uint32_t l3[3];
   local_coords(B, l, l3);
   const int g3[3] = {t3[0] * B.td[0] + (int)l3[0], t3[1] * B.td[1] + (int)l3[1], t3[2] * B.td[2] + (int)l3[2]};
-  const bool ok = T < B.ntiles && l3[2] < (uint32_t)B.td[2] && g3[0] < B.n[0] && g3[1] < B.n[1] &&
-                  g3[2] < B.n[2];
+  const bool ok = T < S.ntiles && Tl < B.ntiles && l3[2] < (uint32_t)B.td[2] && g3[0] < B.n[0] &&
+                  g3[1] < B.n[1] && g3[2] < B.n[2];
   const uint32_t nc = ok ? s_n[tid] : 0u;
   const uint32_t gc = ok ? cell_index(B, g3) : 0u;
   double e = -1.0;
@@ -766,32 +803,34 @@ __global__ __launch_bounds__(DT) void k_draw(Particles P, Box B, const uint32_t*
     if (r == GQ_ACCEPT) e = d * V * B.kT;
     else pend = true;
   }
-  // queue the pending cells: one global atomic per wave
+  // queue the pending cells in this block's segment: one LDS atomic per wave
   const unsigned long long m = __ballot(pend);
   if (m) {
     const uint32_t lane = tid & 63u;
     const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
     const uint32_t leader = (uint32_t)__ffsll((long long)m) - 1u;
     uint32_t base = 0u;
-    if (lane == leader) base = atomicAdd(&status[ST_QUEUE], (uint32_t)__popcll(m));
+    if (lane == leader) base = atomicAdd(&s_qn, (uint32_t)__popcll(m));
     base = (uint32_t)__builtin_amdgcn_readlane((int)base, (int)leader);
-    if (pend) {
-      const size_t i = (size_t)(base + below) * 3u;
-      queue[i] = T * (uint32_t)CPT + l;
-      queue[i + 1] = gc;
-      queue[i + 2] = nc;
-    }
+    if (pend)
+      reinterpret_cast<uint4*>(queue)[(size_t)b * DT + base + below] =
+          make_uint4(T * (uint32_t)CPT + l, gc, nc, bx);
   }
   if (ok && !pend) ehat[(size_t)T * CPT + l] = e;
+  __syncthreads();
+  if (tid == 0) qcount[b] = s_qn;
 }
 
-__global__ __launch_bounds__(256) void k_draw_rest(Box B, uint32_t step, double* __restrict__ ehat,
-                                                   const uint32_t* __restrict__ queue,
-                                                   uint32_t* status, uint32_t seq) {
-  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+__global__ __launch_bounds__(DT) void k_draw_rest(const Box* __restrict__ boxes, uint32_t step,
+                                                  double* __restrict__ ehat,
+                                                  const uint32_t* __restrict__ queue,
+                                                  const uint32_t* __restrict__ qcount,
+                                                  uint32_t* status, uint32_t seq) {
   if (status[1] != 0u && status[2] < seq) return;
-  if (i >= status[ST_QUEUE]) return;
-  const uint32_t slot = queue[3u * (size_t)i], gc = queue[3u * (size_t)i + 1], nc = queue[3u * (size_t)i + 2];
+  if (threadIdx.x >= qcount[blockIdx.x]) return;
+  const uint4 q = reinterpret_cast<const uint4*>(queue)[(size_t)blockIdx.x * DT + threadIdx.x];
+  const uint32_t slot = q.x, gc = q.y, nc = q.z;
+  const Box& B = boxes[q.w];
   bool cap = false;
   ehat[slot] = gamma_mt(1.5 * (double)(nc - 1u), gc, step, B.k0, B.k1, B.kT, cap, 0u);
   if (cap) atomicOr(&status[0], ERR_GAMMA_CAP);
@@ -804,21 +843,22 @@ struct SlabIter {
   size_t i;
   bool valid;
 };
-__device__ inline SlabIter slab_slot(const Box& B, const uint32_t* cnt) {
-  const uint32_t per = (B.cap + 255u) / 256u;
+__device__ inline SlabIter slab_slot(const Slabs& S, const uint32_t* cnt) {
+  const uint32_t per = (S.cap + 255u) / 256u;
   SlabIter s;
   s.T = blockIdx.x / per;
   s.k = (blockIdx.x % per) * 256u + threadIdx.x;
-  s.i = (size_t)s.T * B.cap + s.k;
-  s.valid = s.T < B.ntiles && s.k < min(cnt[s.T], B.cap);
+  s.i = (size_t)s.T * S.cap + s.k;
+  s.valid = s.T < S.ntiles && s.k < min(cnt[s.T], S.cap);
   return s;
 }
 
 template <int FORM>
-__global__ __launch_bounds__(256) void k_stream(Particles P, Box B, const uint32_t* cnt,
+__global__ __launch_bounds__(256) void k_stream(Particles P, Slabs S, const uint32_t* cnt,
                                                 uint32_t* status) {
-  const SlabIter s = slab_slot(B, cnt);
+  const SlabIter s = slab_slot(S, cnt);
   if (!s.valid) return;
+  const Box& B = S.boxes[S.tile_box[s.T]];
   typename VelT<FORM>::T v[3];
   load_vel<FORM>(P, s.i, v);
   Pos<FORM> r;
@@ -829,43 +869,121 @@ __global__ __launch_bounds__(256) void k_stream(Particles P, Box B, const uint32
   if (e) atomicOr(&status[0], e);
 }
 
-// Cell of every particle for shift s, in tag order, and the occupancy.
+// Cell of every particle (box-local index) for the per-box shifts sh, in tag
+// order, and the occupancy (at cell0 + cell).
 template <int FORM>
-__global__ __launch_bounds__(256) void k_cells(Particles P, Box B, const uint32_t* cnt,
-                                               double s0, double s1, double s2, float t0,
-                                               float t1, float t2, int32_t* cell_of_tag,
-                                               uint32_t* counts) {
-  const SlabIter s = slab_slot(B, cnt);
+__global__ __launch_bounds__(256) void k_cells(Particles P, Slabs S, const uint32_t* cnt,
+                                               const ShiftEntry* __restrict__ sh,
+                                               int32_t* cell_of_tag, uint32_t* counts) {
+  const SlabIter s = slab_slot(S, cnt);
   if (!s.valid) return;
+  const uint32_t bx = S.tile_box[s.T];
+  const Box& B = S.boxes[bx];
   Pos<FORM> r;
   r.load(P, s.i);
-  const double sd[3] = {s0, s1, s2};
-  const float s32[3] = {t0, t1, t2};
   int c[3];
-  r.cell3(B, sd, s32, c);
+  r.cell3(B, sh[bx].s, sh[bx].s32, c);
   const uint32_t cell = cell_index(B, c);
   if (cell_of_tag) cell_of_tag[P.tag[s.i]] = (int32_t)cell;
-  if (counts) atomicAdd(&counts[cell], 1u);
+  if (counts) atomicAdd(&counts[B.cell0 + cell], 1u);
+}
+
+// Mass and momentum of every cell of the unshifted grid (the particle's home
+// cell), for the cell-averaged velocity field: exact fixed-point sums in
+// global memory, 8 words per cell (P_x, P_y, P_z, M, two limbs each), at
+// acc[8 (cell0 + cell) ...]. Integer atomics commute, so the sums do not
+// depend on the order in which particles are visited.
+template <int FORM, bool EMB>
+__global__ __launch_bounds__(256) void k_field(Particles P, Slabs S, const uint32_t* cnt,
+                                               const double* __restrict__ emb_mass,
+                                               unsigned long long* acc, uint32_t* status) {
+  const SlabIter s = slab_slot(S, cnt);
+  if (!s.valid) return;
+  const Box B = S.boxes[S.tile_box[s.T]];
+  Pos<FORM> r;
+  r.load(P, s.i);
+  int c[3];
+  r.home3(B, c);
+  const uint32_t cell = B.cell0 + cell_index(B, c);
+  typename VelT<FORM>::T v[3];
+  load_vel<FORM>(P, s.i, v);
+  double m = B.mass;
+  if constexpr (EMB) {
+    const uint32_t i = P.tag[s.i] - B.tag0;
+    if (i >= B.n_solvent) m = emb_mass[i - B.n_solvent];
+  }
+  bool bad = false;
+  const double x[4] = {m * (double)v[0], m * (double)v[1], m * (double)v[2], m};
+  unsigned long long* a = acc + 8ull * cell;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    long long hi, lo;
+    fx_split(x[q], hi, lo, bad);
+    atomicAdd(&a[2 * q], (unsigned long long)hi);
+    atomicAdd(&a[2 * q + 1], (unsigned long long)lo);
+  }
+  if (bad) atomicOr(&status[0], ERR_FIXED_RANGE);
+}
+
+// u = P / M per cell (0 where the cell is empty), and M.
+__global__ void k_field_finish(const unsigned long long* __restrict__ acc, uint64_t ncells,
+                               double* __restrict__ u, double* __restrict__ mass) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  if (i >= ncells) return;
+  const unsigned long long* a = acc + 8ull * i;
+  double w[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    Fx f;
+    f.hi = (long long)a[2 * q];
+    f.lo = (long long)a[2 * q + 1];
+    w[q] = fx_value(f);
+  }
+  if (u)
+    for (int d = 0; d < 3; ++d) u[3 * i + d] = w[3] > 0.0 ? w[d] / w[3] : 0.0;
+  if (mass) mass[i] = w[3];
+}
+
+// Grid shifts of steps n0 .. n0 + nsteps - 1 for every box: entry
+// [k * nbox + b] (zero when the shift is off).
+__global__ void k_shifts(const Box* __restrict__ boxes, uint32_t nbox, uint32_t n0,
+                         uint32_t nsteps, int32_t on, ShiftEntry* __restrict__ out) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= nbox * nsteps) return;
+  const uint32_t b = i % nbox, k = i / nbox;
+  const Box& B = boxes[b];
+  ShiftEntry e;
+  if (on) {
+    grid_shift(B.k0, B.k1, n0 + k, B.a, e.s);
+  } else {
+    e.s[0] = e.s[1] = e.s[2] = 0.0;
+  }
+  for (int d = 0; d < 3; ++d) e.s32[d] = (float)e.s[d];
+  e.pad = 0.0f;
+  out[i] = e;
 }
 
 // Net momentum, kinetic energy and mass in fixed point: block sums in LDS
 // (integer, so exact), then 64-bit atomics, which commute.
 template <int FORM, bool EMB>
-__global__ __launch_bounds__(256) void k_totals(Particles P, Box B, const uint32_t* cnt,
+__global__ __launch_bounds__(256) void k_totals(Particles P, Slabs S, const uint32_t* cnt,
                                                 const double* __restrict__ emb_mass,
                                                 long long* tot, uint32_t* status) {
   __shared__ long long red[10][256];
   Fx acc[5] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}, {0, 0}};
   bool bad = false;
-  const SlabIter s = slab_slot(B, cnt);
+  const SlabIter s = slab_slot(S, cnt);
+  // a block covers part of one tile, so of one box; totals per box
+  const uint32_t bx = S.tile_box[min(s.T, S.ntiles - 1u)];
+  const Box& B = S.boxes[bx];
   if (s.valid) {
     typename VelT<FORM>::T vs[3];
     load_vel<FORM>(P, s.i, vs);
     const double v[3] = {(double)vs[0], (double)vs[1], (double)vs[2]};
     double m = B.mass;
     if constexpr (EMB) {
-      const uint32_t tg = P.tag[s.i];
-      if (tg >= B.n_solvent) m = emb_mass[tg - B.n_solvent];
+      const uint32_t i = P.tag[s.i] - B.tag0;
+      if (i >= B.n_solvent) m = emb_mass[i - B.n_solvent];
     }
     fx_add(acc[0], m * v[0], bad);
     fx_add(acc[1], m * v[1], bad);
@@ -884,7 +1002,7 @@ __global__ __launch_bounds__(256) void k_totals(Particles P, Box B, const uint32
     __syncthreads();
   }
   if (threadIdx.x < 10)
-    atomicAdd(reinterpret_cast<unsigned long long*>(&tot[threadIdx.x]),
+    atomicAdd(reinterpret_cast<unsigned long long*>(&tot[10u * bx + threadIdx.x]),
               (unsigned long long)red[threadIdx.x][0]);
   if (bad) atomicOr(&status[0], ERR_FIXED_RANGE);
 }
@@ -894,7 +1012,7 @@ __global__ __launch_bounds__(256) void k_totals(Particles P, Box B, const uint32
 // the tile of the particle's home cell. Pass 1 (PLACE == false) only counts
 // per tile and checks the box; pass 2 writes.
 template <int FORM, bool PLACE>
-__global__ __launch_bounds__(256) void k_import(Particles P, Box B,
+__global__ __launch_bounds__(256) void k_import(Particles P, Box B, uint32_t cap,
                                                 const double* __restrict__ pos,
                                                 const double* __restrict__ vel,
                                                 uint32_t n, uint32_t tag0, uint32_t* cnt,
@@ -939,11 +1057,11 @@ __global__ __launch_bounds__(256) void k_import(Particles P, Box B,
   }
   int c[3];
   r.home3(B, c);
-  const uint32_t T = tile_index(B, c);
+  const uint32_t T = B.tile0 + tile_index(B, c);
   const uint32_t slot = atomicAdd(&cnt[T], 1u);
   if constexpr (PLACE) {
-    if (slot < B.cap) {
-      const size_t j = (size_t)T * B.cap + slot;
+    if (slot < cap) {
+      const size_t j = (size_t)T * cap + slot;
       store_vel<FORM>(P, j, w);
       P.tag[j] = tag0 + t;
       r.store(P, j);
@@ -955,11 +1073,12 @@ __global__ __launch_bounds__(256) void k_import(Particles P, Box B,
 
 // Internal form -> row-major N x 3 doubles in tag order.
 template <int FORM>
-__global__ __launch_bounds__(256) void k_export(Particles P, Box B, const uint32_t* cnt,
+__global__ __launch_bounds__(256) void k_export(Particles P, Slabs S, const uint32_t* cnt,
                                                 double* __restrict__ pos,
                                                 double* __restrict__ vel) {
-  const SlabIter s = slab_slot(B, cnt);
+  const SlabIter s = slab_slot(S, cnt);
   if (!s.valid) return;
+  const Box& B = S.boxes[S.tile_box[s.T]];
   const uint32_t t = P.tag[s.i];
   if constexpr (FORM == 0) {
 #pragma unroll
@@ -979,15 +1098,15 @@ __global__ __launch_bounds__(256) void k_export(Particles P, Box B, const uint32
 }
 
 // Copy the valid slots of every tile from slabs of capacity old_cap to slabs
-// of capacity B.cap (B.cap >= old_cap); used when slabs are enlarged.
+// of capacity S.cap (S.cap >= old_cap); used when slabs are enlarged.
 template <int FORM>
-__global__ __launch_bounds__(256) void k_repack(Particles src, Particles dst, Box B,
+__global__ __launch_bounds__(256) void k_repack(Particles src, Particles dst, Slabs S,
                                                 uint32_t old_cap, const uint32_t* cnt) {
   const uint32_t per = (old_cap + 255u) / 256u;
   const uint32_t T = blockIdx.x / per;
   const uint32_t k = (blockIdx.x % per) * 256u + threadIdx.x;
-  if (T >= B.ntiles || k >= min(cnt[T], old_cap)) return;
-  const size_t i = (size_t)T * old_cap + k, j = (size_t)T * B.cap + k;
+  if (T >= S.ntiles || k >= min(cnt[T], old_cap)) return;
+  const size_t i = (size_t)T * old_cap + k, j = (size_t)T * S.cap + k;
   typename VelT<FORM>::T v[3];
   load_vel<FORM>(src, i, v);
   store_vel<FORM>(dst, j, v);

@@ -82,3 +82,33 @@ def test_null_context_is_an_error(lib):
 def test_bad_copy_and_philox_arguments(lib):
     assert lib.mpcd_copy_kernel(None, None, -1, None) == binding.MPCD_EINVAL
     assert lib.mpcd_philox4x32_10(None, -5, 0, None) == binding.MPCD_EINVAL
+
+
+def _create_batch(lib, plist, counts):
+    arr = (binding.Params * len(plist))(*plist)
+    n = np.asarray(counts, dtype=np.int64)
+    tot = int(n.sum())
+    pos = np.full((max(tot, 1), 3), 0.5)
+    vel = np.zeros((max(tot, 1), 3))
+    ctx = ctypes.c_void_p()
+    st = lib.mpcd_create_batch(len(plist), arr, n.ctypes.data_as(ctypes.c_void_p),
+                               pos.ctypes.data_as(ctypes.c_void_p),
+                               vel.ctypes.data_as(ctypes.c_void_p), 0, None, ctypes.byref(ctx))
+    return st, ctx
+
+
+def test_batch_create_rejects_bad_boxes(lib):
+    """Validation happens before any device work: no GPU needed."""
+    good = m.make_params((4, 4, 4))
+    assert lib.mpcd_create_batch(0, None, None, None, None, 0, None,
+                                 ctypes.byref(ctypes.c_void_p())) == binding.MPCD_EINVAL
+    bad = m.make_params((4, 4, 4), dt=-1.0)
+    st, ctx = _create_batch(lib, [good, bad], [3, 3])
+    assert st == binding.MPCD_EINVAL and ctx.value is None
+    assert lib.mpcd_last_error().decode().startswith("box 1")
+    mixed = m.make_params((4, 4, 4), precision=m.FP32)
+    st, _ = _create_batch(lib, [good, mixed], [3, 3])
+    assert st == binding.MPCD_EINVAL
+    assert "must match box 0" in lib.mpcd_last_error().decode()
+    st, _ = _create_batch(lib, [good, good], [3, -1])
+    assert st == binding.MPCD_EINVAL

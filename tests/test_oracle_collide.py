@@ -219,3 +219,26 @@ def test_collision_commutes_with_a_boost():
     assert np.array_equal(ia["cell"], ib["cell"])
     assert np.max(np.abs(vb - V0 - va)) < 64 * 200.0 * EPS
     assert np.allclose(ia["xi"], ib["xi"], rtol=1e-10)
+
+
+def test_velocity_field_pins():
+    """Cell-averaged field: a uniform flow gives that flow in every occupied
+    cell and zero elsewhere; cell masses add up to the total mass; the field
+    weighted by the cell masses gives the total momentum; one hand-placed
+    pair of particles gives their mass-weighted mean in their cell."""
+    p = srd.Params((5, 4, 3), seed=1)
+    rng = np.random.default_rng(3)
+    pos = rng.random((200, 3)) * p.L
+    mass = rng.choice([1.0, 5.0], size=200)
+    flow = np.array([0.3, -1.2, 0.05])
+    u, M = srd.velocity_field(pos, np.tile(flow, (200, 1)), mass, p)
+    occ = M > 0
+    assert np.allclose(u[occ], flow, rtol=0, atol=1e-15) and np.all(u[~occ] == 0.0)
+    assert abs(M.sum() - mass.sum()) < 1e-12
+    vel = rng.normal(size=(200, 3))
+    u, M = srd.velocity_field(pos, vel, mass, p)
+    assert np.allclose((M[:, None] * u).sum(axis=0), (mass[:, None] * vel).sum(axis=0), atol=1e-12)
+    # two particles in cell (1, 2, 0): index 1 + 5 * 2 = 11
+    two = np.array([[1.2, 2.5, 0.1], [1.9, 2.0, 0.9]])
+    u, M = srd.velocity_field(two, np.array([[1.0, 0, 0], [4.0, 0, 0]]), np.array([1.0, 3.0]), p)
+    assert M[11] == 4.0 and u[11, 0] == (1.0 + 12.0) / 4.0 and np.count_nonzero(M) == 1

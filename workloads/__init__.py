@@ -80,6 +80,28 @@ def non_gaussian_fluid(n_cells, density, kT=1.0, mass=1.0, seed=1, a=1.0):
     return pos, vel
 
 
+def replica_boxes(n_rep=256, seed=1, side=(8, 64), density=(5.0, 10.0), kT=(0.5, 2.0)):
+    """Parameters of a batch of independent boxes: side n_r uniform on the
+    integers side[0]..side[1], density uniform, kT uniform, seed 1 + r (the
+    box's Philox key). Returns dicts with n_cells, density, kT, seed; the
+    particles come from fluid() with seed 1000 + r."""
+    rng = np.random.default_rng(seed)
+    n = rng.integers(side[0], side[1] + 1, size=n_rep)
+    rho = rng.uniform(density[0], density[1], size=n_rep)
+    t = rng.uniform(kT[0], kT[1], size=n_rep)
+    return [dict(n_cells=(int(n[r]),) * 3, density=float(rho[r]), kT=float(t[r]),
+                 seed=1 + r) for r in range(n_rep)]
+
+
+def replica_inputs(boxes):
+    """Add pos/vel drawn by fluid() (seed 1000 + r) to each box dict."""
+    out = []
+    for r, b in enumerate(boxes):
+        pos, vel = fluid(b["n_cells"], b["density"], kT=b["kT"], seed=1000 + r)
+        out.append(dict(b, pos=pos, vel=vel))
+    return out
+
+
 # Named workloads of the benchmark suite (sizes of the paper's benchmark
 # fluid, sec. 4 and Table 1, scaled to one GPU).
 CONFIGS = {
@@ -91,4 +113,7 @@ CONFIGS = {
     "srd_400c_rho5_beads": dict(n_cells=(400, 400, 400), density=5, kT=1.0,
                                 thermostat=False, steps=200, seed=1,
                                 chains=20000, chain_len=50, bead_mass=5.0),
+    # 256 independent boxes (replica_boxes): sides 8..64 cells, densities
+    # 5..10, kT 0.5..2, Maxwell-Boltzmann thermostat, FP32
+    "srd_batch256_fp32": dict(n_rep=256, thermostat=True, steps=500, seed=1),
 }
