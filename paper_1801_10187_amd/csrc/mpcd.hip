@@ -99,8 +99,6 @@ struct mpcd_ctx_s {
   double* emb_mass = nullptr;
   uint32_t* status = nullptr;      // [0] errors, [1] overflow, [2] failing launch
   double* ehat = nullptr;          // thermostat draws of the next collision, [tile][cpt]
-  uint32_t* dqueue = nullptr;      // cells whose draw needs more than the quick test
-  uint32_t* qcount = nullptr;      // queue segment length per draw block
   long long* tot = nullptr;        // fixed-point totals, 10 words per box
 
   ShiftEntry* shifts = nullptr;    // grid shifts of steps shift_n0 .., [step][box]
@@ -270,8 +268,6 @@ void draw_inst(mpcd_ctx c, uint64_t n, uint32_t seq) {
   constexpr uint32_t tpb = DT / CPT;
   const uint32_t nb = (c->S.ntiles + tpb - 1) / tpb;
   k_draw<CPT><<<nb, DT, 0, c->stream>>>(c->buf[c->cur], c->S, c->cnt[c->ci], (uint32_t)n, c->ehat,
-                                        c->dqueue, c->qcount, c->status, seq);
-  k_draw_rest<<<nb, DT, 0, c->stream>>>(c->S.boxes, (uint32_t)n, c->ehat, c->dqueue, c->qcount,
                                         c->status, seq);
 }
 
@@ -613,12 +609,8 @@ mpcd_status create_impl(int32_t nbox, const mpcd_params* params, const int64_t* 
     return cleanup(fail(MPCD_ENOMEM, "device allocation failed"));
   if (params[0].thermostat) {
     c->ehat = (double*)c->dalloc((size_t)NT * c->cpt * 8);
-    c->dqueue = (uint32_t*)c->dalloc((size_t)NT * c->cpt * 16);
-    c->qcount = (uint32_t*)c->dalloc((size_t)NT * 4);
-    if (!c->ehat || !c->dqueue || !c->qcount) return cleanup(fail(MPCD_ENOMEM, "device allocation failed"));
+    if (!c->ehat) return cleanup(fail(MPCD_ENOMEM, "device allocation failed"));
   }
-  if (c->qcount && hipMemsetAsync(c->qcount, 0, (size_t)NT * 4, c->stream) != hipSuccess)
-    return cleanup(fail(MPCD_EHIP, "hipMemset failed"));
   c->S.boxes = dboxes;
   c->S.tile_box = dtb;
   const uint32_t st_init[8] = {0u, 0u, 0xFFFFFFFFu, 0u, 0u, 0u, 0u, 0u};

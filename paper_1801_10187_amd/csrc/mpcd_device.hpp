@@ -206,18 +206,30 @@ __device__ inline void cell_axis(uint32_t cell, uint32_t step, uint32_t k0,
 // that reach it.
 enum { GQ_ACCEPT = 0, GQ_REJECT = 1, GQ_FULL = 2 };
 
-__device__ inline int gamma_quick(uint32_t cell, uint32_t step, uint32_t j, double c,
-                                  uint32_t k0, uint32_t k1, double& g, double& V,
-                                  double& u2) {
+// The numbers of attempt j: the Box-Muller normal g and the uniform U. They
+// depend on (cell, step, j) only, not on N_c.
+__device__ inline void gamma_numbers(uint32_t cell, uint32_t step, uint32_t j, uint32_t k0,
+                                     uint32_t k1, double& g, double& u2) {
   const U4 w = philox4x32_10(U4{cell, step, TAG_THERMO, j}, k0, k1);
   const double u0 = u01(w.x), u1 = u01(w.y);
   u2 = u01(w.z);
   g = sqrt(-2.0 * log(u0)) * cospi(2.0 * u1);
+}
+
+// The decision that needs no logarithm of U, from the attempt's numbers.
+__device__ inline int gamma_decide(double g, double u2, double c, double& V) {
   const double t = 1.0 + c * g;
   V = t * t * t;
   if (t <= 0.0) return GQ_REJECT;
   const double sq = g * g;
   return u2 < 1.0 - 0.0331 * (sq * sq) ? GQ_ACCEPT : GQ_FULL;
+}
+
+__device__ inline int gamma_quick(uint32_t cell, uint32_t step, uint32_t j, double c,
+                                  uint32_t k0, uint32_t k1, double& g, double& V,
+                                  double& u2) {
+  gamma_numbers(cell, step, j, k0, k1, g, u2);
+  return gamma_decide(g, u2, c, V);
 }
 
 __device__ inline bool gamma_full(double g, double V, double u2, double d) {

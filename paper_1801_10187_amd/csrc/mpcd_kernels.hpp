@@ -721,29 +721,29 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
   if (err) atomicOr(&A.status[0], err);
 }
 
-// Maxwell-Boltzmann draws of one collision (sec. 3.6), in two kernels.
-// k_draw: a block of DT = 256 threads takes 256 / CPT consecutive tiles, one
-// thread per cell. It counts the occupancy N_c of each cell from the
-// local-cell bytes of the tiles' slabs and makes attempt 0 of the draw
-// E_hat ~ Gamma(3 (N_c - 1) / 2, kT) for every cell with N_c >= 2, up to the
-// squeeze test. Accepted draws are written to ehat[T * CPT + l]; a cell whose
-// attempt 0 needs the full test or is rejected (a few per cent) goes to the
-// block's own segment of a queue, {slot, cell, N_c, box}, and the segment's
-// length to qcount[block] (no global atomics). k_draw_rest, one block per
-// k_draw block, runs the sampler for the queued cells from attempt 0 on, one
-// thread per cell; the result is the sequential sampler's either way. Cells
-// with fewer than two particles get -1.
+// Maxwell-Boltzmann draws of one collision (sec. 3.6). A block of DT = 256
+// threads takes 256 / CPT consecutive tiles (all of one box), one thread per
+// cell. It counts the occupancy N_c of each cell from the local-cell bytes of
+// the tiles' slabs, then runs Marsaglia and Tsang's sampler for
+// E_hat ~ Gamma(3 (N_c - 1) / 2, kT) on every cell with N_c >= 2 in two
+// stages: attempt 0 up to the squeeze on every thread; then the few cells
+// that need the logarithmic test or another attempt (a few per cent) are
+// compacted through LDS onto the first threads, which finish them in attempt
+// order. The result is the sequential sampler's either way. Output
+// ehat[T * CPT + l]; -1 for a cell with fewer than two particles.
 constexpr int DT = 256;
 
 template <int CPT>
 __global__ __launch_bounds__(DT) void k_draw(Particles P, Slabs S, const uint32_t* __restrict__ cnt_in,
                                              uint32_t step, double* __restrict__ ehat,
-                                             uint32_t* __restrict__ queue, uint32_t* __restrict__ qcount,
                                              uint32_t* status, uint32_t seq) {
   constexpr int TPB = DT / CPT;  // tiles per block (boxes start at multiples of 4 tiles)
   constexpr int LQ = 4;          // local-cell bytes per tile and thread loaded at once
   __shared__ uint32_t s_n[DT];
   __shared__ uint32_t s_qn;
+  __shared__ uint32_t s_qc[DT];  // pending: global cell index | rejected flag in bit 31 of s_qr
+  __shared__ uint32_t s_qs[DT];  // pending: slot (thread) and "rejected" flag
+  __shared__ double s_qg[DT], s_qV[DT], s_qu[DT];
   __shared__ uint32_t s_quit;
   const uint32_t tid = threadIdx.x;
   const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
@@ -769,6 +769,9 @@ __global__ __launch_bounds__(DT) void k_draw(Particles P, Slabs S, const uint32_
       v[i][q] = k < cnt[i] ? (uint32_t)ld(lc, k) : 0u;
     }
   }
+  // this thread's cell
+  const uint32_t T = b * TPB + tid / (uint32_t)CPT, l = tid % (uint32_t)CPT;
+  const size_t slot = (size_t)T * CPT + l;
   __syncthreads();
   if (s_quit) return;
 #pragma unroll
@@ -782,8 +785,6 @@ __global__ __launch_bounds__(DT) void k_draw(Particles P, Slabs S, const uint32_
   }
   __syncthreads();
 
-  // this thread's cell
-  const uint32_t T = b * TPB + tid / (uint32_t)CPT, l = tid % (uint32_t)CPT;
   const uint32_t Tl = T - B.tile0;  // tile within the box (pad tiles: >= B.ntiles)
   int t3[3];
   tile_coords(B, Tl, t3);
@@ -794,16 +795,17 @@ __global__ __launch_bounds__(DT) void k_draw(Particles P, Slabs S, const uint32_
                   g3[1] < B.n[1] && g3[2] < B.n[2];
   const uint32_t nc = ok ? s_n[tid] : 0u;
   const uint32_t gc = ok ? cell_index(B, g3) : 0u;
-  double e = -1.0;
-  bool pend = false;
+  double e = -1.0, g = 0.0, V = 0.0, u2 = 0.0;
+  int r = GQ_ACCEPT;
   if (nc >= 2u) {
     const double d = 1.5 * (double)(nc - 1u) - 1.0 / 3.0;
-    double g, V, u2;
-    const int r = gamma_quick(gc, step, 0u, 1.0 / sqrt(9.0 * d), B.k0, B.k1, g, V, u2);
+    const double c = 1.0 / sqrt(9.0 * d);
+    gamma_numbers(gc, step, 0u, B.k0, B.k1, g, u2);
+    r = gamma_decide(g, u2, c, V);
     if (r == GQ_ACCEPT) e = d * V * B.kT;
-    else pend = true;
   }
-  // queue the pending cells in this block's segment: one LDS atomic per wave
+  const bool pend = nc >= 2u && r != GQ_ACCEPT;
+  // compact the pending cells onto the first threads: one LDS atomic per wave
   const unsigned long long m = __ballot(pend);
   if (m) {
     const uint32_t lane = tid & 63u;
@@ -812,28 +814,32 @@ __global__ __launch_bounds__(DT) void k_draw(Particles P, Slabs S, const uint32_
     uint32_t base = 0u;
     if (lane == leader) base = atomicAdd(&s_qn, (uint32_t)__popcll(m));
     base = (uint32_t)__builtin_amdgcn_readlane((int)base, (int)leader);
-    if (pend)
-      reinterpret_cast<uint4*>(queue)[(size_t)b * DT + base + below] =
-          make_uint4(T * (uint32_t)CPT + l, gc, nc, bx);
+    if (pend) {
+      const uint32_t i = base + below;
+      s_qs[i] = tid | (r == GQ_REJECT ? 0x80000000u : 0u);
+      s_qc[i] = gc;
+      s_qg[i] = g;
+      s_qV[i] = V;
+      s_qu[i] = u2;
+    }
   }
-  if (ok && !pend) ehat[(size_t)T * CPT + l] = e;
+  if (ok && !pend) ehat[slot] = e;
   __syncthreads();
-  if (tid == 0) qcount[b] = s_qn;
-}
-
-__global__ __launch_bounds__(DT) void k_draw_rest(const Box* __restrict__ boxes, uint32_t step,
-                                                  double* __restrict__ ehat,
-                                                  const uint32_t* __restrict__ queue,
-                                                  const uint32_t* __restrict__ qcount,
-                                                  uint32_t* status, uint32_t seq) {
-  if (status[1] != 0u && status[2] < seq) return;
-  if (threadIdx.x >= qcount[blockIdx.x]) return;
-  const uint4 q = reinterpret_cast<const uint4*>(queue)[(size_t)blockIdx.x * DT + threadIdx.x];
-  const uint32_t slot = q.x, gc = q.y, nc = q.z;
-  const Box& B = boxes[q.w];
-  bool cap = false;
-  ehat[slot] = gamma_mt(1.5 * (double)(nc - 1u), gc, step, B.k0, B.k1, B.kT, cap, 0u);
-  if (cap) atomicOr(&status[0], ERR_GAMMA_CAP);
+  // finish the pending cells in attempt order: the full test of attempt 0,
+  // then attempts 1, 2, ... as the sequential sampler would
+  if (tid < s_qn) {
+    const uint32_t q = s_qs[tid] & 0x7FFFFFFFu;
+    const bool rejected = (s_qs[tid] >> 31) != 0u;
+    const uint32_t nq = s_n[q];
+    const double k = 1.5 * (double)(nq - 1u);
+    const double d = k - 1.0 / 3.0;
+    double res;
+    bool cap = false;
+    if (!rejected && gamma_full(s_qg[tid], s_qV[tid], s_qu[tid], d)) res = d * s_qV[tid] * B.kT;
+    else res = gamma_mt(k, s_qc[tid], step, B.k0, B.k1, B.kT, cap, 1u);
+    ehat[(size_t)(b * TPB + q / (uint32_t)CPT) * CPT + q % (uint32_t)CPT] = res;
+    if (cap) atomicOr(&status[0], ERR_GAMMA_CAP);
+  }
 }
 
 // ------------------------------------------------- elementwise over slabs
