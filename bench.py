@@ -22,6 +22,13 @@ kT 0.5..2, thermostat, FP32; 1.44 x 10^8 particles in all) stepped together:
 throughput over 500 steps in one call, and the latency of single batch steps
 (p50/p99 over 100 calls of mpcd_step(1), each waited for).
 
+    python bench.py --workload srd_serve_poisson50
+
+serves an open-loop stream of requests (Poisson, 50 per second for 60 s;
+10^4..10^7 particles log-uniform, 100..2000 steps, FP32, thermostat), each
+returning its n^3 x 3 cell-averaged velocity field: served vs offered
+throughput and request latency p50/p99.
+
 Prints one JSON line. `roofline` is for the dominant kernel (the collide
 kernel), timed with HIP events on the library's own stream during the timed
 region; `cpu_baseline` is the FP64 numpy oracle on a bounded sample.
@@ -216,6 +223,92 @@ def bench_batch(m, workloads, cfg, args):
     print(json.dumps(out), flush=True)
 
 
+def bench_serve(m, workloads, cfg, args, workers=4, stop_after=75.0):
+    """Open-loop serving: requests (workloads.serve_requests) arrive at their
+    Poisson times; `workers` host threads each take the oldest arrived
+    request, create a context for it on its own HIP stream, run its steps,
+    read its cell-averaged velocity field and destroy the context. No request
+    is started after `stop_after` seconds; those are reported as unserved.
+    Particles of a request are a slice, at a seeded offset, of one pool of
+    uniform and Gaussian numbers scaled to the request's box and kT (drawing
+    10^9 fresh numbers per second on the host would be the bottleneck)."""
+    import threading
+    import torch
+    reqs = workloads.serve_requests(rate=cfg["rate"], duration=cfg["duration"], seed=cfg["seed"])
+    npool = int(max(r["density"] * np.prod(r["n_cells"]) for r in reqs)) + 1
+    rng = np.random.default_rng(cfg["seed"])
+    upool = rng.random((2 * npool, 3))
+    gpool = rng.normal(size=(2 * npool, 3))
+    torch.cuda.init()
+    lock = threading.Lock()
+    nxt = [0]
+    done = []
+    t0 = time.perf_counter()
+
+    def worker():
+        while True:
+            with lock:
+                i = nxt[0]
+                if i >= len(reqs):
+                    return
+                nxt[0] += 1
+            r = reqs[i]
+            now = time.perf_counter() - t0
+            if now < r["t"]:
+                time.sleep(r["t"] - now)
+            if time.perf_counter() - t0 > stop_after:
+                return
+            n = int(round(r["density"] * np.prod(r["n_cells"])))
+            off = int(np.random.default_rng(5000 + i).integers(0, npool))
+            L = np.array(r["n_cells"], dtype=np.float64)
+            pos = upool[off:off + n] * L
+            pos = np.where(pos >= L, 0.0, pos)
+            vel = gpool[off:off + n] * math.sqrt(cfg["kT"])
+            vel -= vel.mean(axis=0)
+            sim = m.Sim(pos, vel, r["n_cells"], kT=cfg["kT"], seed=r["seed"], precision=m.FP32,
+                        thermostat=cfg["thermostat"])
+            try:
+                sim.step(r["steps"])
+                u, _ = sim.velocity_field()
+            finally:
+                sim.close()
+            t_end = time.perf_counter() - t0
+            with lock:
+                done.append((r["t"], t_end, n * r["steps"], u.shape[0]))
+                if len(done) % 250 == 0:
+                    print(f"[serve] {len(done)} requests done at {t_end:.1f} s", file=sys.stderr,
+                          flush=True)
+
+    threads = [threading.Thread(target=worker) for _ in range(workers)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    wall = time.perf_counter() - t0
+    lat = np.array([e - a for a, e, _, _ in done])
+    served = sum(w for _, _, w, _ in done)
+    offered = sum(r["density"] * np.prod(r["n_cells"]) * r["steps"] for r in reqs) / cfg["duration"]
+    out = {
+        "metric": "particle-updates/s (stream+bin+SRD collide) FP32 vs FP64; p99 batch latency",
+        "value": served / wall, "unit": "particle-updates/s", "n_gpus": 1,
+        "steps": int(sum(r["steps"] for r in reqs[:len(done)])), "warmup": 0,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "srd_serve_poisson50", "rate_per_s": cfg["rate"],
+                   "duration_s": cfg["duration"], "requests": len(reqs),
+                   "particles": "log-uniform 1e4..1e7", "steps": "uniform 100..2000",
+                   "density": [5, 10], "kT": cfg["kT"], "thermostat": "maxwell-boltzmann",
+                   "form": "fp32", "workers": workers, "stop_after_s": stop_after},
+        "served_requests": len(done), "unserved_requests": len(reqs) - len(done),
+        "offered_updates_per_s": offered, "served_updates_per_s": served / wall,
+        "wall_s": wall,
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3) if len(lat) else None,
+                       "p99": float(np.percentile(lat, 99) * 1e3) if len(lat) else None,
+                       "what": "request completion minus arrival, completed requests"},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,7 +320,7 @@ def main():
                     help="storage forms to time (default fp32,fp64; fp32 for the large box)")
     ap.add_argument("--workload", default=WORKLOAD,
                     choices=["srd_100c_rho10_mbthermo", "srd_400c_rho5_beads",
-                             "srd_batch256_fp32"])
+                             "srd_batch256_fp32", "srd_serve_poisson50"])
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the streaming copy kernel (1 GiB, 20 times)")
     args = ap.parse_args()
@@ -248,6 +341,8 @@ def main():
     cfg = workloads.CONFIGS[wl]
     if wl == "srd_batch256_fp32":
         return bench_batch(m, workloads, cfg, args)
+    if wl == "srd_serve_poisson50":
+        return bench_serve(m, workloads, cfg, args)
     big = wl != WORKLOAD
     if big and args.steps == 1000:
         args.steps = cfg["steps"]

@@ -102,6 +102,31 @@ def replica_inputs(boxes):
     return out
 
 
+def serve_requests(rate=50.0, duration=60.0, seed=1, n_range=(1e4, 1e7),
+                   density=(5.0, 10.0), steps=(100, 2000)):
+    """Open-loop request stream: Poisson arrivals at `rate` per second over
+    `duration` seconds (exponential gaps); per request N log-uniform on
+    n_range, density uniform, cells per axis max(2, round((N / rho)^(1/3))),
+    steps uniform on the integers steps[0]..steps[1], seed 1 + i. Returns a
+    list of dicts (t, n_cells, density, steps, seed); particles come from
+    fluid() with seed 5000 + i."""
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    i = 0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            break
+        N = math.exp(rng.uniform(math.log(n_range[0]), math.log(n_range[1])))
+        rho = rng.uniform(density[0], density[1])
+        n = max(2, int(round((N / rho) ** (1.0 / 3.0))))
+        k = int(rng.integers(steps[0], steps[1] + 1))
+        out.append(dict(t=t, n_cells=(n, n, n), density=float(rho), steps=k, seed=1 + i))
+        i += 1
+    return out
+
+
 # Named workloads of the benchmark suite (sizes of the paper's benchmark
 # fluid, sec. 4 and Table 1, scaled to one GPU).
 CONFIGS = {
@@ -116,4 +141,7 @@ CONFIGS = {
     # 256 independent boxes (replica_boxes): sides 8..64 cells, densities
     # 5..10, kT 0.5..2, Maxwell-Boltzmann thermostat, FP32
     "srd_batch256_fp32": dict(n_rep=256, thermostat=True, steps=500, seed=1),
+    # open-loop serving (serve_requests): 50 requests/s for 60 s, each a
+    # thermostatted FP32 box returning its cell-averaged velocity field
+    "srd_serve_poisson50": dict(rate=50.0, duration=60.0, seed=1, thermostat=True, kT=1.0),
 }
