@@ -329,18 +329,15 @@ mpcd_status alloc_slabs(mpcd_ctx c, uint32_t cap, Particles out[2], std::vector<
         P.v[d] = (double*)get(S * 8);
         if (!P.x[d] || !P.v[d]) return fail(MPCD_ENOMEM, "device allocation of the slabs failed");
       }
+      P.tag = (uint32_t*)get(S * 4);
+      if (!P.tag) return fail(MPCD_ENOMEM, "device allocation of the slabs failed");
     } else {
-      P.h = (uint32_t*)get(S * 4);
-      if (!P.h) return fail(MPCD_ENOMEM, "device allocation of the slabs failed");
-      for (int d = 0; d < 3; ++d) {
-        P.o[d] = (float*)get(S * 4);
-        P.vf[d] = (float*)get(S * 4);
-        if (!P.o[d] || !P.vf[d]) return fail(MPCD_ENOMEM, "device allocation of the slabs failed");
-      }
+      P.ra = (uint4*)get(S * 16);
+      P.rb = (uint4*)get(S * 16);
+      if (!P.ra || !P.rb) return fail(MPCD_ENOMEM, "device allocation of the slabs failed");
     }
-    P.tag = (uint32_t*)get(S * 4);
     P.lc = (uint8_t*)get(S);
-    if (!P.tag || !P.lc) return fail(MPCD_ENOMEM, "device allocation of the slabs failed");
+    if (!P.lc) return fail(MPCD_ENOMEM, "device allocation of the slabs failed");
   }
   return MPCD_OK;
 }

@@ -7,9 +7,11 @@
 // array per component, so a block reads and writes its tile as unit-stride
 // streams:
 //   FP64 form: x[3][S], v[3][S] double;
-//   FP32 form: h[S] home cell packed 10:10:10, o[3][S] float offset inside the
-//              home cell, v[3][S] float;
-//   tag[S] uint32 particle identity;
+//   FP32 form: two 16-byte words per particle, ra[S] = {home cell packed
+//              10:10:10, float offset inside the home cell x, y, z} and
+//              rb[S] = {float velocity x, y, z, tag}, so a lane moves a
+//              particle with two vector loads or stores;
+//   tag[S] uint32 particle identity (FP64 form; inside rb in the FP32 form);
 //   lc[S]  uint8 the particle's collision cell inside its tile, written by
 //          the launch that placed it there;      S = ntiles * cap.
 //
@@ -76,12 +78,11 @@ struct ShiftEntry {
 };
 
 struct Particles {
-  double* x[3];
+  double* x[3];  // FP64 form
   double* v[3];
-  uint32_t* h;
-  float* o[3];
-  float* vf[3];
   uint32_t* tag;
+  uint4* ra;     // FP32 form: {home cell packed 10:10:10, offset x, y, z (FP32 bits)}
+  uint4* rb;     // FP32 form: {velocity x, y, z (FP32 bits), tag}
   uint8_t* lc;   // local cell of the particle inside its tile (set by a scatter)
 };
 
@@ -126,13 +127,14 @@ __device__ inline Particles tile_view(const Particles& P, size_t off) {
     if constexpr (FORM == 0) {
       Q.x[d] = P.x[d] + off;
       Q.v[d] = P.v[d] + off;
-    } else {
-      Q.o[d] = P.o[d] + off;
-      Q.vf[d] = P.vf[d] + off;
     }
   }
-  if constexpr (FORM == 1) Q.h = P.h + off;
-  Q.tag = P.tag + off;
+  if constexpr (FORM == 0) {
+    Q.tag = P.tag + off;
+  } else {
+    Q.ra = P.ra + off;
+    Q.rb = P.rb + off;
+  }
   Q.lc = P.lc + off;
   return Q;
 }
@@ -181,29 +183,45 @@ __device__ inline int tile_coord(int c, const Box& B, int d) {
   return B.nt[d] == 1 ? 0 : (c >> B.tsh[d]);
 }
 
+// Velocity and tag of a particle. The FP32 form keeps them in one 16-byte
+// word, so a lane moves them with one vector load or store.
 template <int FORM, class I>
-__device__ inline void load_vel(const Particles& P, I i, typename VelT<FORM>::T v[3]) {
+__device__ inline void load_vt(const Particles& P, I i, typename VelT<FORM>::T v[3], uint32_t& tag) {
   if constexpr (FORM == 0) {
     v[0] = ld(P.v[0], i);
     v[1] = ld(P.v[1], i);
     v[2] = ld(P.v[2], i);
+    tag = ld(P.tag, i);
   } else {
-    v[0] = ld(P.vf[0], i);
-    v[1] = ld(P.vf[1], i);
-    v[2] = ld(P.vf[2], i);
+    const uint4 b = ld(P.rb, i);
+    v[0] = __uint_as_float(b.x);
+    v[1] = __uint_as_float(b.y);
+    v[2] = __uint_as_float(b.z);
+    tag = b.w;
   }
 }
 
 template <int FORM, class I>
-__device__ inline void store_vel(const Particles& P, I j, const typename VelT<FORM>::T w[3]) {
+__device__ inline void load_vel(const Particles& P, I i, typename VelT<FORM>::T v[3]) {
+  uint32_t tag;
+  load_vt<FORM>(P, i, v, tag);
+}
+
+template <int FORM, class I>
+__device__ inline uint32_t load_tag(const Particles& P, I i) {
+  if constexpr (FORM == 0) return ld(P.tag, i);
+  else return ld(reinterpret_cast<const uint32_t*>(P.rb), (I)(4 * i + 3));
+}
+
+template <int FORM, class I>
+__device__ inline void store_vt(const Particles& P, I j, const typename VelT<FORM>::T w[3], uint32_t tag) {
   if constexpr (FORM == 0) {
     st(P.v[0], j, w[0]);
     st(P.v[1], j, w[1]);
     st(P.v[2], j, w[2]);
+    st(P.tag, j, tag);
   } else {
-    st(P.vf[0], j, w[0]);
-    st(P.vf[1], j, w[1]);
-    st(P.vf[2], j, w[2]);
+    st(P.rb, j, make_uint4(__float_as_uint(w[0]), __float_as_uint(w[1]), __float_as_uint(w[2]), tag));
   }
 }
 
@@ -248,17 +266,15 @@ struct Pos<1> {
   float o[3];
   template <class I>
   __device__ void load(const Particles& P, I i) {
-    hp = ld(P.h, i);
-    o[0] = ld(P.o[0], i);
-    o[1] = ld(P.o[1], i);
-    o[2] = ld(P.o[2], i);
+    const uint4 a = ld(P.ra, i);
+    hp = a.x;
+    o[0] = __uint_as_float(a.y);
+    o[1] = __uint_as_float(a.z);
+    o[2] = __uint_as_float(a.w);
   }
   template <class I>
   __device__ void store(const Particles& P, I j) const {
-    st(P.h, j, hp);
-    st(P.o[0], j, o[0]);
-    st(P.o[1], j, o[1]);
-    st(P.o[2], j, o[2]);
+    st(P.ra, j, make_uint4(hp, __float_as_uint(o[0]), __float_as_uint(o[1]), __float_as_uint(o[2])));
   }
   __device__ void stream(const Box& B, const float v[3], uint32_t&) {
     int h[3];
@@ -474,8 +490,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
     lcs[q] = 0u;
     tg[q] = 0u;
     if (k < nreg) {
-      load_vel<FORM>(In, k, v[q]);
-      tg[q] = ld(In.tag, k);
+      load_vt<FORM>(In, k, v[q], tg[q]);
       r[q].load(In, k);
       if constexpr (COLL) lcs[q] = (uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1);
     }
@@ -508,8 +523,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
     atomicMin(&A.status[2], A.seq);
   };
   auto put = [&](size_t j, const VT w[3], uint32_t tag, const Pos<FORM>& rr, uint32_t lcell) {
-    store_vel<FORM>(A.out, j, w);
-    st(A.out.tag, j, tag);
+    store_vt<FORM>(A.out, j, w, tag);
     rr.store(A.out, j);
     st(A.out.lc, j, (uint8_t)lcell);
   };
@@ -579,7 +593,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
       Pos<FORM> rr;
       rr.load(In, k);
       if (STREAM_IN) rr.stream(B, vv, err);
-      scatter_one(rr, sd, sd32, vv, ld(In.tag, k));
+      scatter_one(rr, sd, sd32, vv, load_tag<FORM>(In, k));
     }
   } else {
     // ---- cell sums: count, momentum (and mass) in exact fixed point
@@ -596,7 +610,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
     for (uint32_t k = TREG + tid; k < cnt; k += TT) {
       VT vv[3];
       load_vel<FORM>(In, k, vv);
-      sum_mom((uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1), vv, mass_of(ld(In.tag, k)));
+      sum_mom((uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1), vv, mass_of(load_tag<FORM>(In, k)));
     }
     __syncthreads();
 
@@ -632,7 +646,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
       for (uint32_t k = TREG + tid; k < cnt; k += TT) {
         VT vv[3];
         load_vel<FORM>(In, k, vv);
-        sum_energy((uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1), vv, mass_of(ld(In.tag, k)));
+        sum_energy((uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1), vv, mass_of(load_tag<FORM>(In, k)));
       }
       __syncthreads();
       if (cthr) ek = 0.5 * AC::value(s_acc[RE][tid], s_acc[RE + NL - 1][tid]);
@@ -687,8 +701,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
           v[q][2] = w[2];
           if constexpr (MODE == MODE_COLLIDE) {
             const Particles Out = tile_view<FORM>(A.out, tbase);
-            store_vel<FORM>(Out, k, v[q]);
-            st(Out.tag, k, tg[q]);
+            store_vt<FORM>(Out, k, v[q], tg[q]);
             r[q].store(Out, k);
             st(Out.lc, k, (uint8_t)lcs[q]);
           } else {
@@ -699,20 +712,20 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
       if constexpr (MODE == MODE_COLLIDE_SCATTER) scatter(sh1.s, sh1.s32, v);
       for (uint32_t k = TREG + tid; k < cnt; k += TT) {
         VT vv[3], ww[3];
-        load_vel<FORM>(In, k, vv);
+        uint32_t tag;
+        load_vt<FORM>(In, k, vv, tag);
         Pos<FORM> rr;
         rr.load(In, k);
         const uint32_t lc = (uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1);
         rotate(lc, vv, ww);
         if constexpr (MODE == MODE_COLLIDE) {
           const Particles Out = tile_view<FORM>(A.out, tbase);
-          store_vel<FORM>(Out, k, ww);
-          st(Out.tag, k, ld(In.tag, k));
+          store_vt<FORM>(Out, k, ww, tag);
           rr.store(Out, k);
           st(Out.lc, k, (uint8_t)lc);
         } else {
           rr.stream(B, ww, err);
-          scatter_one(rr, sh1.s, sh1.s32, ww, ld(In.tag, k));
+          scatter_one(rr, sh1.s, sh1.s32, ww, tag);
         }
       }
     }
@@ -890,7 +903,7 @@ __global__ __launch_bounds__(256) void k_cells(Particles P, Slabs S, const uint3
   int c[3];
   r.cell3(B, sh[bx].s, sh[bx].s32, c);
   const uint32_t cell = cell_index(B, c);
-  if (cell_of_tag) cell_of_tag[P.tag[s.i]] = (int32_t)cell;
+  if (cell_of_tag) cell_of_tag[load_tag<FORM>(P, s.i)] = (int32_t)cell;
   if (counts) atomicAdd(&counts[B.cell0 + cell], 1u);
 }
 
@@ -915,7 +928,7 @@ __global__ __launch_bounds__(256) void k_field(Particles P, Slabs S, const uint3
   load_vel<FORM>(P, s.i, v);
   double m = B.mass;
   if constexpr (EMB) {
-    const uint32_t i = P.tag[s.i] - B.tag0;
+    const uint32_t i = load_tag<FORM>(P, s.i) - B.tag0;
     if (i >= B.n_solvent) m = emb_mass[i - B.n_solvent];
   }
   bool bad = false;
@@ -988,7 +1001,7 @@ __global__ __launch_bounds__(256) void k_totals(Particles P, Slabs S, const uint
     const double v[3] = {(double)vs[0], (double)vs[1], (double)vs[2]};
     double m = B.mass;
     if constexpr (EMB) {
-      const uint32_t i = P.tag[s.i] - B.tag0;
+      const uint32_t i = load_tag<FORM>(P, s.i) - B.tag0;
       if (i >= B.n_solvent) m = emb_mass[i - B.n_solvent];
     }
     fx_add(acc[0], m * v[0], bad);
@@ -1068,8 +1081,7 @@ __global__ __launch_bounds__(256) void k_import(Particles P, Box B, uint32_t cap
   if constexpr (PLACE) {
     if (slot < cap) {
       const size_t j = (size_t)T * cap + slot;
-      store_vel<FORM>(P, j, w);
-      P.tag[j] = tag0 + t;
+      store_vt<FORM>(P, j, w, tag0 + t);
       r.store(P, j);
     } else {
       atomicOr(bad_pos, 2u);
@@ -1085,20 +1097,24 @@ __global__ __launch_bounds__(256) void k_export(Particles P, Slabs S, const uint
   const SlabIter s = slab_slot(S, cnt);
   if (!s.valid) return;
   const Box& B = S.boxes[S.tile_box[s.T]];
-  const uint32_t t = P.tag[s.i];
+  typename VelT<FORM>::T v[3];
+  uint32_t t;
+  load_vt<FORM>(P, s.i, v, t);
+  Pos<FORM> r;
+  r.load(P, s.i);
   if constexpr (FORM == 0) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      pos[3ull * t + d] = P.x[d][s.i];
-      vel[3ull * t + d] = P.v[d][s.i];
+      pos[3ull * t + d] = r.x[d];
+      vel[3ull * t + d] = v[d];
     }
   } else {
     int h[3];
-    unpack_home(P.h[s.i], h[0], h[1], h[2]);
+    unpack_home(r.hp, h[0], h[1], h[2]);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      pos[3ull * t + d] = (double)h[d] * B.a + (double)P.o[d][s.i];
-      vel[3ull * t + d] = (double)P.vf[d][s.i];
+      pos[3ull * t + d] = (double)h[d] * B.a + (double)r.o[d];
+      vel[3ull * t + d] = (double)v[d];
     }
   }
 }
@@ -1114,12 +1130,12 @@ __global__ __launch_bounds__(256) void k_repack(Particles src, Particles dst, Sl
   if (T >= S.ntiles || k >= min(cnt[T], old_cap)) return;
   const size_t i = (size_t)T * old_cap + k, j = (size_t)T * S.cap + k;
   typename VelT<FORM>::T v[3];
-  load_vel<FORM>(src, i, v);
-  store_vel<FORM>(dst, j, v);
+  uint32_t tag;
+  load_vt<FORM>(src, i, v, tag);
+  store_vt<FORM>(dst, j, v, tag);
   Pos<FORM> r;
   r.load(src, i);
   r.store(dst, j);
-  dst.tag[j] = src.tag[i];
   dst.lc[j] = src.lc[i];
 }
 
