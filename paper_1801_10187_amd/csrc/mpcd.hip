@@ -324,11 +324,10 @@ mpcd_status alloc_slabs(mpcd_ctx c, uint32_t cap, Particles out[2], std::vector<
     Particles& P = out[b];
     P = Particles{};
     if (c->form == 0) {
-      for (int d = 0; d < 3; ++d) {
-        P.x[d] = (double*)get(S * 8);
-        P.v[d] = (double*)get(S * 8);
-        if (!P.x[d] || !P.v[d]) return fail(MPCD_ENOMEM, "device allocation of the slabs failed");
-      }
+      P.wa = (double2*)get(S * 16);
+      P.wb = (double2*)get(S * 16);
+      P.wc = (double2*)get(S * 16);
+      if (!P.wa || !P.wb || !P.wc) return fail(MPCD_ENOMEM, "device allocation of the slabs failed");
       P.tag = (uint32_t*)get(S * 4);
       if (!P.tag) return fail(MPCD_ENOMEM, "device allocation of the slabs failed");
     } else {

@@ -6,7 +6,8 @@
 // no particular order. Within a slab the data is structure of arrays, one
 // array per component, so a block reads and writes its tile as unit-stride
 // streams:
-//   FP64 form: x[3][S], v[3][S] double;
+//   FP64 form: three 16-byte words per particle, wa[S] = {x, y},
+//              wb[S] = {z, v_x}, wc[S] = {v_y, v_z} (double), and tag[S];
 //   FP32 form: two 16-byte words per particle, ra[S] = {home cell packed
 //              10:10:10, float offset inside the home cell x, y, z} and
 //              rb[S] = {float velocity x, y, z, tag}, so a lane moves a
@@ -78,9 +79,10 @@ struct ShiftEntry {
 };
 
 struct Particles {
-  double* x[3];  // FP64 form
-  double* v[3];
-  uint32_t* tag;
+  double2* wa;   // FP64 form: {x, y}, {z, v_x}, {v_y, v_z} in three 16-byte words
+  double2* wb;
+  double2* wc;
+  uint32_t* tag; // FP64 form: tag
   uint4* ra;     // FP32 form: {home cell packed 10:10:10, offset x, y, z (FP32 bits)}
   uint4* rb;     // FP32 form: {velocity x, y, z (FP32 bits), tag}
   uint8_t* lc;   // local cell of the particle inside its tile (set by a scatter)
@@ -122,14 +124,10 @@ __device__ inline void st(T* base, size_t j, T v) {
 template <int FORM>
 __device__ inline Particles tile_view(const Particles& P, size_t off) {
   Particles Q = P;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    if constexpr (FORM == 0) {
-      Q.x[d] = P.x[d] + off;
-      Q.v[d] = P.v[d] + off;
-    }
-  }
   if constexpr (FORM == 0) {
+    Q.wa = P.wa + off;
+    Q.wb = P.wb + off;
+    Q.wc = P.wc + off;
     Q.tag = P.tag + off;
   } else {
     Q.ra = P.ra + off;
@@ -183,14 +181,15 @@ __device__ inline int tile_coord(int c, const Box& B, int d) {
   return B.nt[d] == 1 ? 0 : (c >> B.tsh[d]);
 }
 
-// Velocity and tag of a particle. The FP32 form keeps them in one 16-byte
-// word, so a lane moves them with one vector load or store.
+// Velocity and tag of a particle. Both forms keep a particle in 16-byte
+// words, so a lane moves it with few vector loads and stores.
 template <int FORM, class I>
 __device__ inline void load_vt(const Particles& P, I i, typename VelT<FORM>::T v[3], uint32_t& tag) {
   if constexpr (FORM == 0) {
-    v[0] = ld(P.v[0], i);
-    v[1] = ld(P.v[1], i);
-    v[2] = ld(P.v[2], i);
+    const double2 b = ld(P.wb, i), c = ld(P.wc, i);
+    v[0] = b.y;
+    v[1] = c.x;
+    v[2] = c.y;
     tag = ld(P.tag, i);
   } else {
     const uint4 b = ld(P.rb, i);
@@ -213,17 +212,7 @@ __device__ inline uint32_t load_tag(const Particles& P, I i) {
   else return ld(reinterpret_cast<const uint32_t*>(P.rb), (I)(4 * i + 3));
 }
 
-template <int FORM, class I>
-__device__ inline void store_vt(const Particles& P, I j, const typename VelT<FORM>::T w[3], uint32_t tag) {
-  if constexpr (FORM == 0) {
-    st(P.v[0], j, w[0]);
-    st(P.v[1], j, w[1]);
-    st(P.v[2], j, w[2]);
-    st(P.tag, j, tag);
-  } else {
-    st(P.rb, j, make_uint4(__float_as_uint(w[0]), __float_as_uint(w[1]), __float_as_uint(w[2]), tag));
-  }
-}
+
 
 // Position of one particle in registers: stream (eq. 1) and bin (sec. 3.4).
 template <int FORM>
@@ -233,15 +222,10 @@ struct Pos<0> {
   double x[3];
   template <class I>
   __device__ void load(const Particles& P, I i) {
-    x[0] = ld(P.x[0], i);
-    x[1] = ld(P.x[1], i);
-    x[2] = ld(P.x[2], i);
-  }
-  template <class I>
-  __device__ void store(const Particles& P, I j) const {
-    st(P.x[0], j, x[0]);
-    st(P.x[1], j, x[1]);
-    st(P.x[2], j, x[2]);
+    const double2 a = ld(P.wa, i);
+    x[0] = a.x;
+    x[1] = a.y;
+    x[2] = ld(P.wb, i).x;
   }
   __device__ void stream(const Box& B, const double v[3], uint32_t& err) {
 #pragma unroll
@@ -272,10 +256,6 @@ struct Pos<1> {
     o[1] = __uint_as_float(a.z);
     o[2] = __uint_as_float(a.w);
   }
-  template <class I>
-  __device__ void store(const Particles& P, I j) const {
-    st(P.ra, j, make_uint4(hp, __float_as_uint(o[0]), __float_as_uint(o[1]), __float_as_uint(o[2])));
-  }
   __device__ void stream(const Box& B, const float v[3], uint32_t&) {
     int h[3];
     unpack_home(hp, h[0], h[1], h[2]);
@@ -291,6 +271,39 @@ struct Pos<1> {
   }
   __device__ void home3(const Box&, int c[3]) const { unpack_home(hp, c[0], c[1], c[2]); }
 };
+
+// A whole particle: position, velocity and tag.
+template <int FORM, class I>
+__device__ inline void load_part(const Particles& P, I i, Pos<FORM>& r, typename VelT<FORM>::T v[3],
+                                 uint32_t& tag) {
+  if constexpr (FORM == 0) {
+    const double2 a = ld(P.wa, i), b = ld(P.wb, i), c = ld(P.wc, i);
+    r.x[0] = a.x;
+    r.x[1] = a.y;
+    r.x[2] = b.x;
+    v[0] = b.y;
+    v[1] = c.x;
+    v[2] = c.y;
+    tag = ld(P.tag, i);
+  } else {
+    r.load(P, i);
+    load_vt<FORM>(P, i, v, tag);
+  }
+}
+
+template <int FORM, class I>
+__device__ inline void store_part(const Particles& P, I j, const Pos<FORM>& r,
+                                  const typename VelT<FORM>::T w[3], uint32_t tag) {
+  if constexpr (FORM == 0) {
+    st(P.wa, j, make_double2(r.x[0], r.x[1]));
+    st(P.wb, j, make_double2(r.x[2], w[0]));
+    st(P.wc, j, make_double2(w[1], w[2]));
+    st(P.tag, j, tag);
+  } else {
+    st(P.ra, j, make_uint4(r.hp, __float_as_uint(r.o[0]), __float_as_uint(r.o[1]), __float_as_uint(r.o[2])));
+    st(P.rb, j, make_uint4(__float_as_uint(w[0]), __float_as_uint(w[1]), __float_as_uint(w[2]), tag));
+  }
+}
 
 __device__ inline uint32_t cell_index(const Box& B, const int c[3]) {
   return (uint32_t)c[0] + (uint32_t)B.n[0] * ((uint32_t)c[1] + (uint32_t)B.n[1] * (uint32_t)c[2]);
@@ -490,8 +503,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
     lcs[q] = 0u;
     tg[q] = 0u;
     if (k < nreg) {
-      load_vt<FORM>(In, k, v[q], tg[q]);
-      r[q].load(In, k);
+      load_part<FORM>(In, k, r[q], v[q], tg[q]);
       if constexpr (COLL) lcs[q] = (uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1);
     }
   }
@@ -523,8 +535,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
     atomicMin(&A.status[2], A.seq);
   };
   auto put = [&](size_t j, const VT w[3], uint32_t tag, const Pos<FORM>& rr, uint32_t lcell) {
-    store_vt<FORM>(A.out, j, w, tag);
-    rr.store(A.out, j);
+    store_part<FORM>(A.out, j, rr, w, tag);
     st(A.out.lc, j, (uint8_t)lcell);
   };
   auto scatter = [&](const double* sd, const float* sd32, const VT (*w)[3]) {
@@ -589,11 +600,11 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
     scatter(sd, sd32, v);
     for (uint32_t k = TREG + tid; k < cnt; k += TT) {
       VT vv[3];
-      load_vel<FORM>(In, k, vv);
+      uint32_t tag;
       Pos<FORM> rr;
-      rr.load(In, k);
+      load_part<FORM>(In, k, rr, vv, tag);
       if (STREAM_IN) rr.stream(B, vv, err);
-      scatter_one(rr, sd, sd32, vv, load_tag<FORM>(In, k));
+      scatter_one(rr, sd, sd32, vv, tag);
     }
   } else {
     // ---- cell sums: count, momentum (and mass) in exact fixed point
@@ -701,8 +712,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
           v[q][2] = w[2];
           if constexpr (MODE == MODE_COLLIDE) {
             const Particles Out = tile_view<FORM>(A.out, tbase);
-            store_vt<FORM>(Out, k, v[q], tg[q]);
-            r[q].store(Out, k);
+            store_part<FORM>(Out, k, r[q], v[q], tg[q]);
             st(Out.lc, k, (uint8_t)lcs[q]);
           } else {
             r[q].stream(B, v[q], err);
@@ -713,15 +723,13 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
       for (uint32_t k = TREG + tid; k < cnt; k += TT) {
         VT vv[3], ww[3];
         uint32_t tag;
-        load_vt<FORM>(In, k, vv, tag);
         Pos<FORM> rr;
-        rr.load(In, k);
+        load_part<FORM>(In, k, rr, vv, tag);
         const uint32_t lc = (uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1);
         rotate(lc, vv, ww);
         if constexpr (MODE == MODE_COLLIDE) {
           const Particles Out = tile_view<FORM>(A.out, tbase);
-          store_vt<FORM>(Out, k, ww, tag);
-          rr.store(Out, k);
+          store_part<FORM>(Out, k, rr, ww, tag);
           st(Out.lc, k, (uint8_t)lc);
         } else {
           rr.stream(B, ww, err);
@@ -879,12 +887,12 @@ __global__ __launch_bounds__(256) void k_stream(Particles P, Slabs S, const uint
   if (!s.valid) return;
   const Box& B = S.boxes[S.tile_box[s.T]];
   typename VelT<FORM>::T v[3];
-  load_vel<FORM>(P, s.i, v);
+  uint32_t tag;
   Pos<FORM> r;
-  r.load(P, s.i);
+  load_part<FORM>(P, s.i, r, v, tag);
   uint32_t e = 0;
   r.stream(B, v, e);
-  r.store(P, s.i);
+  store_part<FORM>(P, s.i, r, v, tag);
   if (e) atomicOr(&status[0], e);
 }
 
@@ -1081,8 +1089,7 @@ __global__ __launch_bounds__(256) void k_import(Particles P, Box B, uint32_t cap
   if constexpr (PLACE) {
     if (slot < cap) {
       const size_t j = (size_t)T * cap + slot;
-      store_vt<FORM>(P, j, w, tag0 + t);
-      r.store(P, j);
+      store_part<FORM>(P, j, r, w, tag0 + t);
     } else {
       atomicOr(bad_pos, 2u);
     }
@@ -1099,9 +1106,8 @@ __global__ __launch_bounds__(256) void k_export(Particles P, Slabs S, const uint
   const Box& B = S.boxes[S.tile_box[s.T]];
   typename VelT<FORM>::T v[3];
   uint32_t t;
-  load_vt<FORM>(P, s.i, v, t);
   Pos<FORM> r;
-  r.load(P, s.i);
+  load_part<FORM>(P, s.i, r, v, t);
   if constexpr (FORM == 0) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -1131,11 +1137,9 @@ __global__ __launch_bounds__(256) void k_repack(Particles src, Particles dst, Sl
   const size_t i = (size_t)T * old_cap + k, j = (size_t)T * S.cap + k;
   typename VelT<FORM>::T v[3];
   uint32_t tag;
-  load_vt<FORM>(src, i, v, tag);
-  store_vt<FORM>(dst, j, v, tag);
   Pos<FORM> r;
-  r.load(src, i);
-  r.store(dst, j);
+  load_part<FORM>(src, i, r, v, tag);
+  store_part<FORM>(dst, j, r, v, tag);
   dst.lc[j] = src.lc[i];
 }
 
