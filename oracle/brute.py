@@ -11,7 +11,7 @@ inputs; it is far too slow for anything else.
 from fractions import Fraction
 import math
 
-from .philox import (TAG_AXIS, TAG_SHIFT, TAG_THERMO, philox_scalar, seed_key,
+from .philox import (TAG_AT, TAG_AXIS, TAG_SHIFT, TAG_THERMO, philox_scalar, seed_key,
                      uniform01_scalar)
 from .srd import GAMMA_MAX_ATTEMPTS
 
@@ -105,3 +105,45 @@ def brute_step(pos, vel, mass, p, step):
         props[c] = dict(count=len(idx), mass=float(M), u=u, ek=ek, axis=n,
                         xi=xi)
     return newpos, newvel, cells, s, props
+
+
+def brute_at_step(pos, vel, mass, p, step):
+    """One step with the Andersen-thermostat rule (eq. 4, sec. 3.7), particle
+    by particle: stream and bin as brute_step, then per particle a random
+    velocity from the scalar Philox (counter (tag, step, TAG_AT, 0), tag =
+    list index) by Box-Muller, and v <- u + dv - (sum_j m_j dv_j) / M_c with
+    u and the random mean as exact rational sums rounded once."""
+    L = [n * p.a for n in p.n_cells]
+    nx, ny, _ = p.n_cells
+    key = seed_key(p.seed)
+    newpos = [[_wrap(r[d] + v[d] * p.dt, L[d]) for d in range(3)] for r, v in zip(pos, vel)]
+    if p.grid_shift:
+        w = philox_scalar((0, step, TAG_SHIFT, 0), key)
+        s = [(uniform01_scalar(w[d]) - 0.5) * p.a for d in range(3)]
+    else:
+        s = [0.0, 0.0, 0.0]
+    cells = []
+    for r in newpos:
+        ijk = [min(int(math.floor(_wrap(r[d] + s[d], L[d]) * p.inv_a)), p.n_cells[d] - 1)
+               for d in range(3)]
+        cells.append(ijk[0] + nx * (ijk[1] + ny * ijk[2]))
+    kicks = []
+    for i in range(len(pos)):
+        u = [uniform01_scalar(x) for x in philox_scalar((i, step, TAG_AT, 0), key)]
+        r0 = math.sqrt(-2.0 * math.log(u[0]))
+        r2 = math.sqrt(-2.0 * math.log(u[2]))
+        g = [r0 * math.cos((2.0 * math.pi) * u[1]), r0 * math.sin((2.0 * math.pi) * u[1]),
+             r2 * math.cos((2.0 * math.pi) * u[3])]
+        sc = math.sqrt(p.kT / mass[i])
+        kicks.append([sc * x for x in g])
+    members = {}
+    for i, c in enumerate(cells):
+        members.setdefault(c, []).append(i)
+    newvel = [list(v) for v in vel]
+    for c, idx in members.items():
+        M = sum(Fraction(mass[i]) for i in idx)
+        u = [float(sum(Fraction(mass[i]) * Fraction(vel[i][d]) for i in idx) / M) for d in range(3)]
+        wm = [float(sum(Fraction(mass[i]) * Fraction(kicks[i][d]) for i in idx) / M) for d in range(3)]
+        for i in idx:
+            newvel[i] = [u[d] + kicks[i][d] - wm[d] for d in range(3)]
+    return newpos, newvel, cells

@@ -79,6 +79,10 @@ def collide32(h, o, v, mass, p, step):
     s = srd.grid_shift(p, step)
     cell = bin32(h, o, s, p)
     v64 = v.astype(np.float64)
+    if p.rule == "at":
+        vnew, info = srd.collide_at(cell, v64, mass, p, step)
+        info.update(shift=s, cell=cell)
+        return vnew.astype(np.float32), info
     count, M, P, u, ek = srd.cell_sums(cell, v64, mass, p.ncells)
     all_cells = np.arange(p.ncells, dtype=np.uint64)
     axis = srd.cell_axes(all_cells, step, p)

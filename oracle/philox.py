@@ -28,6 +28,7 @@ _MASK32 = np.uint64(0xFFFFFFFF)
 TAG_AXIS = 0
 TAG_THERMO = 1
 TAG_SHIFT = 2
+TAG_AT = 3      # per-particle random velocities of the Andersen-thermostat rule
 
 
 def philox4x32_10(ctr, key):

@@ -19,14 +19,19 @@ Readings of points the paper leaves open (each is listed in the design doc):
 * thermostat draws E ~ Gamma(3(Nc-1)/2, kT) (centre-of-mass motion removed)
   by Marsaglia-Tsang (with its squeeze test) and a Box-Muller normal (cos
   branch), at most 64 attempts; xi = 1 for Nc < 2 or E_k = 0;
-* rotation by +alpha, right-handed (Rodrigues' formula).
+* rotation by +alpha, right-handed (Rodrigues' formula);
+* Andersen-thermostat rule (eq. 4, sec. 3.7): per particle a Philox counter
+  (tag, step, TAG_AT, 0), Box-Muller on words (0, 1) for two components (cos
+  and sin branches) and on words (2, 3) for the third (cos branch), scaled by
+  sqrt(kT / m); the cell's mean random velocity is mass-weighted, which is
+  the paper's 1/N_c sum for equal masses and conserves momentum with beads.
 """
 from dataclasses import dataclass, field
 import math
 
 import numpy as np
 
-from .philox import (TAG_AXIS, TAG_SHIFT, TAG_THERMO, philox4x32_10, seed_key,
+from .philox import (TAG_AT, TAG_AXIS, TAG_SHIFT, TAG_THERMO, philox4x32_10, seed_key,
                      uniform01)
 
 GAMMA_MAX_ATTEMPTS = 64
@@ -46,6 +51,7 @@ class Params:
     solvent_mass: float = 1.0
     thermostat: bool = False
     grid_shift: bool = True
+    rule: str = "srd"        # collision rule: "srd" (eq. 2) or "at" (eq. 4)
     # derived constants, computed once on the host (both sides take these
     # values rather than re-deriving them)
     L: np.ndarray = field(init=False)
@@ -222,12 +228,54 @@ def rotate(vel, cell, u, axis, xi, p):
     return uc + dvr
 
 
+# ------------------------------------------------- Andersen thermostat rule
+def at_kicks(tags, step, mass, p):
+    """Random velocities of the AT rule (sec. 3.7): per particle the Philox
+    words of counter (tag, step, TAG_AT, 0) -> uniforms u0..u3; Box-Muller
+    g0 = r0 cos(2 pi u1), g1 = r0 sin(2 pi u1) with r0 = sqrt(-2 ln u0), and
+    g2 = sqrt(-2 ln u2) cos(2 pi u3); velocity sqrt(kT / m) (g0, g1, g2)."""
+    tags = np.asarray(tags, dtype=np.uint64)
+    n = tags.size
+    ctr = np.stack([tags, np.full(n, step, dtype=np.uint64),
+                    np.full(n, TAG_AT, dtype=np.uint64), np.zeros(n, dtype=np.uint64)],
+                   axis=1).astype(np.uint32)
+    w = philox4x32_10(ctr, seed_key(p.seed))
+    u = uniform01(w)
+    r0 = np.sqrt(-2.0 * np.log(u[:, 0]))
+    r2 = np.sqrt(-2.0 * np.log(u[:, 2]))
+    g = np.stack([r0 * np.cos((2.0 * math.pi) * u[:, 1]),
+                  r0 * np.sin((2.0 * math.pi) * u[:, 1]),
+                  r2 * np.cos((2.0 * math.pi) * u[:, 3])], axis=1)
+    return np.sqrt(p.kT / np.asarray(mass, dtype=np.float64))[:, None] * g
+
+
+def collide_at(cell, vel, mass, p, step, tags=None):
+    """AT collision (eq. 4): v_i <- u + dv_i - sum_j m_j dv_j / M_c, the sums
+    over the particles of the cell."""
+    n = vel.shape[0]
+    tags = np.arange(n) if tags is None else tags
+    count, M, P, u, ek = cell_sums(cell, vel, mass, p.ncells)
+    dv = at_kicks(tags, step, mass, p)
+    Q = np.stack([np.bincount(cell, weights=mass * dv[:, d], minlength=p.ncells)
+                  for d in range(3)], axis=1)
+    wmean = np.zeros((p.ncells, 3))
+    occ = M > 0
+    wmean[occ] = Q[occ] / M[occ, None]
+    vnew = u[cell] + dv - wmean[cell]
+    return vnew, dict(count=count, mass=M, momentum=P, u=u, ek=ek, kick=dv, kick_mean=wmean)
+
+
 # -------------------------------------------------------------- whole step
 def collide(pos_streamed, vel, mass, p, step):
-    """Bin, cell properties, draws and rotation for step `step`, given
-    already streamed positions. Returns (new velocities, info dict)."""
+    """Bin, cell properties, draws and rotation (or the AT rule) for step
+    `step`, given already streamed positions. Returns (new velocities, info
+    dict)."""
     s = grid_shift(p, step)
     cell = bin_cells(pos_streamed, s, p)
+    if p.rule == "at":
+        vnew, info = collide_at(cell, vel, mass, p, step)
+        info.update(shift=s, cell=cell)
+        return vnew, info
     count, M, P, u, ek = cell_sums(cell, vel, mass, p.ncells)
     all_cells = np.arange(p.ncells, dtype=np.uint64)
     axis = cell_axes(all_cells, step, p)
