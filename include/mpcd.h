@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define MPCD_ABI_VERSION 2
+#define MPCD_ABI_VERSION 3
 
 typedef struct mpcd_ctx_s* mpcd_ctx;
 
@@ -56,6 +56,13 @@ typedef enum {
 
 typedef enum { MPCD_FP64 = 0, MPCD_FP32 = 1 } mpcd_precision;
 
+/* Collision rule: stochastic rotation (eq. 2, Alg. 1), or the Andersen
+ * thermostat (eq. 4, sec. 3.7): v_i <- u + dv_i - sum_j m_j dv_j / M_c with
+ * dv_i ~ N(0, kT / m_i) per component, drawn per particle from Philox counter
+ * (tag within the box, step, 3, 0) by Box-Muller. The AT rule thermostats by
+ * itself: thermostat must be 0 with it. */
+typedef enum { MPCD_SRD = 0, MPCD_AT = 1 } mpcd_collision;
+
 /* Problem parameters as the paper states the problem (sec. 2, sec. 4). */
 typedef struct {
   int32_t n_cells[3];  /* cells per axis (>= 1); FP32 form: <= 1024 per axis    */
@@ -69,6 +76,7 @@ typedef struct {
   int32_t thermostat;  /* 0 none, 1 Maxwell-Boltzmann cell scaling (sec. 2, 3.6) */
   int32_t grid_shift;  /* 1 random grid shift each step (sec. 2), 0 none         */
   int32_t flags;       /* 0, or MPCD_FLAG_TIGHT_SLABS                            */
+  int32_t collision;   /* mpcd_collision: MPCD_SRD (0) or MPCD_AT (1)            */
 } mpcd_params;
 
 /* Test-only layout flag: size the per-tile particle slabs to exactly the
@@ -165,7 +173,8 @@ mpcd_status mpcd_get_cells(mpcd_ctx ctx, int32_t* cell_of_tag, int32_t* counts,
 mpcd_status mpcd_get_cell_props(mpcd_ctx ctx, double* mass, double* momentum,
                                 double* ek, int32_t pointers_on_device);
 
-/* Per-cell random draws of the binned state for the current step counter:
+/* Per-cell random draws of the binned state for the current step counter
+ * (SRD rule only; MPCD_EINVAL under the AT rule, which draws per particle):
  * axis[n_cells x 3] (sec. 3.6, cylindrical projection) and xi[n_cells]
  * (thermostat scale; 1 when the thermostat is off or N_c < 2). Cells with no
  * particle get axis (0, 0, 0) and xi 1. Only valid between mpcd_bin and

@@ -3,8 +3,8 @@
 The hot path lives in libmpcd.so (HIP kernels behind the C ABI of
 include/mpcd.h); `binding` marshals arguments to it with ctypes.
 """
-from .binding import (FP32, FP64, Batch, MpcdError, Sim, copy_kernel, declared_symbols,
-                      load, make_params, philox)
+from .binding import (AT, FP32, FP64, SRD, Batch, MpcdError, Sim, copy_kernel,
+                      declared_symbols, load, make_params, philox)
 
-__all__ = ["FP32", "FP64", "Batch", "MpcdError", "Sim", "copy_kernel", "declared_symbols",
-           "load", "make_params", "philox"]
+__all__ = ["AT", "FP32", "FP64", "SRD", "Batch", "MpcdError", "Sim", "copy_kernel",
+           "declared_symbols", "load", "make_params", "philox"]

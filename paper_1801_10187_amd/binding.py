@@ -18,6 +18,7 @@ HEADER = os.path.join(ROOT, "include", "mpcd.h")
 
 MPCD_OK, MPCD_EINVAL, MPCD_ENOMEM, MPCD_EHIP, MPCD_ERANGE, MPCD_ESTATE = range(6)
 FP64, FP32 = 0, 1
+SRD, AT = 0, 1
 FLAG_TIGHT_SLABS = 1
 STATUS_NAMES = {0: "MPCD_OK", 1: "MPCD_EINVAL", 2: "MPCD_ENOMEM", 3: "MPCD_EHIP",
                 4: "MPCD_ERANGE", 5: "MPCD_ESTATE"}
@@ -40,7 +41,8 @@ class Params(ctypes.Structure):
                 ("precision", ctypes.c_int32),
                 ("thermostat", ctypes.c_int32),
                 ("grid_shift", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32),
+                ("collision", ctypes.c_int32)]
 
 
 _lib = None
@@ -118,7 +120,7 @@ def _ptr(a):
 
 def make_params(n_cells, a=1.0, alpha=130.0 * math.pi / 180.0, dt=0.1, kT=1.0,
                 seed=1, solvent_mass=1.0, precision=FP64, thermostat=False,
-                grid_shift=True, flags=0):
+                grid_shift=True, flags=0, collision=0):
     p = Params()
     n = [int(x) for x in np.broadcast_to(np.asarray(n_cells), (3,))]
     p.n_cells[:] = n
@@ -129,6 +131,7 @@ def make_params(n_cells, a=1.0, alpha=130.0 * math.pi / 180.0, dt=0.1, kT=1.0,
     p.thermostat = int(bool(thermostat)) if thermostat in (0, 1, True, False) else int(thermostat)
     p.grid_shift = int(bool(grid_shift)) if grid_shift in (0, 1, True, False) else int(grid_shift)
     p.flags = int(flags)
+    p.collision = int(collision)
     return p
 
 
@@ -138,10 +141,10 @@ class Sim:
     def __init__(self, pos, vel, n_cells, a=1.0, alpha=130.0 * math.pi / 180.0,
                  dt=0.1, kT=1.0, seed=1, solvent_mass=1.0, precision=FP64,
                  thermostat=False, grid_shift=True, emb_pos=None, emb_vel=None,
-                 emb_mass=None, hip_stream=None, flags=0):
+                 emb_mass=None, hip_stream=None, flags=0, collision=0):
         lib = load()
         self.params = make_params(n_cells, a, alpha, dt, kT, seed, solvent_mass,
-                                  precision, thermostat, grid_shift, flags)
+                                  precision, thermostat, grid_shift, flags, collision)
         pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
         vel = np.ascontiguousarray(vel, dtype=np.float64).reshape(-1, 3)
         n_emb = 0
@@ -279,7 +282,7 @@ class Batch(Sim):
     after the other (see box())."""
 
     def __init__(self, boxes, precision=FP64, thermostat=False, grid_shift=True,
-                 hip_stream=None, flags=0):
+                 hip_stream=None, flags=0, collision=0):
         lib = load()
         nb = len(boxes)
         arr = (Params * nb)()
@@ -290,7 +293,7 @@ class Batch(Sim):
                                  bx.get("alpha", 130.0 * math.pi / 180.0), bx.get("dt", 0.1),
                                  bx.get("kT", 1.0), bx.get("seed", 1 + b),
                                  bx.get("solvent_mass", 1.0), precision, thermostat,
-                                 grid_shift, flags)
+                                 grid_shift, flags, collision)
             pos_l.append(np.asarray(bx["pos"], dtype=np.float64).reshape(-1, 3))
             vel_l.append(np.asarray(bx["vel"], dtype=np.float64).reshape(-1, 3))
             counts[b] = pos_l[-1].shape[0]

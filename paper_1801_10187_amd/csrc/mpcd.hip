@@ -213,39 +213,48 @@ uint32_t slab_blocks(const mpcd_ctx c, uint32_t cap) {
 }
 
 // --- tile kernel dispatch
-template <int F, int CPT, int MODE, bool SI>
+template <int F, int CPT, int MODE, bool SI, bool AT>
 void tile_inst2(mpcd_ctx c, const TileArgs& a, bool th, bool em) {
   const uint32_t nb = c->S.ntiles;
-  if (th) {
-    if (em) k_tile<F, CPT, MODE, SI, true, true><<<nb, TT, 0, c->stream>>>(a);
-    else k_tile<F, CPT, MODE, SI, true, false><<<nb, TT, 0, c->stream>>>(a);
+  if constexpr (AT) {  // the AT rule runs without the rotation's thermostat
+    if (em) k_tile<F, CPT, MODE, SI, false, true, true><<<nb, TT, 0, c->stream>>>(a);
+    else k_tile<F, CPT, MODE, SI, false, false, true><<<nb, TT, 0, c->stream>>>(a);
+  } else if (th) {
+    if (em) k_tile<F, CPT, MODE, SI, true, true, false><<<nb, TT, 0, c->stream>>>(a);
+    else k_tile<F, CPT, MODE, SI, true, false, false><<<nb, TT, 0, c->stream>>>(a);
   } else {
-    if (em) k_tile<F, CPT, MODE, SI, false, true><<<nb, TT, 0, c->stream>>>(a);
-    else k_tile<F, CPT, MODE, SI, false, false><<<nb, TT, 0, c->stream>>>(a);
+    if (em) k_tile<F, CPT, MODE, SI, false, true, false><<<nb, TT, 0, c->stream>>>(a);
+    else k_tile<F, CPT, MODE, SI, false, false, false><<<nb, TT, 0, c->stream>>>(a);
   }
 }
 
 template <int F, int CPT>
-void tile_inst1(mpcd_ctx c, const TileArgs& a, int mode, bool stream_in, bool th, bool em) {
+void tile_inst1(mpcd_ctx c, const TileArgs& a, int mode, bool stream_in, bool th, bool em, bool at) {
   switch (mode) {
     case MODE_BIN:
-      // binning needs no cell sums: thermostat/embedded variants are the same
-      if (stream_in) tile_inst2<F, CPT, MODE_BIN, true>(c, a, false, false);
-      else tile_inst2<F, CPT, MODE_BIN, false>(c, a, false, false);
+      // binning needs no cell sums: thermostat/embedded/rule variants are the same
+      if (stream_in) tile_inst2<F, CPT, MODE_BIN, true, false>(c, a, false, false);
+      else tile_inst2<F, CPT, MODE_BIN, false, false>(c, a, false, false);
       break;
-    case MODE_COLLIDE: tile_inst2<F, CPT, MODE_COLLIDE, false>(c, a, th, em); break;
-    case MODE_COLLIDE_SCATTER: tile_inst2<F, CPT, MODE_COLLIDE_SCATTER, false>(c, a, th, em); break;
-    default: tile_inst2<F, CPT, MODE_DIAG, false>(c, a, th, em); break;
+    case MODE_COLLIDE:
+      if (at) tile_inst2<F, CPT, MODE_COLLIDE, false, true>(c, a, th, em);
+      else tile_inst2<F, CPT, MODE_COLLIDE, false, false>(c, a, th, em);
+      break;
+    case MODE_COLLIDE_SCATTER:
+      if (at) tile_inst2<F, CPT, MODE_COLLIDE_SCATTER, false, true>(c, a, th, em);
+      else tile_inst2<F, CPT, MODE_COLLIDE_SCATTER, false, false>(c, a, th, em);
+      break;
+    default: tile_inst2<F, CPT, MODE_DIAG, false, false>(c, a, th, em); break;  // cell sums only
   }
 }
 
 template <int F>
 void tile_dispatch(mpcd_ctx c, const TileArgs& a, int mode, bool stream_in) {
-  const bool th = c->p.thermostat != 0, em = c->n_emb > 0;
+  const bool th = c->p.thermostat != 0, em = c->n_emb > 0, at = c->p.collision == MPCD_AT;
   switch (c->cpt) {
-    case 64: tile_inst1<F, 64>(c, a, mode, stream_in, th, em); break;
-    case 128: tile_inst1<F, 128>(c, a, mode, stream_in, th, em); break;
-    default: tile_inst1<F, 256>(c, a, mode, stream_in, th, em); break;
+    case 64: tile_inst1<F, 64>(c, a, mode, stream_in, th, em, at); break;
+    case 128: tile_inst1<F, 128>(c, a, mode, stream_in, th, em, at); break;
+    default: tile_inst1<F, 256>(c, a, mode, stream_in, th, em, at); break;
   }
 }
 
@@ -432,6 +441,10 @@ mpcd_status validate(const mpcd_params* p, int64_t ns, int64_t ne) {
   if (p->thermostat != 0 && p->thermostat != 1) return fail(MPCD_EINVAL, "thermostat must be 0 or 1");
   if (p->grid_shift != 0 && p->grid_shift != 1) return fail(MPCD_EINVAL, "grid_shift must be 0 or 1");
   if ((uint32_t)p->flags & ~(uint32_t)MPCD_FLAG_TIGHT_SLABS) return fail(MPCD_EINVAL, "unknown flags");
+  if (p->collision != MPCD_SRD && p->collision != MPCD_AT)
+    return fail(MPCD_EINVAL, "collision must be MPCD_SRD or MPCD_AT");
+  if (p->collision == MPCD_AT && p->thermostat)
+    return fail(MPCD_EINVAL, "the AT rule thermostats by itself: thermostat must be 0");
   if (p->precision == MPCD_FP32)
     for (int d = 0; d < 3; ++d)
       if (p->n_cells[d] > 1024) return fail(MPCD_EINVAL, "FP32 form supports at most 1024 cells per axis");
@@ -525,8 +538,10 @@ mpcd_status create_impl(int32_t nbox, const mpcd_params* params, const int64_t* 
     }
     const mpcd_params& q = params[b];
     if (q.precision != params[0].precision || q.thermostat != params[0].thermostat ||
-        q.grid_shift != params[0].grid_shift || q.flags != params[0].flags)
-      return fail(MPCD_EINVAL, "box %d: precision, thermostat, grid_shift and flags must match box 0", b);
+        q.grid_shift != params[0].grid_shift || q.flags != params[0].flags ||
+        q.collision != params[0].collision)
+      return fail(MPCD_EINVAL,
+                  "box %d: precision, thermostat, grid_shift, flags and collision must match box 0", b);
     ns_total += n_solv[b];
     ncells_total += (double)q.n_cells[0] * q.n_cells[1] * q.n_cells[2];
   }
@@ -995,6 +1010,8 @@ mpcd_status mpcd_get_cell_props(mpcd_ctx c, double* mass, double* momentum, doub
 }
 
 mpcd_status mpcd_get_cell_draws(mpcd_ctx c, double* axis, double* xi, int32_t on_device) {
+  ST_TRY(check_ctx(c));
+  if (c->p.collision == MPCD_AT) return fail(MPCD_EINVAL, "no per-cell draws under the AT rule");
   return cell_diag(c, nullptr, nullptr, nullptr, axis, xi, on_device);
 }
 

@@ -23,6 +23,7 @@ struct U4 {
 constexpr uint32_t TAG_AXIS = 0;
 constexpr uint32_t TAG_THERMO = 1;
 constexpr uint32_t TAG_SHIFT = 2;
+constexpr uint32_t TAG_AT = 3;
 constexpr int GAMMA_MAX_ATTEMPTS = 64;
 
 __host__ __device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
@@ -269,6 +270,22 @@ __device__ inline double thermo_xi(uint32_t cnt, double ek, uint32_t cell,
   const double e_hat =
       gamma_mt(1.5 * (double)(cnt - 1u), cell, step, k0, k1, kT, cap_hit);
   return sqrt(e_hat / ek);
+}
+
+// Random velocity of one particle under the Andersen-thermostat rule (eq. 4,
+// sec. 3.7): counter (tag, step, TAG_AT, 0); Box-Muller on words 0, 1 gives
+// two components (cos and sin branches, via sincospi(2 u)), words 2, 3 the
+// third (cos branch); scaled by `scale` = sqrt(kT / m).
+__device__ inline void at_kick(uint32_t tag, uint32_t step, uint32_t k0, uint32_t k1,
+                               double scale, double dv[3]) {
+  const U4 w = philox4x32_10(U4{tag, step, TAG_AT, 0u}, k0, k1);
+  const double r0 = sqrt(-2.0 * log(u01(w.x)));
+  const double r2 = sqrt(-2.0 * log(u01(w.z)));
+  double s1, c1;
+  sincospi(2.0 * u01(w.y), &s1, &c1);
+  dv[0] = scale * (r0 * c1);
+  dv[1] = scale * (r0 * s1);
+  dv[2] = scale * (r2 * cospi(2.0 * u01(w.w)));
 }
 
 // xi * R(alpha, n) in row-major order, R = cos a I + sin a [n]x +

@@ -411,18 +411,23 @@ struct Acc {
 // One block per tile. In the per-cell phases thread l < CPT works for cell
 // l: it draws the axis, forms u, xi and the rotation. The thermostat's Gamma
 // draws come from k_draw, launched just before.
-template <int FORM, int CPT, int MODE, bool STREAM_IN, bool THERMO, bool EMB>
+// ATR: the Andersen-thermostat rule (eq. 4) instead of the rotation; every
+// particle draws a random velocity dv in the gather, the cell sums gain
+// sum m dv, and the update is v <- (u + dv) - sum m dv / M.
+template <int FORM, int CPT, int MODE, bool STREAM_IN, bool THERMO, bool EMB, bool ATR>
 __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
   using VT = typename VelT<FORM>::T;
   using AC = Acc<FORM>;
   constexpr bool COLL = MODE != MODE_BIN;
   constexpr bool SCAT = MODE == MODE_BIN || MODE == MODE_COLLIDE_SCATTER;
   constexpr bool EK = THERMO || MODE == MODE_DIAG;
+  constexpr bool AT = ATR && COLL && MODE != MODE_DIAG;
   constexpr int NL = AC::NL;
   constexpr int TQ = tq_for(CPT);
   constexpr int TREG = TT * TQ;
   constexpr int RP = 0;                       // momentum rows: RP + NL * axis
-  constexpr int RE = 3 * NL;                  // relative kinetic energy
+  constexpr int RQ = 3 * NL;                  // AT: sum m dv rows, RQ + NL * axis
+  constexpr int RE = AT ? RQ + 3 * NL : RQ;   // relative kinetic energy
   constexpr int RM = EK ? RE + NL : RE;       // mass (embedded particles)
   constexpr int NROW = COLL ? RM + (EMB ? NL : 0) : 1;
   constexpr int CC = COLL ? CPT : 1;
@@ -497,6 +502,10 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
   uint32_t tg[TQ];
   uint32_t lcs[TQ];
   Pos<FORM> r[TQ];
+  double dv[AT ? TQ : 1][3];
+  auto kick = [&](uint32_t tag, double m, double out[3]) {
+    at_kick(tag - B.tag0, A.step, B.k0, B.k1, sqrt(B.kT / m), out);
+  };
 #pragma unroll
   for (int q = 0; q < TQ; ++q) {
     const uint32_t k = tid + (uint32_t)(q * TT);
@@ -506,6 +515,11 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
       load_part<FORM>(In, k, r[q], v[q], tg[q]);
       if constexpr (COLL) lcs[q] = (uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1);
     }
+  }
+  if constexpr (AT) {
+#pragma unroll
+    for (int q = 0; q < TQ; ++q)
+      if (tid + (uint32_t)(q * TT) < nreg) kick(tg[q], mass_of(tg[q]), dv[q]);
   }
 
   // cell thread: the rotation axis needs only (cell, step), so it is drawn
@@ -517,7 +531,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
   if constexpr (THERMO)
     if (cthr) ehat = A.ehat[(size_t)T * CPT + tid];
   if constexpr (COLL) {
-    if (cthr) {
+    if (cthr && !AT) {
       double n[3] = {0.0, 0.0, 0.0};
       if (cok) cell_axis(gcell, A.step, B.k0, B.k1, n);
       s_R[0][tid] = n[0];
@@ -608,20 +622,29 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
     }
   } else {
     // ---- cell sums: count, momentum (and mass) in exact fixed point
-    auto sum_mom = [&](uint32_t lc, const VT vv[3], double m) {
+    auto sum_mom = [&](uint32_t lc, const VT vv[3], double m, const double* kv) {
       atomicAdd(&s_cnt[lc], 1u);
 #pragma unroll
       for (int d = 0; d < 3; ++d)
         AC::add(&s_acc[RP + NL * d][lc], &s_acc[RP + NL * d + NL - 1][lc], m * (double)vv[d], bad);
+      if constexpr (AT) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          AC::add(&s_acc[RQ + NL * d][lc], &s_acc[RQ + NL * d + NL - 1][lc], m * kv[d], bad);
+      }
       if constexpr (EMB) AC::add(&s_acc[RM][lc], &s_acc[RM + NL - 1][lc], m, bad);
     };
 #pragma unroll
     for (int q = 0; q < TQ; ++q)
-      if (tid + (uint32_t)(q * TT) < nreg) sum_mom(lcs[q], v[q], mass_of(tg[q]));
+      if (tid + (uint32_t)(q * TT) < nreg) sum_mom(lcs[q], v[q], mass_of(tg[q]), dv[AT ? q : 0]);
     for (uint32_t k = TREG + tid; k < cnt; k += TT) {
       VT vv[3];
-      load_vel<FORM>(In, k, vv);
-      sum_mom((uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1), vv, mass_of(load_tag<FORM>(In, k)));
+      uint32_t tag;
+      load_vt<FORM>(In, k, vv, tag);
+      const double m = mass_of(tag);
+      double kv[3] = {0.0, 0.0, 0.0};
+      if constexpr (AT) kick(tag, m, kv);
+      sum_mom((uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1), vv, m, kv);
     }
     __syncthreads();
 
@@ -641,6 +664,13 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
       s_u[0][tid] = u[0];
       s_u[1][tid] = u[1];
       s_u[2][tid] = u[2];
+      if constexpr (AT) {
+        // mass-weighted mean random velocity of the cell, in s_R[0..2]
+        const double M = nc > 0u ? cell_mass(tid, nc) : 1.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          s_R[d][tid] = nc > 0u ? AC::value(s_acc[RQ + NL * d][tid], s_acc[RQ + NL * d + NL - 1][tid]) / M : 0.0;
+      }
     }
 
     double ek = 0.0;
@@ -682,7 +712,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
           A.d_ek[oc] = ek;
           A.d_xi[oc] = xi;
         }
-      } else {
+      } else if constexpr (!AT) {
         double R[9];
         rotation_matrix(n, B.ca, B.sa, B.omc, xi, R);
 #pragma unroll
@@ -694,7 +724,13 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
       __syncthreads();
       // ---- rotate (Alg. 1): v <- u + xi R (v - u) in FP64, rounded once to
       // the storage precision
-      auto rotate = [&](uint32_t lc, const VT vv[3], VT w[3]) {
+      auto rotate = [&](uint32_t lc, const VT vv[3], VT w[3], const double* kv) {
+        if constexpr (AT) {
+          // AT rule (eq. 4): u + dv - mean dv, rounded once
+#pragma unroll
+          for (int d = 0; d < 3; ++d) w[d] = (VT)((s_u[d][lc] + kv[d]) - s_R[d][lc]);
+          return;
+        }
         const double ux = s_u[0][lc], uy = s_u[1][lc], uz = s_u[2][lc];
         const double dx = (double)vv[0] - ux, dy = (double)vv[1] - uy, dz = (double)vv[2] - uz;
         w[0] = (VT)(ux + (s_R[0][lc] * dx + s_R[1][lc] * dy + s_R[2][lc] * dz));
@@ -706,7 +742,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
         const uint32_t k = tid + (uint32_t)(q * TT);
         if (k < nreg) {
           VT w[3];
-          rotate(lcs[q], v[q], w);
+          rotate(lcs[q], v[q], w, dv[AT ? q : 0]);
           v[q][0] = w[0];
           v[q][1] = w[1];
           v[q][2] = w[2];
@@ -726,7 +762,9 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
         Pos<FORM> rr;
         load_part<FORM>(In, k, rr, vv, tag);
         const uint32_t lc = (uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1);
-        rotate(lc, vv, ww);
+        double kv[3] = {0.0, 0.0, 0.0};
+        if constexpr (AT) kick(tag, mass_of(tag), kv);
+        rotate(lc, vv, ww, kv);
         if constexpr (MODE == MODE_COLLIDE) {
           const Particles Out = tile_view<FORM>(A.out, tbase);
           store_part<FORM>(Out, k, rr, ww, tag);

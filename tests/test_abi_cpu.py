@@ -53,7 +53,7 @@ def _create(lib, p, n=1, pos=None, vel=None):
                                          ("kT", -1.0), ("solvent_mass", 0.0),
                                          ("precision", 7), ("thermostat", 2),
                                          ("grid_shift", 5), ("flags", 2),
-                                         ("alpha", float("nan"))])
+                                         ("alpha", float("nan")), ("collision", 2)])
 def test_create_rejects_bad_parameters(lib, field, value):
     p = m.make_params((4, 4, 4))
     setattr(p, field, value)
@@ -112,3 +112,10 @@ def test_batch_create_rejects_bad_boxes(lib):
     assert "must match box 0" in lib.mpcd_last_error().decode()
     st, _ = _create_batch(lib, [good, good], [3, -1])
     assert st == binding.MPCD_EINVAL
+
+
+def test_at_rule_excludes_the_rotation_thermostat(lib):
+    p = m.make_params((4, 4, 4), thermostat=True, collision=m.AT)
+    st, ctx = _create(lib, p)
+    assert st == binding.MPCD_EINVAL and ctx.value is None
+    assert "AT rule" in lib.mpcd_last_error().decode()
