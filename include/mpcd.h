@@ -75,7 +75,7 @@ typedef struct {
   int32_t precision;   /* mpcd_precision: storage form of positions/velocities   */
   int32_t thermostat;  /* 0 none, 1 Maxwell-Boltzmann cell scaling (sec. 2, 3.6) */
   int32_t grid_shift;  /* 1 random grid shift each step (sec. 2), 0 none         */
-  int32_t flags;       /* 0, or MPCD_FLAG_TIGHT_SLABS                            */
+  int32_t flags;       /* 0, or MPCD_FLAG_TIGHT_SLABS | MPCD_FLAG_MD_SOLUTE      */
   int32_t collision;   /* mpcd_collision: MPCD_SRD (0) or MPCD_AT (1)            */
 } mpcd_params;
 
@@ -83,6 +83,15 @@ typedef struct {
  * initial maximum occupancy (no headroom), so that the first steps overflow
  * them and the enlarge-and-replay path runs. Results are unchanged. */
 #define MPCD_FLAG_TIGHT_SLABS 1
+
+/* Solute coupling through an external MD integrator (sec. 3.6): the embedded
+ * particles are not streamed by MPCD; between collisions the caller moves
+ * them (and changes their velocities) with its own equations of motion and
+ * hands their state over with mpcd_set_embedded; the collision then mixes
+ * them with the solvent and mpcd_get_embedded returns their new velocities.
+ * Without this flag embedded particles stream ballistically like the
+ * solvent. */
+#define MPCD_FLAG_MD_SOLUTE 2
 
 /* Create a context and upload the initial state (sec. 3.2 particle data).
  *  pos, vel      n_solvent x 3 doubles; positions inside [0, L) per axis.
@@ -152,6 +161,20 @@ mpcd_status mpcd_collide(mpcd_ctx ctx);
  * fused with the next step's stream and binning. nsteps >= 0. Waits for the
  * device at its end (see mpcd_bin about slab overflow). */
 mpcd_status mpcd_step(mpcd_ctx ctx, int64_t nsteps);
+
+/* State of the embedded particles only (tags n_solvent .. n_total - 1, box 0):
+ * pos, vel are n_embedded x 3 doubles, row i = embedded particle i as given to
+ * mpcd_create. get: any state; synchronises. set: only between steps (after
+ * create or a collide, else MPCD_ESTATE); positions must lie in [0, L)
+ * (else MPCD_EINVAL, and nothing is guaranteed about which rows were taken);
+ * the values are stored in the context's precision; the next binning moves
+ * each particle to the tile of its new position. MPCD_EINVAL if the context
+ * has no embedded particles. The exchange with an MD integrator
+ * (MPCD_FLAG_MD_SOLUTE). */
+mpcd_status mpcd_get_embedded(mpcd_ctx ctx, double* pos, double* vel,
+                              int32_t pointers_on_device);
+mpcd_status mpcd_set_embedded(mpcd_ctx ctx, const double* pos, const double* vel,
+                              int32_t pointers_on_device);
 
 /* Copy the state out in tag order: pos, vel are n_total x 3 doubles, where
  * n_total = n_solvent + n_embedded. Synchronises the context's stream. */

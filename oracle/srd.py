@@ -81,12 +81,18 @@ def wrap(w, L):
     return np.where(w >= L, 0.0, w)
 
 
-def stream(pos, vel, p):
-    """Ballistic streaming r <- r + v*dt in a periodic box (eq. 1)."""
+def stream(pos, vel, p, moving=None):
+    """Ballistic streaming r <- r + v*dt in a periodic box (eq. 1). With a
+    boolean mask `moving`, only those particles stream; the others (solutes
+    integrated by molecular dynamics between collisions, sec. 3.6) keep
+    their positions."""
     step = vel * p.dt
     if np.any(np.abs(step) >= p.L):
         raise ValueError("a particle moves a whole box length in one step")
-    return wrap(pos + step, p.L)
+    out = wrap(pos + step, p.L)
+    if moving is not None:
+        out = np.where(np.asarray(moving)[:, None], out, pos)
+    return out
 
 
 # ------------------------------------------------------------- grid shift
@@ -289,9 +295,10 @@ def collide(pos_streamed, vel, mass, p, step):
     return vnew, info
 
 
-def srd_step(pos, vel, mass, p, step):
-    """One full MPCD step: stream, then collide with counter `step`."""
-    pos1 = stream(pos, vel, p)
+def srd_step(pos, vel, mass, p, step, moving=None):
+    """One full MPCD step: stream (the particles in `moving`, default all),
+    then collide with counter `step`."""
+    pos1 = stream(pos, vel, p, moving)
     vel1, info = collide(pos1, vel, mass, p, step)
     return pos1, vel1, info
 

@@ -20,6 +20,7 @@ MPCD_OK, MPCD_EINVAL, MPCD_ENOMEM, MPCD_EHIP, MPCD_ERANGE, MPCD_ESTATE = range(6
 FP64, FP32 = 0, 1
 SRD, AT = 0, 1
 FLAG_TIGHT_SLABS = 1
+FLAG_MD_SOLUTE = 2
 STATUS_NAMES = {0: "MPCD_OK", 1: "MPCD_EINVAL", 2: "MPCD_ENOMEM", 3: "MPCD_EHIP",
                 4: "MPCD_ERANGE", 5: "MPCD_ESTATE"}
 
@@ -93,6 +94,8 @@ def load():
                               ctypes.POINTER(ctypes.c_int64), _P, ctypes.c_uint64]),
         "mpcd_box_totals": (st, [_P, _P, _P, _P]),
         "mpcd_get_velocity_field": (st, [_P, _P, _P, ctypes.c_int32]),
+        "mpcd_get_embedded": (st, [_P, _P, _P, ctypes.c_int32]),
+        "mpcd_set_embedded": (st, [_P, _P, _P, ctypes.c_int32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -206,6 +209,19 @@ class Sim:
         xi = np.empty(self.ncells)
         _check(load().mpcd_get_cell_draws(self._ctx, _ptr(axis), _ptr(xi), 0))
         return axis, xi
+
+    def get_embedded(self):
+        """Positions and velocities (n_embedded, 3) of the embedded particles."""
+        pos = np.empty((self.n_embedded, 3))
+        vel = np.empty((self.n_embedded, 3))
+        _check(load().mpcd_get_embedded(self._ctx, _ptr(pos), _ptr(vel), 0))
+        return pos, vel
+
+    def set_embedded(self, pos, vel):
+        """Hand the embedded particles' state (from an MD integrator) over."""
+        pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+        vel = np.ascontiguousarray(vel, dtype=np.float64).reshape(-1, 3)
+        _check(load().mpcd_set_embedded(self._ctx, _ptr(pos), _ptr(vel), 0))
 
     def velocity_field(self):
         """Mass-weighted mean velocity (n_cells, 3) and mass (n_cells) per

@@ -440,7 +440,8 @@ mpcd_status validate(const mpcd_params* p, int64_t ns, int64_t ne) {
     return fail(MPCD_EINVAL, "precision must be MPCD_FP64 or MPCD_FP32");
   if (p->thermostat != 0 && p->thermostat != 1) return fail(MPCD_EINVAL, "thermostat must be 0 or 1");
   if (p->grid_shift != 0 && p->grid_shift != 1) return fail(MPCD_EINVAL, "grid_shift must be 0 or 1");
-  if ((uint32_t)p->flags & ~(uint32_t)MPCD_FLAG_TIGHT_SLABS) return fail(MPCD_EINVAL, "unknown flags");
+  if ((uint32_t)p->flags & ~(uint32_t)(MPCD_FLAG_TIGHT_SLABS | MPCD_FLAG_MD_SOLUTE))
+    return fail(MPCD_EINVAL, "unknown flags");
   if (p->collision != MPCD_SRD && p->collision != MPCD_AT)
     return fail(MPCD_EINVAL, "collision must be MPCD_SRD or MPCD_AT");
   if (p->collision == MPCD_AT && p->thermostat)
@@ -513,6 +514,7 @@ Box make_box(const mpcd_params& p) {
   B.mass = p.solvent_mass;
   B.k0 = (uint32_t)(p.seed & 0xFFFFFFFFull);
   B.k1 = (uint32_t)(p.seed >> 32);
+  B.md_solute = ((uint32_t)p.flags & MPCD_FLAG_MD_SOLUTE) ? 1u : 0u;
   return B;
 }
 
@@ -924,6 +926,67 @@ mpcd_status mpcd_get_state(mpcd_ctx c, double* pos, double* vel, int32_t on_devi
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (tmp) (void)hipFree(tmp);
   if (e != hipSuccess) return fail(MPCD_EHIP, "get_state: %s", hipGetErrorString(e));
+  return take_err(c);
+}
+
+mpcd_status mpcd_get_embedded(mpcd_ctx c, double* pos, double* vel, int32_t on_device) {
+  ST_TRY(check_ctx(c));
+  if (c->n_emb == 0) return fail(MPCD_EINVAL, "no embedded particles");
+  if (!pos || !vel) return fail(MPCD_EINVAL, "pos/vel NULL");
+  const size_t n = c->n_emb;
+  double* dp = pos;
+  double* dv = vel;
+  double* tmp = nullptr;
+  if (!on_device) {
+    HIP_TRY(hipMalloc(&tmp, n * 48));
+    dp = tmp;
+    dv = tmp + 3 * n;
+  }
+  const uint32_t nb = slab_blocks(c, c->S.cap);
+  if (c->form == 0) k_emb_export<0><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->S, c->cnt[c->ci], dp, dv);
+  else k_emb_export<1><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->S, c->cnt[c->ci], dp, dv);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && tmp) {
+    e = hipMemcpyAsync(pos, dp, n * 24, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(vel, dv, n * 24, hipMemcpyDeviceToHost, c->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (tmp) (void)hipFree(tmp);
+  if (e != hipSuccess) return fail(MPCD_EHIP, "get_embedded: %s", hipGetErrorString(e));
+  return take_err(c);
+}
+
+mpcd_status mpcd_set_embedded(mpcd_ctx c, const double* pos, const double* vel, int32_t on_device) {
+  ST_TRY(check_ctx(c));
+  if (c->n_emb == 0) return fail(MPCD_EINVAL, "no embedded particles");
+  if (!pos || !vel) return fail(MPCD_EINVAL, "pos/vel NULL");
+  if (c->phase != Phase::Idle) return fail(MPCD_ESTATE, "mpcd_set_embedded: only between steps");
+  const size_t n = c->n_emb;
+  const double* dp = pos;
+  const double* dv = vel;
+  double* tmp = nullptr;
+  uint32_t* bad = nullptr;
+  HIP_TRY(hipMalloc(&bad, 256 + (on_device ? 0 : n * 48)));
+  hipError_t e = hipMemsetAsync(bad, 0, 4, c->stream);
+  if (!on_device) {
+    tmp = (double*)((char*)bad + 256);
+    if (e == hipSuccess) e = hipMemcpyAsync(tmp, pos, n * 24, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(tmp + 3 * n, vel, n * 24, hipMemcpyHostToDevice, c->stream);
+    dp = tmp;
+    dv = tmp + 3 * n;
+  }
+  if (e == hipSuccess) {
+    const uint32_t nb = slab_blocks(c, c->S.cap);
+    if (c->form == 0) k_emb_import<0><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->S, c->cnt[c->ci], dp, dv, bad);
+    else k_emb_import<1><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->S, c->cnt[c->ci], dp, dv, bad);
+    e = hipGetLastError();
+  }
+  uint32_t hbad = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(bad);
+  if (e != hipSuccess) return fail(MPCD_EHIP, "set_embedded: %s", hipGetErrorString(e));
+  if (hbad) return fail(MPCD_EINVAL, "an embedded position lies outside [0, L)");
   return take_err(c);
 }
 

@@ -59,7 +59,14 @@ struct Box {
   uint32_t tile0;      // its first tile in the slab arrays
   uint32_t tag0;       // its first particle tag
   uint32_t cell0;      // its first cell in per-cell outputs
+  uint32_t md_solute;  // 1: embedded particles are moved by an external MD integrator, not streamed
 };
+
+// Whether the MPCD stream moves particle `tag` (embedded particles are left to
+// the MD integrator when the box couples solutes that way, sec. 3.6).
+__device__ inline bool streamed(const Box& B, uint32_t tag) {
+  return !(B.md_solute && tag - B.tag0 >= B.n_solvent);
+}
 
 // Several independent boxes share one set of slabs: box b owns the tiles
 // [tile0, tile0 + ntiles) (padded so that every box starts at a multiple of
@@ -609,7 +616,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
     if constexpr (STREAM_IN) {
 #pragma unroll
       for (int q = 0; q < TQ; ++q)
-        if (tid + (uint32_t)(q * TT) < nreg) r[q].stream(B, v[q], err);
+        if (tid + (uint32_t)(q * TT) < nreg && streamed(B, tg[q])) r[q].stream(B, v[q], err);
     }
     scatter(sd, sd32, v);
     for (uint32_t k = TREG + tid; k < cnt; k += TT) {
@@ -617,7 +624,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
       uint32_t tag;
       Pos<FORM> rr;
       load_part<FORM>(In, k, rr, vv, tag);
-      if (STREAM_IN) rr.stream(B, vv, err);
+      if (STREAM_IN && streamed(B, tag)) rr.stream(B, vv, err);
       scatter_one(rr, sd, sd32, vv, tag);
     }
   } else {
@@ -751,7 +758,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
             store_part<FORM>(Out, k, r[q], v[q], tg[q]);
             st(Out.lc, k, (uint8_t)lcs[q]);
           } else {
-            r[q].stream(B, v[q], err);
+            if (streamed(B, tg[q])) r[q].stream(B, v[q], err);
           }
         }
       }
@@ -770,7 +777,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
           store_part<FORM>(Out, k, rr, ww, tag);
           st(Out.lc, k, (uint8_t)lc);
         } else {
-          rr.stream(B, ww, err);
+          if (streamed(B, tag)) rr.stream(B, ww, err);
           scatter_one(rr, sh1.s, sh1.s32, ww, tag);
         }
       }
@@ -929,7 +936,7 @@ __global__ __launch_bounds__(256) void k_stream(Particles P, Slabs S, const uint
   Pos<FORM> r;
   load_part<FORM>(P, s.i, r, v, tag);
   uint32_t e = 0;
-  r.stream(B, v, e);
+  if (streamed(B, tag)) r.stream(B, v, e);
   store_part<FORM>(P, s.i, r, v, tag);
   if (e) atomicOr(&status[0], e);
 }
@@ -1076,6 +1083,34 @@ __global__ __launch_bounds__(256) void k_totals(Particles P, Slabs S, const uint
 // Row-major N x 3 doubles (tag order) -> internal form, placed in the slab of
 // the tile of the particle's home cell. Pass 1 (PLACE == false) only counts
 // per tile and checks the box; pass 2 writes.
+// A position in [0, L) in the storage form: FP64 as is; FP32 as home cell
+// floor(x / a) (clamped) and the FP32 offset x - h a, an offset that rounds
+// up to a moving to the next cell at offset 0.
+template <int FORM>
+__device__ inline void to_form(const Box& B, const double x[3], Pos<FORM>& r) {
+  if constexpr (FORM == 0) {
+    r.x[0] = x[0];
+    r.x[1] = x[1];
+    r.x[2] = x[2];
+  } else {
+    int hh[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      int hd = (int)floor(x[d] * B.inv_a);
+      hd = hd < 0 ? 0 : (hd > B.n[d] - 1 ? B.n[d] - 1 : hd);
+      float o = (float)(x[d] - (double)hd * B.a);
+      if (o >= B.a32) {
+        o = 0.0f;
+        hd = hd + 1 == B.n[d] ? 0 : hd + 1;
+      }
+      if (o < 0.0f) o = 0.0f;
+      hh[d] = hd;
+      r.o[d] = o;
+    }
+    r.hp = pack_home(hh[0], hh[1], hh[2]);
+  }
+}
+
 template <int FORM, bool PLACE>
 __global__ __launch_bounds__(256) void k_import(Particles P, Box B, uint32_t cap,
                                                 const double* __restrict__ pos,
@@ -1099,27 +1134,7 @@ __global__ __launch_bounds__(256) void k_import(Particles P, Box B, uint32_t cap
   Pos<FORM> r;
   using VT = typename VelT<FORM>::T;
   const VT w[3] = {(VT)v[0], (VT)v[1], (VT)v[2]};
-  if constexpr (FORM == 0) {
-    r.x[0] = x[0];
-    r.x[1] = x[1];
-    r.x[2] = x[2];
-  } else {
-    int hh[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      int hd = (int)floor(x[d] * B.inv_a);
-      hd = hd < 0 ? 0 : (hd > B.n[d] - 1 ? B.n[d] - 1 : hd);
-      float o = (float)(x[d] - (double)hd * B.a);
-      if (o >= B.a32) {
-        o = 0.0f;
-        hd = hd + 1 == B.n[d] ? 0 : hd + 1;
-      }
-      if (o < 0.0f) o = 0.0f;
-      hh[d] = hd;
-      r.o[d] = o;
-    }
-    r.hp = pack_home(hh[0], hh[1], hh[2]);
-  }
+  to_form<FORM>(B, x, r);
   int c[3];
   r.home3(B, c);
   const uint32_t T = B.tile0 + tile_index(B, c);
@@ -1161,6 +1176,65 @@ __global__ __launch_bounds__(256) void k_export(Particles P, Slabs S, const uint
       vel[3ull * t + d] = (double)v[d];
     }
   }
+}
+
+// Embedded particles (box 0) out of / into the slabs, rows tag - n_solvent of
+// row-major n_emb x 3 doubles: the exchange with an external MD integrator
+// between collisions. The update writes in place; the next binning moves a
+// particle to the tile of its new position.
+template <int FORM>
+__global__ __launch_bounds__(256) void k_emb_export(Particles P, Slabs S, const uint32_t* cnt,
+                                                    double* __restrict__ pos, double* __restrict__ vel) {
+  const SlabIter s = slab_slot(S, cnt);
+  if (!s.valid) return;
+  const Box B = S.boxes[S.tile_box[s.T]];
+  typename VelT<FORM>::T v[3];
+  uint32_t t;
+  Pos<FORM> r;
+  load_part<FORM>(P, s.i, r, v, t);
+  const uint32_t i = t - B.tag0;
+  if (i < B.n_solvent) return;
+  const size_t row = 3ull * (i - B.n_solvent);
+  if constexpr (FORM == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) pos[row + d] = r.x[d];
+  } else {
+    int h[3];
+    unpack_home(r.hp, h[0], h[1], h[2]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) pos[row + d] = (double)h[d] * B.a + (double)r.o[d];
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) vel[row + d] = (double)v[d];
+}
+
+template <int FORM>
+__global__ __launch_bounds__(256) void k_emb_import(Particles P, Slabs S, const uint32_t* cnt,
+                                                    const double* __restrict__ pos,
+                                                    const double* __restrict__ vel, uint32_t* bad_pos) {
+  const SlabIter s = slab_slot(S, cnt);
+  if (!s.valid) return;
+  const Box B = S.boxes[S.tile_box[s.T]];
+  const uint32_t t = load_tag<FORM>(P, s.i);
+  const uint32_t i = t - B.tag0;
+  if (i < B.n_solvent) return;
+  const size_t row = 3ull * (i - B.n_solvent);
+  double x[3];
+  bool bad = false;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    x[d] = pos[row + d];
+    bad |= !(x[d] >= 0.0 && x[d] < B.L[d]);
+  }
+  if (bad) {
+    atomicOr(bad_pos, 1u);
+    return;
+  }
+  using VT = typename VelT<FORM>::T;
+  const VT w[3] = {(VT)vel[row], (VT)vel[row + 1], (VT)vel[row + 2]};
+  Pos<FORM> r;
+  to_form<FORM>(B, x, r);
+  store_part<FORM>(P, s.i, r, w, t);
 }
 
 // Copy the valid slots of every tile from slabs of capacity old_cap to slabs

@@ -52,7 +52,7 @@ def _create(lib, p, n=1, pos=None, vel=None):
 @pytest.mark.parametrize("field,value", [("a", 0.0), ("a", -1.0), ("dt", -0.1),
                                          ("kT", -1.0), ("solvent_mass", 0.0),
                                          ("precision", 7), ("thermostat", 2),
-                                         ("grid_shift", 5), ("flags", 2),
+                                         ("grid_shift", 5), ("flags", 4),
                                          ("alpha", float("nan")), ("collision", 2)])
 def test_create_rejects_bad_parameters(lib, field, value):
     p = m.make_params((4, 4, 4))
