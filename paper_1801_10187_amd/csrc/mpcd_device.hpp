@@ -261,17 +261,6 @@ __device__ inline double gamma_mt(double k, uint32_t cell, uint32_t step,
   return k * theta;
 }
 
-// Maxwell-Boltzmann cell thermostat factor xi = sqrt(E_hat / E_k) with
-// E_hat ~ Gamma(3 (N_c - 1) / 2, kT); 1 for N_c < 2 or E_k == 0.
-__device__ inline double thermo_xi(uint32_t cnt, double ek, uint32_t cell,
-                                   uint32_t step, uint32_t k0, uint32_t k1,
-                                   double kT, bool& cap_hit) {
-  if (cnt < 2u || !(ek > 0.0)) return 1.0;
-  const double e_hat =
-      gamma_mt(1.5 * (double)(cnt - 1u), cell, step, k0, k1, kT, cap_hit);
-  return sqrt(e_hat / ek);
-}
-
 // Random velocity of one particle under the Andersen-thermostat rule (eq. 4,
 // sec. 3.7): counter (tag, step, TAG_AT, 0); Box-Muller on words 0, 1 gives
 // two components (cos and sin branches, via sincospi(2 u)), words 2, 3 the
