@@ -55,7 +55,10 @@ mpcd_status fail(mpcd_status st, const char* fmt, ...) {
 enum class Phase { Idle, Streamed, Binned };
 
 // One queued kernel of a stepping call.
-enum class Op { BinStream, Bin, Draw, CollideScatter, Collide };
+// CollideKeep: collide + scatter whose input slots also receive the
+// collided velocities, so that the input holds the state after the collision
+// and the output the same state streamed and binned for the next step.
+enum class Op { BinStream, Bin, Draw, CollideScatter, Collide, CollideKeep };
 struct Launch {
   Op op;
   uint64_t step;
@@ -108,6 +111,10 @@ struct mpcd_ctx_s {
   uint64_t last_bin_step = 0;
   Phase phase = Phase::Idle;
   bool have_bin = false;
+  // buf[1 - cur] with cnt[(ci + 1) % 3] holds the current state streamed and
+  // binned for step `step` (left by the last mpcd_step), so the next
+  // mpcd_step starts with its collision
+  bool pre = false;
   int64_t regrows = 0;
 
   bool prof = false;
@@ -307,6 +314,11 @@ mpcd_status launch_tile(mpcd_ctx c, Op op, uint64_t n, uint32_t seq) {
     case Op::BinStream: mode = MODE_BIN; stream_in = true; break;
     case Op::Bin: mode = MODE_BIN; break;
     case Op::CollideScatter: mode = MODE_COLLIDE_SCATTER; a.shn = shift_at(c, n + 1); break;
+    case Op::CollideKeep:
+      mode = MODE_COLLIDE_SCATTER;
+      a.shn = shift_at(c, n + 1);
+      a.keep = 1u;
+      break;
     default: mode = MODE_COLLIDE; break;
   }
   {
@@ -314,6 +326,10 @@ mpcd_status launch_tile(mpcd_ctx c, Op op, uint64_t n, uint32_t seq) {
     if (c->form == 0) tile_dispatch<0>(c, a, mode, stream_in);
     else tile_dispatch<1>(c, a, mode, stream_in);
     HIP_TRY(hipGetLastError());
+  }
+  if (op == Op::CollideKeep) {  // the input stays current; the output is the prepared next binning
+    c->pre = true;
+    return MPCD_OK;
   }
   c->cur = 1 - c->cur;
   if (mode != MODE_COLLIDE) c->ci = (c->ci + 1) % 3;
@@ -398,12 +414,27 @@ mpcd_status regrow(mpcd_ctx c, int in_cur, int in_ci) {
   c->S.cap = new_cap;
   c->cur = 0;
   c->ci = 0;
+  c->pre = false;
   c->regrows += 1;
   return MPCD_OK;
 }
 
+// Give up the binning prepared by the last mpcd_step. Its counts sit in
+// cnt[(ci + 1) % 3], which the next scatter would add to, while the counts
+// the last collide + scatter cleared sit in cnt[(ci + 2) % 3]: swapping the
+// two pointers hands the next scatter clean counts and leaves the stale
+// ones to be cleared by it.
+void drop_prepared(mpcd_ctx c) {
+  if (!c->pre) return;
+  std::swap(c->cnt[(c->ci + 1) % 3], c->cnt[(c->ci + 2) % 3]);
+  c->pre = false;
+}
+
 // Run a list of tile launches, then confirm that no slab overflowed; replay
-// from the failing launch after enlarging the slabs if one did.
+// from the failing launch after enlarging the slabs if one did. A failing
+// CollideKeep is not replayed: all its blocks ran, so its input holds the
+// collided state, which the enlarged slabs now hold; only the prepared
+// binning is given up.
 mpcd_status run_launches(mpcd_ctx c, const std::vector<Launch>& L) {
   size_t from = 0;
   for (int attempt = 0; attempt < 16; ++attempt) {
@@ -419,6 +450,7 @@ mpcd_status run_launches(mpcd_ctx c, const std::vector<Launch>& L) {
     if (st[1] == 0) return MPCD_OK;
     const size_t bad = std::min<size_t>(st[2], in_state.size() - 1);
     ST_TRY(regrow(c, in_state[bad].first, in_state[bad].second));
+    if (L[from + bad].op == Op::CollideKeep) return MPCD_OK;
     from += bad;
   }
   return fail(MPCD_ENOMEM, "slab capacity kept overflowing");
@@ -845,6 +877,7 @@ void mpcd_destroy(mpcd_ctx c) {
 mpcd_status mpcd_stream(mpcd_ctx c) {
   ST_TRY(check_ctx(c));
   if (c->phase != Phase::Idle) return fail(MPCD_ESTATE, "mpcd_stream: expected the state after create or collide");
+  drop_prepared(c);  // the binning that follows overwrites the prepared one
   if (c->N) {
     ProfScope ps(c, 1);
     const uint32_t nb = slab_blocks(c, c->S.cap);
@@ -888,10 +921,16 @@ mpcd_status mpcd_step(mpcd_ctx c, int64_t nsteps) {
   ST_TRY(ensure_shifts(c, c->step, (uint64_t)nsteps + 1));
   std::vector<Launch> L;
   L.reserve(2 * (size_t)nsteps + 1);
-  L.push_back({Op::BinStream, c->step});
+  if (c->pre) {  // the last call left this step's binning ready
+    c->cur = 1 - c->cur;
+    c->ci = (c->ci + 1) % 3;
+    c->pre = false;
+  } else {
+    L.push_back({Op::BinStream, c->step});
+  }
   for (int64_t k = 0; k < nsteps; ++k) {
     if (c->p.thermostat) L.push_back({Op::Draw, c->step + (uint64_t)k});
-    L.push_back({k + 1 < nsteps ? Op::CollideScatter : Op::Collide, c->step + (uint64_t)k});
+    L.push_back({k + 1 < nsteps ? Op::CollideScatter : Op::CollideKeep, c->step + (uint64_t)k});
   }
   ST_TRY(run_launches(c, L));
   c->step += (uint64_t)nsteps;
@@ -961,6 +1000,7 @@ mpcd_status mpcd_set_embedded(mpcd_ctx c, const double* pos, const double* vel, 
   if (c->n_emb == 0) return fail(MPCD_EINVAL, "no embedded particles");
   if (!pos || !vel) return fail(MPCD_EINVAL, "pos/vel NULL");
   if (c->phase != Phase::Idle) return fail(MPCD_ESTATE, "mpcd_set_embedded: only between steps");
+  drop_prepared(c);  // the new positions are binned afresh by the next step
   const size_t n = c->n_emb;
   const double* dp = pos;
   const double* dv = vel;
@@ -1147,6 +1187,7 @@ mpcd_status mpcd_set_step(mpcd_ctx c, uint64_t n) {
   ST_TRY(check_ctx(c));
   if (c->phase != Phase::Idle) return fail(MPCD_ESTATE, "mpcd_set_step: only between steps");
   if (n >= 0xFFFFFFFFull) return fail(MPCD_ERANGE, "step counter beyond 2^32 - 1");
+  if (n != c->step) drop_prepared(c);  // the prepared binning used step `step`'s shift
   c->step = n;
   return MPCD_OK;
 }

@@ -358,6 +358,18 @@ __device__ inline void store_part(const Particles& P, I j, const Pos<FORM>& r,
   }
 }
 
+// The velocity-bearing words of record j only (position words unchanged).
+template <int FORM, class I>
+__device__ inline void store_vel(const Particles& P, I j, const Pos<FORM>& r,
+                                 const typename VelT<FORM>::T w[3], uint32_t tag) {
+  if constexpr (FORM == 0) {
+    st(P.wb, j, make_double2(r.x[2], w[0]));
+    st(P.wc, j, make_double2(w[1], w[2]));
+  } else {
+    st(P.rb, j, make_uint4(__float_as_uint(w[0]), __float_as_uint(w[1]), __float_as_uint(w[2]), tag));
+  }
+}
+
 __device__ inline uint32_t cell_index(const Box& B, const int c[3]) {
   return (uint32_t)c[0] + (uint32_t)B.n[0] * ((uint32_t)c[1] + (uint32_t)B.n[1] * (uint32_t)c[2]);
 }
@@ -432,6 +444,8 @@ struct TileArgs {
   double* d_ek;
   double* d_axis;
   double* d_xi;
+  uint32_t keep;            // collide + scatter: also write the collided
+                            // velocities back into the input slots
 };
 
 // Fixed-point accumulator rows of one cell sum: the FP64 form keeps two limbs
@@ -804,6 +818,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
             store_part<FORM>(Out, k, r[q], v[q], tg[q]);
             st(Out.lc, k, (uint8_t)lcs[q]);
           } else {
+            if (A.keep) store_vel<FORM>(In, k, r[q], v[q], tg[q]);
             if (streamed(B, tg[q])) r[q].stream(B, v[q], err);
           }
         }
@@ -823,6 +838,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
           store_part<FORM>(Out, k, rr, ww, tag);
           st(Out.lc, k, (uint8_t)lc);
         } else {
+          if (A.keep) store_vel<FORM>(In, k, rr, ww, tag);
           if (streamed(B, tag)) rr.stream(B, ww, err);
           scatter_one(rr, sh1.s, sh1.s32, ww, tag);
         }
