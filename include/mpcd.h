@@ -159,7 +159,14 @@ mpcd_status mpcd_collide(mpcd_ctx ctx);
 /* nsteps whole steps (stream, bin, collide), equivalent to calling the three
  * entry points nsteps times: one launch per step, each step's collision
  * fused with the next step's stream and binning. nsteps >= 0. Waits for the
- * device at its end (see mpcd_bin about slab overflow). */
+ * device at its end (see mpcd_bin about slab overflow).
+ * The last launch also leaves the next step's stream and binning prepared
+ * beside the collided state, so that the next mpcd_step starts with its
+ * collision; the state every get_* reads is the collided one either way.
+ * mpcd_stream, mpcd_set_embedded and a changed step counter give the
+ * prepared binning up (the next mpcd_step then streams and bins first), as
+ * does a slab overflow in that launch. Results never depend on how a run is
+ * split into calls. */
 mpcd_status mpcd_step(mpcd_ctx ctx, int64_t nsteps);
 
 /* State of the embedded particles only (tags n_solvent .. n_total - 1, box 0):
