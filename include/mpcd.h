@@ -79,9 +79,10 @@ typedef struct {
   int32_t collision;   /* mpcd_collision: MPCD_SRD (0) or MPCD_AT (1)            */
 } mpcd_params;
 
-/* Test-only layout flag: size the per-tile particle slabs to exactly the
- * initial maximum occupancy (no headroom), so that the first steps overflow
- * them and the enlarge-and-replay path runs. Results are unchanged. */
+/* Test-only layout flag: size the per-tile particle slabs to the initial
+ * maximum occupancy rounded up to a multiple of 4 (no other headroom), so
+ * that the first steps overflow them and the enlarge-and-replay path runs.
+ * Results are unchanged. */
 #define MPCD_FLAG_TIGHT_SLABS 1
 
 /* Solute coupling through an external MD integrator (sec. 3.6): the embedded
@@ -257,10 +258,12 @@ mpcd_status mpcd_get_layout(mpcd_ctx ctx, int32_t tile[3], int64_t* n_tiles,
  * collision kernel (collide, stream and bin of the next step), 1 the
  * stream / stream+bin kernels, 2 the thermostat draw kernel (Gamma draws of
  * every cell, launched before each collision when the thermostat is on;
- * sec. 3.6). While enabled,
- * each launch is bracketed by two events; mpcd_profile_read synchronises,
- * returns the summed milliseconds and launch count since the last read,
- * and clears them. */
+ * sec. 3.6). on = 0 disables; on = P >= 1 brackets the first launch of each
+ * kind and then one in every P with two events (P = 1: every launch; each
+ * bracketed launch costs a few microseconds of stream time, so a larger P
+ * disturbs a timed run less). mpcd_profile_read synchronises, returns the
+ * summed milliseconds and the number of bracketed launches since the last
+ * read, and clears them. MPCD_EINVAL for on < 0. */
 mpcd_status mpcd_profile_enable(mpcd_ctx ctx, int32_t on);
 mpcd_status mpcd_profile_read(mpcd_ctx ctx, int32_t which, double* total_ms,
                               int64_t* launches);

@@ -262,8 +262,10 @@ class Sim:
         return tuple(tile), nt.value, cap.value, rg.value
 
     # -- timing
-    def profile(self, on=True):
-        _check(load().mpcd_profile_enable(self._ctx, int(bool(on))))
+    def profile(self, on=True, every=1):
+        """Time launches with HIP events: the first of each kind, then one in
+        every `every` (mpcd_profile_enable)."""
+        _check(load().mpcd_profile_enable(self._ctx, int(every) if on else 0))
 
     def profile_read(self, which=0):
         ms = ctypes.c_double()

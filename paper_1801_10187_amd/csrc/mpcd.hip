@@ -117,7 +117,8 @@ struct mpcd_ctx_s {
   bool pre = false;
   int64_t regrows = 0;
 
-  bool prof = false;
+  int32_t prof_every = 0;          // time one launch in every prof_every of a kind (0: off)
+  uint64_t prof_seen[3] = {0, 0, 0};
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[3];
 
@@ -203,13 +204,14 @@ struct ProfScope {
   int which;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   ProfScope(mpcd_ctx c_, int w) : c(c_), which(w) {
-    if (!c->prof) return;
+    if (c->prof_every <= 0) return;
+    if (c->prof_seen[which]++ % (uint64_t)c->prof_every != 0) return;
     e0 = pool_event(c);
     e1 = pool_event(c);
     if (e0 && e1) (void)hipEventRecord(e0, c->stream);
   }
   ~ProfScope() {
-    if (!c->prof || !e0 || !e1) return;
+    if (!e0 || !e1) return;
     (void)hipEventRecord(e1, c->stream);
     c->ev_used[which].emplace_back(e0, e1);
   }
@@ -743,7 +745,7 @@ mpcd_status create_impl(int32_t nbox, const mpcd_params* params, const int64_t* 
   for (uint32_t v : cnt_h) mx = std::max(mx, v);
   uint32_t cap;
   if ((uint32_t)params[0].flags & MPCD_FLAG_TIGHT_SLABS) {
-    cap = std::max<uint32_t>(mx, 1u);
+    cap = round_up(std::max<uint32_t>(mx, 1u), 4);  // the draw kernel reads 4 local-cell bytes at once
   } else {
     const uint64_t want = std::max<uint64_t>((uint64_t)mx + mx / 5,
                                              (uint64_t)(max_mean + 8.0 * std::sqrt(max_mean) + 64.0));
@@ -1241,7 +1243,9 @@ mpcd_status mpcd_get_layout(mpcd_ctx c, int32_t tile[3], int64_t* n_tiles, int64
 
 mpcd_status mpcd_profile_enable(mpcd_ctx c, int32_t on) {
   ST_TRY(check_ctx(c));
-  c->prof = on != 0;
+  if (on < 0) return fail(MPCD_EINVAL, "profile period < 0");
+  c->prof_every = on;
+  for (uint64_t& n : c->prof_seen) n = 0;
   return MPCD_OK;
 }
 

@@ -866,7 +866,6 @@ __global__ __launch_bounds__(DT) void k_draw(Particles P, Slabs S, const uint32_
                                              uint32_t step, double* __restrict__ ehat,
                                              uint32_t* status, uint32_t seq) {
   constexpr int TPB = DT / CPT;  // tiles per block (boxes start at multiples of 4 tiles)
-  constexpr int LQ = 4;          // local-cell bytes per tile and thread loaded at once
   __shared__ uint32_t s_n[DT];
   __shared__ uint32_t s_qn;
   __shared__ uint32_t s_qc[DT];  // pending: global cell index | rejected flag in bit 31 of s_qr
@@ -883,19 +882,19 @@ __global__ __launch_bounds__(DT) void k_draw(Particles P, Slabs S, const uint32_
   }
   s_n[tid] = 0u;
 
-  // occupancies: all loads of the block issued together, then the counts
+  // occupancies: the tiles' counts and the first local-cell bytes of their
+  // slabs (one 32-bit word of 4 bytes per thread; cap is a multiple of 4) are
+  // loaded together, and the bytes at or beyond a tile's count are dropped
+  // once the count is known
+  const uint32_t nw = min((uint32_t)DT, S.cap / 4u);
   uint32_t cnt[TPB];
-  uint32_t v[TPB][LQ];
+  uint32_t v[TPB];
 #pragma unroll
   for (int i = 0; i < TPB; ++i) {
     const uint32_t T = b * TPB + i;
     cnt[i] = T < S.ntiles ? min(cnt_in[T], S.cap) : 0u;
-    const uint8_t* lc = P.lc + (size_t)T * S.cap;
-#pragma unroll
-    for (int q = 0; q < LQ; ++q) {
-      const uint32_t k = tid + (uint32_t)(q * DT);
-      v[i][q] = k < cnt[i] ? (uint32_t)ld(lc, k) : 0u;
-    }
+    const uint32_t* lw = reinterpret_cast<const uint32_t*>(P.lc + (size_t)T * S.cap);
+    v[i] = (T < S.ntiles && tid < nw) ? ld(lw, tid) : 0u;
   }
   // this thread's cell
   const uint32_t T = b * TPB + tid / (uint32_t)CPT, l = tid % (uint32_t)CPT;
@@ -905,10 +904,11 @@ __global__ __launch_bounds__(DT) void k_draw(Particles P, Slabs S, const uint32_
 #pragma unroll
   for (int i = 0; i < TPB; ++i) {
 #pragma unroll
-    for (int q = 0; q < LQ; ++q)
-      if (tid + (uint32_t)(q * DT) < cnt[i]) atomicAdd(&s_n[i * CPT + (v[i][q] & (uint32_t)(CPT - 1))], 1u);
+    for (int j = 0; j < 4; ++j)
+      if (tid < nw && 4u * tid + (uint32_t)j < cnt[i])
+        atomicAdd(&s_n[i * CPT + ((v[i] >> (8 * j)) & (uint32_t)(CPT - 1))], 1u);
     const uint8_t* lc = P.lc + (size_t)(b * TPB + i) * S.cap;
-    for (uint32_t k = tid + (uint32_t)(LQ * DT); k < cnt[i]; k += DT)
+    for (uint32_t k = 4u * nw + tid; k < cnt[i]; k += DT)
       atomicAdd(&s_n[i * CPT + ((uint32_t)ld(lc, k) & (uint32_t)(CPT - 1))], 1u);
   }
   __syncthreads();

@@ -126,7 +126,7 @@ def test_overflow_in_the_last_launch_of_a_call():
     maximum: scatters into the prepared binning overflow, the slabs grow and
     the collided state is kept; the run still matches the oracle."""
     banner("overflow at the end of a call")
-    p = srd.Params((12, 12, 12), seed=59)
+    p = srd.Params((12, 12, 12), seed=59, thermostat=True)
     pos, vel = workloads.fluid(p.n_cells, 9, seed=60)
     vel = vel - (pos - p.L / 2)
     mass = np.ones(pos.shape[0])
