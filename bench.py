@@ -6,7 +6,9 @@ Workload (default): the 100^3-cell fluid at 10 particles per cell (10^7
 particles), alpha = 130 deg, dt = 0.1, kT = 1, random grid shift,
 Maxwell-Boltzmann cell thermostat, synthetic positions/velocities (seed 1).
 The headline value is the FP32 cell-relative form; the plain FP64 form runs on
-the same input and is reported beside it. A step is one whole pass of the hot
+the same input and is reported beside it, and so does the Andersen-thermostat
+collision rule (eq. 4) in both forms (without the cell thermostat, which that
+rule replaces). A step is one whole pass of the hot
 path: stream, grid shift, binning, cell reduction, draws and rotation.
 
     python bench.py --workload srd_400c_rho5_beads
@@ -29,9 +31,16 @@ serves an open-loop stream of requests (Poisson, 50 per second for 60 s;
 returning its n^3 x 3 cell-averaged velocity field: served vs offered
 throughput and request latency p50/p99.
 
+    python bench.py --workload srd_400c_rho5_md
+
+couples the beads of the 400^3 box through an external MD integrator: per
+collision their state is handed over and read back on device buffers (50
+collisions), beside the same context stepped without the exchange.
+
 Prints one JSON line. `roofline` is for the dominant kernel (the collide
 kernel), timed with HIP events on the library's own stream during the timed
-region (the first launch and then one in every PROFILE_EVERY); `cpu_baseline` is the FP64 numpy oracle on a bounded sample.
+region (the first launch and then one in every PROFILE_EVERY);
+`cpu_baseline` is the FP64 numpy oracle on a bounded sample.
 """
 import argparse
 import json
@@ -86,11 +95,13 @@ def measured_traffic(form, workload=WORKLOAD):
     return rec.get("bytes_per_launch", {}).get(workload, {}).get(form)
 
 
-def run_form(m, inp, cfg, precision, steps, warmup):
+def run_form(m, inp, cfg, precision, steps, warmup, collision=0):
     import torch
     pos, vel, bpos, bvel, bmass = inp
+    # the AT rule thermostats by itself: it runs without the cell thermostat
+    thermo = cfg["thermostat"] if collision == m.SRD else False
     sim = m.Sim(pos, vel, cfg["n_cells"], kT=cfg["kT"], seed=cfg["seed"],
-                precision=precision, thermostat=cfg["thermostat"],
+                precision=precision, thermostat=thermo, collision=collision,
                 emb_pos=bpos, emb_vel=bvel, emb_mass=bmass)
     try:
         sim.step(warmup)
@@ -314,6 +325,77 @@ def bench_serve(m, workloads, cfg, args, workers=4, stop_after=75.0):
     print(json.dumps(out), flush=True)
 
 
+def bench_md(m, workloads, cfg, args):
+    """Solutes coupled through an external MD integrator (sec. 3.6): per
+    collision the beads' state is handed over (mpcd_set_embedded), one step
+    runs and the collided bead velocities come back (mpcd_get_embedded), on
+    device buffers. The integrator itself (forces, moving the beads) is the
+    caller's and is not part of the timed cycle, so the beads keep their
+    positions here; the same context is then stepped without the exchange
+    for comparison."""
+    import torch
+    steps = cfg["steps"] if args.steps == 1000 else args.steps
+    pos, vel, bpos, bvel, bmass = make_input(cfg)
+    N = pos.shape[0] + bpos.shape[0]
+    torch.cuda.init()
+    sim = m.Sim(pos, vel, cfg["n_cells"], kT=cfg["kT"], seed=cfg["seed"], precision=m.FP32,
+                thermostat=False, emb_pos=bpos, emb_vel=bvel, emb_mass=bmass,
+                flags=m.binding.FLAG_MD_SOLUTE)
+    del pos, vel
+    dpos = torch.from_numpy(bpos).cuda()
+    dvel = torch.from_numpy(bvel).cuda()
+    torch.cuda.synchronize()
+
+    def cycle():
+        sim.set_embedded_device(dpos.data_ptr(), dvel.data_ptr())
+        sim.step(1)
+        sim.get_embedded_device(dpos.data_ptr(), dvel.data_ptr())
+
+    try:
+        for _ in range(args.warmup):
+            cycle()
+        sim.sync()
+        sim.profile(True, every=PROFILE_EVERY)
+        for w in (0, 1):
+            sim.profile_read(w)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            cycle()
+        sim.sync()
+        t1 = time.perf_counter()
+        coll_ms, coll_n = sim.profile_read(0)
+        bin_ms, bin_n = sim.profile_read(1)
+        t2 = time.perf_counter()
+        sim.step(steps)
+        sim.sync()
+        t3 = time.perf_counter()
+        sim.profile(False)
+    finally:
+        sim.close()
+    cyc = (t1 - t0) / steps
+    plain = (t3 - t2) / steps
+    avg_us = 1e3 * coll_ms / max(coll_n, 1)
+    gbs = collide_bytes_per_particle("fp32", cfg["density"]) * N / (avg_us * 1e-6) / 1e9
+    out = {
+        "metric": "particle-updates/s (stream+bin+SRD collide) FP32 vs FP64; p99 batch latency",
+        "value": N / cyc, "unit": "particle-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * cyc, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "srd_400c_rho5_md", "n_cells": list(cfg["n_cells"]),
+                   "particles": N, "density": cfg["density"], "embedded_beads": int(bpos.shape[0]),
+                   "coupling": "external MD, state exchanged on device every collision",
+                   "thermostat": "none", "form": "fp32"},
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_tile (collide + stream + bin + scatter)", "kernel_avg_us": avg_us,
+                     "bytes_per_particle": collide_bytes_per_particle("fp32", cfg["density"])},
+        "bin_kernel_avg_us": 1e3 * bin_ms / max(bin_n, 1),
+        "ms_per_step_without_exchange": 1e3 * plain,
+        "exchange_overhead_ms": 1e3 * (cyc - plain),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -322,10 +404,11 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default=None,
-                    help="storage forms to time (default fp32,fp64; fp32 for the large box)")
+                    help="storage forms to time, a suffix _at for the Andersen-thermostat "
+                         "rule (default fp32,fp64,fp32_at,fp64_at; fp32 for the large box)")
     ap.add_argument("--workload", default=WORKLOAD,
                     choices=["srd_100c_rho10_mbthermo", "srd_400c_rho5_beads",
-                             "srd_batch256_fp32", "srd_serve_poisson50"])
+                             "srd_batch256_fp32", "srd_serve_poisson50", "srd_400c_rho5_md"])
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the streaming copy kernel (1 GiB, 20 times)")
     args = ap.parse_args()
@@ -348,6 +431,8 @@ def main():
         return bench_batch(m, workloads, cfg, args)
     if wl == "srd_serve_poisson50":
         return bench_serve(m, workloads, cfg, args)
+    if wl == "srd_400c_rho5_md":
+        return bench_md(m, workloads, cfg, args)
     big = wl != WORKLOAD
     if big and args.steps == 1000:
         args.steps = cfg["steps"]
@@ -355,19 +440,25 @@ def main():
     N = inp[0].shape[0] + (0 if inp[2] is None else inp[2].shape[0])
     rho = cfg["density"]
     torch.cuda.init()
-    forms = [f.strip() for f in (args.forms or ("fp32" if big else "fp32,fp64")).split(",")
-             if f.strip()]
+    forms = [f.strip() for f in (args.forms or ("fp32" if big else "fp32,fp64,fp32_at,fp64_at"))
+             .split(",") if f.strip()]
     res = {}
     for form in forms:
-        prec = m.FP32 if form == "fp32" else m.FP64
-        r = run_form(m, inp, cfg, prec, args.steps, args.warmup)
+        base = form.split("_")[0]
+        if base not in STATE_BYTES or form not in (base, base + "_at"):
+            sys.exit(f"unknown form {form}")
+        prec = m.FP32 if base == "fp32" else m.FP64
+        rule = m.AT if form.endswith("_at") else m.SRD
+        r = run_form(m, inp, cfg, prec, args.steps, args.warmup, rule)
         r["updates_per_s"] = N * args.steps / r["seconds"]
         r["ms_per_step"] = 1e3 * r["seconds"] / args.steps
         avg_us = 1e3 * r["collide_ms"] / max(r["collide_launches"], 1)
         r["collide_avg_us"] = avg_us
-        per_launch = collide_bytes_per_particle(form, rho) * N
+        per_launch = collide_bytes_per_particle(base, rho) * N
         r["collide_GBs"] = per_launch / (avg_us * 1e-6) / 1e9
-        r["step_floor_frac"] = r["updates_per_s"] * floor_bytes_per_update(form, rho) / (HBM_PEAK_GBS * 1e9)
+        r["step_floor_frac"] = r["updates_per_s"] * floor_bytes_per_update(base, rho) / (HBM_PEAK_GBS * 1e9)
+        r["rule"] = "at" if rule == m.AT else "srd"
+        r["thermostat"] = "maxwell-boltzmann" if (cfg["thermostat"] and rule == m.SRD) else "none"
         res[form] = r
         print(f"[bench] {form}: {r['updates_per_s']:.4g} updates/s, "
               f"{r['ms_per_step']:.4f} ms/step, collide {avg_us:.1f} us "
@@ -387,7 +478,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if head_form == "fp32" else "f64",
+        "dtype": "f32" if head_form.startswith("fp32") else "f64",
         "data": "synthetic",
         "config": {"workload": wl, "n_cells": list(cfg["n_cells"]),
                    "particles": N, "density": rho, "alpha_deg": 130, "dt": 0.1,
@@ -401,15 +492,15 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": head["collide_GBs"] / HBM_PEAK_GBS,
-            "traffic": measured_traffic(head_form, wl),
+            "traffic": measured_traffic(head_form, wl) if head_form in STATE_BYTES else None,
             "kernel": "k_tile (collide + stream + bin + scatter)",
             "kernel_avg_us": head["collide_avg_us"],
-            "bytes_per_particle": collide_bytes_per_particle(head_form, rho),
+            "bytes_per_particle": collide_bytes_per_particle(head_form.split("_")[0], rho),
         },
         "step_floor_frac": head["step_floor_frac"],
         "forms": {f: {"updates_per_s": r["updates_per_s"], "ms_per_step": r["ms_per_step"],
                       "collide_avg_us": r["collide_avg_us"], "collide_GBs": r["collide_GBs"],
-                      "draw_avg_us": r["draw_us"],
+                      "draw_avg_us": r["draw_us"], "rule": r["rule"], "thermostat": r["thermostat"],
                       "step_floor_frac": r["step_floor_frac"], "kT_end": r["kT"],
                       "net_momentum_end": r["net_momentum"]} for f, r in res.items()},
     }
@@ -417,6 +508,9 @@ def main():
     out["roofline"]["frac_of_copy_ceiling"] = head["collide_GBs"] / out["copy_ceiling_GBs"]
     if "fp32" in res and "fp64" in res:
         out["fp32_over_fp64"] = res["fp32"]["updates_per_s"] / res["fp64"]["updates_per_s"]
+    for base in ("fp32", "fp64"):  # the AT rule against the thermostatted SRD step
+        if base in res and base + "_at" in res:
+            out[base + "_at_over_srd"] = res[base + "_at"]["updates_per_s"] / res[base]["updates_per_s"]
     if not args.no_cpu_baseline:
         if big:
             out["cpu_baseline"] = cpu_baseline(make_input(cfg, scale=60), (60, 60, 60), cfg,

@@ -166,8 +166,9 @@ mpcd_status mpcd_collide(mpcd_ctx ctx);
  * collision; the state every get_* reads is the collided one either way.
  * mpcd_stream, mpcd_set_embedded and a changed step counter give the
  * prepared binning up (the next mpcd_step then streams and bins first), as
- * does a slab overflow in that launch. Results never depend on how a run is
- * split into calls. */
+ * does a slab overflow in that launch; with MPCD_FLAG_MD_SOLUTE, where the
+ * solutes' state is handed over before every collision, no binning is
+ * prepared. Results never depend on how a run is split into calls. */
 mpcd_status mpcd_step(mpcd_ctx ctx, int64_t nsteps);
 
 /* State of the embedded particles only (tags n_solvent .. n_total - 1, box 0):
@@ -178,7 +179,10 @@ mpcd_status mpcd_step(mpcd_ctx ctx, int64_t nsteps);
  * the values are stored in the context's precision; the next binning moves
  * each particle to the tile of its new position. MPCD_EINVAL if the context
  * has no embedded particles. The exchange with an MD integrator
- * (MPCD_FLAG_MD_SOLUTE). */
+ * (MPCD_FLAG_MD_SOLUTE). The context keeps the slot of every embedded
+ * particle, so both calls cost O(n_embedded) work on the device (one thread
+ * per particle), whatever the number of solvent particles; with device
+ * pointers they allocate nothing. */
 mpcd_status mpcd_get_embedded(mpcd_ctx ctx, double* pos, double* vel,
                               int32_t pointers_on_device);
 mpcd_status mpcd_set_embedded(mpcd_ctx ctx, const double* pos, const double* vel,

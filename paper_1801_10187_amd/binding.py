@@ -59,6 +59,14 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: run "
                           "`python -m paper_1801_10187_amd.build` first")
+    # torch ships its own HIP runtime under the same soname as the system's.
+    # Whichever is loaded first is the one the library links to; with torch
+    # imported first, the library and torch share that one runtime (two
+    # runtimes in one process leave torch without a device).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     st = ctypes.c_int
     sig = {
@@ -222,6 +230,16 @@ class Sim:
         pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
         vel = np.ascontiguousarray(vel, dtype=np.float64).reshape(-1, 3)
         _check(load().mpcd_set_embedded(self._ctx, _ptr(pos), _ptr(vel), 0))
+
+    def get_embedded_device(self, pos_ptr, vel_ptr):
+        """get_embedded into device buffers of n_embedded x 3 doubles each."""
+        _check(load().mpcd_get_embedded(self._ctx, ctypes.c_void_p(pos_ptr),
+                                        ctypes.c_void_p(vel_ptr), 1))
+
+    def set_embedded_device(self, pos_ptr, vel_ptr):
+        """set_embedded from device buffers of n_embedded x 3 doubles each."""
+        _check(load().mpcd_set_embedded(self._ctx, ctypes.c_void_p(pos_ptr),
+                                        ctypes.c_void_p(vel_ptr), 1))
 
     def velocity_field(self):
         """Mass-weighted mean velocity (n_cells, 3) and mass (n_cells) per

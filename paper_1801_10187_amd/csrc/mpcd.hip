@@ -100,6 +100,8 @@ struct mpcd_ctx_s {
   uint32_t* cnt[3] = {nullptr, nullptr, nullptr};
   int ci = 0;                      // cnt[ci] describes buf[cur]
   double* emb_mass = nullptr;
+  uint32_t* flag = nullptr;        // one word a host call checks after a kernel (range errors)
+  uint32_t* eslot[2] = {nullptr, nullptr};  // slot of each embedded particle in buf[0], buf[1]
   uint32_t* status = nullptr;      // [0] errors, [1] overflow, [2] failing launch
   double* ehat = nullptr;          // thermostat draws of the next collision, [tile][cpt]
   long long* tot = nullptr;        // fixed-point totals, 10 words per box
@@ -278,6 +280,7 @@ TileArgs tile_args(mpcd_ctx c) {
   a.emb_mass = c->emb_mass;
   a.status = c->status;
   a.ehat = c->ehat;
+  a.eslot_out = c->n_emb ? c->eslot[1 - c->cur] : nullptr;
   return a;
 }
 
@@ -398,9 +401,11 @@ mpcd_status regrow(mpcd_ctx c, int in_cur, int in_ci) {
   S.cap = new_cap;
   const uint32_t blocks = nt * ((old_cap + 255u) / 256u);
   if (c->form == 0)
-    k_repack<0><<<blocks, 256, 0, c->stream>>>(c->buf[in_cur], nb[0], S, old_cap, c->cnt[in_ci]);
+    k_repack<0><<<blocks, 256, 0, c->stream>>>(c->buf[in_cur], nb[0], S, old_cap, c->cnt[in_ci],
+                                               c->n_emb ? c->eslot[0] : nullptr);
   else
-    k_repack<1><<<blocks, 256, 0, c->stream>>>(c->buf[in_cur], nb[0], S, old_cap, c->cnt[in_ci]);
+    k_repack<1><<<blocks, 256, 0, c->stream>>>(c->buf[in_cur], nb[0], S, old_cap, c->cnt[in_ci],
+                                               c->n_emb ? c->eslot[0] : nullptr);
   HIP_TRY(hipGetLastError());
   if (in_ci != 0)
     HIP_TRY(hipMemcpyAsync(c->cnt[0], c->cnt[in_ci], (size_t)nt * 4, hipMemcpyDeviceToDevice, c->stream));
@@ -651,6 +656,12 @@ mpcd_status create_impl(int32_t nbox, const mpcd_params* params, const int64_t* 
   Box* dboxes = (Box*)c->dalloc((size_t)nbox * sizeof(Box));
   uint32_t* dtb = (uint32_t*)c->dalloc((size_t)NT * 4);
   uint32_t* bad = (uint32_t*)c->dalloc(256);
+  c->flag = bad;
+  if (c->n_emb) {
+    c->eslot[0] = (uint32_t*)c->dalloc((size_t)c->n_emb * 4);
+    c->eslot[1] = (uint32_t*)c->dalloc((size_t)c->n_emb * 4);
+    if (!c->eslot[0] || !c->eslot[1]) return cleanup(fail(MPCD_ENOMEM, "device allocation failed"));
+  }
   if (!c->cnt[0] || !c->cnt[1] || !c->cnt[2] || !c->status || !c->tot || !c->emb_mass || !dboxes ||
       !dtb || !bad)
     return cleanup(fail(MPCD_ENOMEM, "device allocation failed"));
@@ -703,6 +714,7 @@ mpcd_status create_impl(int32_t nbox, const mpcd_params* params, const int64_t* 
   }
   // one import launch per (box, particle kind)
   auto import_all = [&](bool place, uint32_t cap, uint32_t* cnt) {
+    uint32_t* es = c->n_emb ? c->eslot[0] : nullptr;
     uint64_t row = 0;
     for (uint32_t b = 0; b < c->nbox; ++b) {
       const Box& B = c->boxes[b];
@@ -717,11 +729,11 @@ mpcd_status create_impl(int32_t nbox, const mpcd_params* params, const int64_t* 
         if (q.n == 0) continue;
         const uint32_t g = blocks_for(q.n, kGrid);
         if (c->form == 0) {
-          if (place) k_import<0, true><<<g, kGrid, 0, c->stream>>>(c->buf[0], B, cap, q.p, q.v, q.n, q.tag0, cnt, bad);
-          else k_import<0, false><<<g, kGrid, 0, c->stream>>>(c->buf[0], B, cap, q.p, q.v, q.n, q.tag0, cnt, bad);
+          if (place) k_import<0, true><<<g, kGrid, 0, c->stream>>>(c->buf[0], B, cap, q.p, q.v, q.n, q.tag0, cnt, bad, es);
+          else k_import<0, false><<<g, kGrid, 0, c->stream>>>(c->buf[0], B, cap, q.p, q.v, q.n, q.tag0, cnt, bad, es);
         } else {
-          if (place) k_import<1, true><<<g, kGrid, 0, c->stream>>>(c->buf[0], B, cap, q.p, q.v, q.n, q.tag0, cnt, bad);
-          else k_import<1, false><<<g, kGrid, 0, c->stream>>>(c->buf[0], B, cap, q.p, q.v, q.n, q.tag0, cnt, bad);
+          if (place) k_import<1, true><<<g, kGrid, 0, c->stream>>>(c->buf[0], B, cap, q.p, q.v, q.n, q.tag0, cnt, bad, es);
+          else k_import<1, false><<<g, kGrid, 0, c->stream>>>(c->buf[0], B, cap, q.p, q.v, q.n, q.tag0, cnt, bad, es);
         }
       }
     }
@@ -930,9 +942,13 @@ mpcd_status mpcd_step(mpcd_ctx c, int64_t nsteps) {
   } else {
     L.push_back({Op::BinStream, c->step});
   }
+  // With solutes coupled to an MD integrator the caller hands their new state
+  // over before every collision, which gives a prepared binning up: such a
+  // call ends with the plain collision, which writes less.
+  const Op last = (c->p.flags & MPCD_FLAG_MD_SOLUTE) ? Op::Collide : Op::CollideKeep;
   for (int64_t k = 0; k < nsteps; ++k) {
     if (c->p.thermostat) L.push_back({Op::Draw, c->step + (uint64_t)k});
-    L.push_back({k + 1 < nsteps ? Op::CollideScatter : Op::CollideKeep, c->step + (uint64_t)k});
+    L.push_back({k + 1 < nsteps ? Op::CollideScatter : last, c->step + (uint64_t)k});
   }
   ST_TRY(run_launches(c, L));
   c->step += (uint64_t)nsteps;
@@ -983,17 +999,25 @@ mpcd_status mpcd_get_embedded(mpcd_ctx c, double* pos, double* vel, int32_t on_d
     dp = tmp;
     dv = tmp + 3 * n;
   }
-  const uint32_t nb = slab_blocks(c, c->S.cap);
-  if (c->form == 0) k_emb_export<0><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->S, c->cnt[c->ci], dp, dv);
-  else k_emb_export<1><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->S, c->cnt[c->ci], dp, dv);
-  hipError_t e = hipGetLastError();
+  const uint32_t nb = blocks_for(n, kGrid);
+  hipError_t e = hipMemsetAsync(c->flag, 0, 4, c->stream);
+  if (e == hipSuccess) {
+    if (c->form == 0)
+      k_emb_export<0><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->boxes[0], c->eslot[c->cur], (uint32_t)n, (size_t)c->S.ntiles * c->S.cap, dp, dv, c->flag);
+    else
+      k_emb_export<1><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->boxes[0], c->eslot[c->cur], (uint32_t)n, (size_t)c->S.ntiles * c->S.cap, dp, dv, c->flag);
+    e = hipGetLastError();
+  }
+  uint32_t hflag = 0;
   if (e == hipSuccess && tmp) {
     e = hipMemcpyAsync(pos, dp, n * 24, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(vel, dv, n * 24, hipMemcpyDeviceToHost, c->stream);
   }
+  if (e == hipSuccess) e = hipMemcpyAsync(&hflag, c->flag, 4, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (tmp) (void)hipFree(tmp);
   if (e != hipSuccess) return fail(MPCD_EHIP, "get_embedded: %s", hipGetErrorString(e));
+  if (hflag) return fail(MPCD_EHIP, "get_embedded: the embedded-particle index is out of date");
   return take_err(c);
 }
 
@@ -1006,28 +1030,30 @@ mpcd_status mpcd_set_embedded(mpcd_ctx c, const double* pos, const double* vel, 
   const size_t n = c->n_emb;
   const double* dp = pos;
   const double* dv = vel;
-  double* tmp = nullptr;
-  uint32_t* bad = nullptr;
-  HIP_TRY(hipMalloc(&bad, 256 + (on_device ? 0 : n * 48)));
-  hipError_t e = hipMemsetAsync(bad, 0, 4, c->stream);
+  double* tmp = nullptr;  // host arrays are staged through device memory
+  hipError_t e = hipSuccess;
   if (!on_device) {
-    tmp = (double*)((char*)bad + 256);
-    if (e == hipSuccess) e = hipMemcpyAsync(tmp, pos, n * 24, hipMemcpyHostToDevice, c->stream);
+    HIP_TRY(hipMalloc(&tmp, n * 48));
+    e = hipMemcpyAsync(tmp, pos, n * 24, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(tmp + 3 * n, vel, n * 24, hipMemcpyHostToDevice, c->stream);
     dp = tmp;
     dv = tmp + 3 * n;
   }
+  if (e == hipSuccess) e = hipMemsetAsync(c->flag, 0, 4, c->stream);
   if (e == hipSuccess) {
-    const uint32_t nb = slab_blocks(c, c->S.cap);
-    if (c->form == 0) k_emb_import<0><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->S, c->cnt[c->ci], dp, dv, bad);
-    else k_emb_import<1><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->S, c->cnt[c->ci], dp, dv, bad);
+    const uint32_t nb = blocks_for(n, kGrid);
+    if (c->form == 0)
+      k_emb_import<0><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->boxes[0], c->eslot[c->cur], (uint32_t)n, (size_t)c->S.ntiles * c->S.cap, dp, dv, c->flag);
+    else
+      k_emb_import<1><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->boxes[0], c->eslot[c->cur], (uint32_t)n, (size_t)c->S.ntiles * c->S.cap, dp, dv, c->flag);
     e = hipGetLastError();
   }
   uint32_t hbad = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, c->flag, 4, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  (void)hipFree(bad);
+  if (tmp) (void)hipFree(tmp);
   if (e != hipSuccess) return fail(MPCD_EHIP, "set_embedded: %s", hipGetErrorString(e));
+  if (hbad & 4u) return fail(MPCD_EHIP, "set_embedded: the embedded-particle index is out of date");
   if (hbad) return fail(MPCD_EINVAL, "an embedded position lies outside [0, L)");
   return take_err(c);
 }

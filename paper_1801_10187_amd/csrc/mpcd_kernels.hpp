@@ -446,7 +446,16 @@ struct TileArgs {
   double* d_xi;
   uint32_t keep;            // collide + scatter: also write the collided
                             // velocities back into the input slots
+  uint32_t* eslot_out;      // slot of each embedded particle in the output
+                            // buffer (null without embedded particles)
 };
+
+// Record the slot j of an embedded particle (tag) in the index of the buffer
+// it was written to; solvent particles are not indexed.
+__device__ inline void note_slot(uint32_t* eslot, const Box& B, uint32_t tag, size_t j) {
+  const uint32_t i = tag - B.tag0;
+  if (i >= B.n_solvent) eslot[i - B.n_solvent] = (uint32_t)j;
+}
 
 // Fixed-point accumulator rows of one cell sum: the FP64 form keeps two limbs
 // (fx_split), the FP32 form one (fx1_split).
@@ -618,6 +627,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
   auto put = [&](size_t j, const VT w[3], uint32_t tag, const Pos<FORM>& rr, uint32_t lcell) {
     store_part<FORM>(A.out, j, rr, w, tag);
     st(A.out.lc, j, (uint8_t)lcell);
+    if (A.eslot_out) note_slot(A.eslot_out, B, tag, j);
   };
   auto scatter = [&](const double* sd, const float* sd32, const VT (*w)[3]) {
     // per particle: local cell in the destination (bits 0-7), bin (8-12),
@@ -817,6 +827,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
             const Particles Out = tile_view<FORM>(A.out, tbase);
             store_part<FORM>(Out, k, r[q], v[q], tg[q]);
             st(Out.lc, k, (uint8_t)lcs[q]);
+            if (A.eslot_out) note_slot(A.eslot_out, B, tg[q], tbase + k);
           } else {
             if (A.keep) store_vel<FORM>(In, k, r[q], v[q], tg[q]);
             if (streamed(B, tg[q])) r[q].stream(B, v[q], err);
@@ -837,6 +848,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
           const Particles Out = tile_view<FORM>(A.out, tbase);
           store_part<FORM>(Out, k, rr, ww, tag);
           st(Out.lc, k, (uint8_t)lc);
+          if (A.eslot_out) note_slot(A.eslot_out, B, tag, tbase + k);
         } else {
           if (A.keep) store_vel<FORM>(In, k, rr, ww, tag);
           if (streamed(B, tag)) rr.stream(B, ww, err);
@@ -1178,7 +1190,7 @@ __global__ __launch_bounds__(256) void k_import(Particles P, Box B, uint32_t cap
                                                 const double* __restrict__ pos,
                                                 const double* __restrict__ vel,
                                                 uint32_t n, uint32_t tag0, uint32_t* cnt,
-                                                uint32_t* bad_pos) {
+                                                uint32_t* bad_pos, uint32_t* eslot) {
   const uint32_t t = blockIdx.x * 256u + threadIdx.x;
   if (t >= n) return;
   double x[3], v[3];
@@ -1205,6 +1217,7 @@ __global__ __launch_bounds__(256) void k_import(Particles P, Box B, uint32_t cap
     if (slot < cap) {
       const size_t j = (size_t)T * cap + slot;
       store_part<FORM>(P, j, r, w, tag0 + t);
+      if (eslot) note_slot(eslot, B, tag0 + t, j);
     } else {
       atomicOr(bad_pos, 2u);
     }
@@ -1244,19 +1257,30 @@ __global__ __launch_bounds__(256) void k_export(Particles P, Slabs S, const uint
 // row-major n_emb x 3 doubles: the exchange with an external MD integrator
 // between collisions. The update writes in place; the next binning moves a
 // particle to the tile of its new position.
+// Embedded particles of box B (the only box that has them), one thread
+// each, found through the slot index of the current buffer (nslots slots).
+// A slot out of range or not holding the expected tag sets bit 2 of *flag
+// and is left alone.
 template <int FORM>
-__global__ __launch_bounds__(256) void k_emb_export(Particles P, Slabs S, const uint32_t* cnt,
-                                                    double* __restrict__ pos, double* __restrict__ vel) {
-  const SlabIter s = slab_slot(S, cnt);
-  if (!s.valid) return;
-  const Box B = S.boxes[S.tile_box[s.T]];
+__global__ __launch_bounds__(256) void k_emb_export(Particles P, Box B, const uint32_t* __restrict__ eslot,
+                                                    uint32_t n, size_t nslots, double* __restrict__ pos,
+                                                    double* __restrict__ vel, uint32_t* flag) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= n) return;
+  const size_t j = eslot[i];
+  if (j >= nslots) {
+    atomicOr(flag, 4u);
+    return;
+  }
   typename VelT<FORM>::T v[3];
   uint32_t t;
   Pos<FORM> r;
-  load_part<FORM>(P, s.i, r, v, t);
-  const uint32_t i = t - B.tag0;
-  if (i < B.n_solvent) return;
-  const size_t row = 3ull * (i - B.n_solvent);
+  load_part<FORM>(P, j, r, v, t);
+  if (t != B.tag0 + B.n_solvent + i) {
+    atomicOr(flag, 4u);
+    return;
+  }
+  const size_t row = 3ull * i;
   if constexpr (FORM == 0) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) pos[row + d] = r.x[d];
@@ -1270,17 +1294,20 @@ __global__ __launch_bounds__(256) void k_emb_export(Particles P, Slabs S, const 
   for (int d = 0; d < 3; ++d) vel[row + d] = (double)v[d];
 }
 
+// Positions outside [0, L) set bit 0 of *flag and are not stored.
 template <int FORM>
-__global__ __launch_bounds__(256) void k_emb_import(Particles P, Slabs S, const uint32_t* cnt,
-                                                    const double* __restrict__ pos,
-                                                    const double* __restrict__ vel, uint32_t* bad_pos) {
-  const SlabIter s = slab_slot(S, cnt);
-  if (!s.valid) return;
-  const Box B = S.boxes[S.tile_box[s.T]];
-  const uint32_t t = load_tag<FORM>(P, s.i);
-  const uint32_t i = t - B.tag0;
-  if (i < B.n_solvent) return;
-  const size_t row = 3ull * (i - B.n_solvent);
+__global__ __launch_bounds__(256) void k_emb_import(Particles P, Box B, const uint32_t* __restrict__ eslot,
+                                                    uint32_t n, size_t nslots, const double* __restrict__ pos,
+                                                    const double* __restrict__ vel, uint32_t* flag) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= n) return;
+  const size_t j = eslot[i];
+  const uint32_t t = B.tag0 + B.n_solvent + i;
+  if (j >= nslots || load_tag<FORM>(P, j) != t) {
+    atomicOr(flag, 4u);
+    return;
+  }
+  const size_t row = 3ull * i;
   double x[3];
   bool bad = false;
 #pragma unroll
@@ -1289,21 +1316,21 @@ __global__ __launch_bounds__(256) void k_emb_import(Particles P, Slabs S, const 
     bad |= !(x[d] >= 0.0 && x[d] < B.L[d]);
   }
   if (bad) {
-    atomicOr(bad_pos, 1u);
+    atomicOr(flag, 1u);
     return;
   }
   using VT = typename VelT<FORM>::T;
   const VT w[3] = {(VT)vel[row], (VT)vel[row + 1], (VT)vel[row + 2]};
   Pos<FORM> r;
   to_form<FORM>(B, x, r);
-  store_part<FORM>(P, s.i, r, w, t);
+  store_part<FORM>(P, j, r, w, t);
 }
 
 // Copy the valid slots of every tile from slabs of capacity old_cap to slabs
 // of capacity S.cap (S.cap >= old_cap); used when slabs are enlarged.
 template <int FORM>
 __global__ __launch_bounds__(256) void k_repack(Particles src, Particles dst, Slabs S,
-                                                uint32_t old_cap, const uint32_t* cnt) {
+                                                uint32_t old_cap, const uint32_t* cnt, uint32_t* eslot) {
   const uint32_t per = (old_cap + 255u) / 256u;
   const uint32_t T = blockIdx.x / per;
   const uint32_t k = (blockIdx.x % per) * 256u + threadIdx.x;
@@ -1315,6 +1342,7 @@ __global__ __launch_bounds__(256) void k_repack(Particles src, Particles dst, Sl
   load_part<FORM>(src, i, r, v, tag);
   store_part<FORM>(dst, j, r, v, tag);
   dst.lc[j] = src.lc[i];
+  if (eslot) note_slot(eslot, S.boxes[S.tile_box[T]], tag, j);
 }
 
 // --------------------------------------------------------- test kernels

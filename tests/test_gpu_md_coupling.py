@@ -69,3 +69,35 @@ def test_md_solutes_are_not_streamed():
         bad[0, 0] = -1.0
         with pytest.raises(m.MpcdError):
             s.set_embedded(bad, ev)
+
+
+def test_md_exchange_on_device_buffers():
+    """The exchange through device buffers gives the host-array exchange's
+    results bit for bit (pointers_on_device = 1)."""
+    import torch
+    banner("md exchange on device buffers")
+    p = srd.Params((8, 8, 8), seed=77, thermostat=True)
+    pos, vel = workloads.fluid(p.n_cells, 6, seed=78)
+    bpos, bvel, bmass = workloads.beads(p.n_cells, 3, 8, seed=79)
+    kw = dict(seed=p.seed, thermostat=True, emb_pos=bpos, emb_vel=bvel, emb_mass=bmass,
+              flags=m.binding.FLAG_MD_SOLUTE)
+    with m.Sim(pos, vel, p.n_cells, **kw) as a, m.Sim(pos, vel, p.n_cells, **kw) as b:
+        dpos = torch.empty((bpos.shape[0], 3), dtype=torch.float64, device="cuda")
+        dvel = torch.empty_like(dpos)
+        hp, hv = bpos.copy(), bvel.copy()
+        for _ in range(3):
+            hp = (hp + 0.05) % p.L            # stands in for the integrator's move
+            dpos.copy_(torch.from_numpy(hp))
+            dvel.copy_(torch.from_numpy(hv))
+            torch.cuda.synchronize()
+            a.set_embedded(hp, hv)
+            a.step(1)
+            hp, hv = a.get_embedded()
+            b.set_embedded_device(dpos.data_ptr(), dvel.data_ptr())
+            b.step(1)
+            b.get_embedded_device(dpos.data_ptr(), dvel.data_ptr())
+            assert np.array_equal(dpos.cpu().numpy(), hp)
+            assert np.array_equal(dvel.cpu().numpy(), hv)
+        pa, va = a.get_state()
+        pb, vb = b.get_state()
+    assert np.array_equal(pa, pb) and np.array_equal(va, vb)

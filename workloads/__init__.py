@@ -138,6 +138,11 @@ CONFIGS = {
     "srd_400c_rho5_beads": dict(n_cells=(400, 400, 400), density=5, kT=1.0,
                                 thermostat=False, steps=200, seed=1,
                                 chains=20000, chain_len=50, bead_mass=5.0),
+    # the same box with the beads coupled through an external MD integrator
+    # (MPCD_FLAG_MD_SOLUTE): state exchanged on device buffers every collision
+    "srd_400c_rho5_md": dict(n_cells=(400, 400, 400), density=5, kT=1.0,
+                             thermostat=False, steps=50, seed=1,
+                             chains=20000, chain_len=50, bead_mass=5.0),
     # 256 independent boxes (replica_boxes): sides 8..64 cells, densities
     # 5..10, kT 0.5..2, Maxwell-Boltzmann thermostat, FP32
     "srd_batch256_fp32": dict(n_rep=256, thermostat=True, steps=500, seed=1),
