@@ -578,7 +578,10 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
   uint32_t tg[TQ];
   uint32_t lcs[TQ];
   Pos<FORM> r[TQ];
-  double dv[AT ? TQ : 1][3];
+  // AT rule: each register-resident particle's kick, drawn once and used by
+  // the cell sums and the update, waits in LDS (in registers it would hold 6
+  // VGPRs per particle slot through the whole kernel and cut occupancy)
+  __shared__ double s_dv[AT ? 3 : 1][AT ? TREG : 1];
   auto kick = [&](uint32_t tag, double m, double out[3]) {
     at_kick(tag - B.tag0, A.step, B.k0, B.k1, sqrt(B.kT / m), out);
   };
@@ -595,7 +598,12 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
   if constexpr (AT) {
 #pragma unroll
     for (int q = 0; q < TQ; ++q)
-      if (tid + (uint32_t)(q * TT) < nreg) kick(tg[q], mass_of(tg[q]), dv[q]);
+      if (tid + (uint32_t)(q * TT) < nreg) {
+        double kv[3];
+        kick(tg[q], mass_of(tg[q]), kv);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) s_dv[d][tid + (uint32_t)(q * TT)] = kv[d];
+      }
   }
 
   // cell thread: the rotation axis needs only (cell, step), so it is drawn
@@ -713,7 +721,14 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
     };
 #pragma unroll
     for (int q = 0; q < TQ; ++q)
-      if (tid + (uint32_t)(q * TT) < nreg) sum_mom(lcs[q], v[q], mass_of(tg[q]), dv[AT ? q : 0]);
+      if (tid + (uint32_t)(q * TT) < nreg) {
+        double kv[3] = {0.0, 0.0, 0.0};
+        if constexpr (AT) {
+#pragma unroll
+          for (int d = 0; d < 3; ++d) kv[d] = s_dv[d][tid + (uint32_t)(q * TT)];
+        }
+        sum_mom(lcs[q], v[q], mass_of(tg[q]), kv);
+      }
     for (uint32_t k = TREG + tid; k < cnt; k += TT) {
       VT vv[3];
       uint32_t tag;
@@ -819,7 +834,12 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
         const uint32_t k = tid + (uint32_t)(q * TT);
         if (k < nreg) {
           VT w[3];
-          rotate(lcs[q], v[q], w, dv[AT ? q : 0]);
+          double kv[3] = {0.0, 0.0, 0.0};
+          if constexpr (AT) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) kv[d] = s_dv[d][k];
+          }
+          rotate(lcs[q], v[q], w, kv);
           v[q][0] = w[0];
           v[q][1] = w[1];
           v[q][2] = w[2];
