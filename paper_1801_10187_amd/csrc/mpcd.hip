@@ -1,15 +1,16 @@
 // libmpcd: host side of the C ABI declared in include/mpcd.h.
 //
 // A context holds one box, or several independent boxes stepped together
-// (a batch). It owns every device buffer (hipMalloc at create, hipFree at
-// destroy) and enqueues all work on one HIP stream. Particles live in
-// fixed-capacity per-tile slabs (see mpcd_kernels.hpp); the tiles of all
-// boxes share the slab arrays, and every launch covers all of them. A call
-// to mpcd_step launches one stream+bin kernel and then, per step, the
-// thermostat draws (if on) and one tile kernel; it waits for the stream at
-// its end to confirm that no slab overflowed. If one did, the input of the
-// failing launch is still intact: the slabs are enlarged, that input is
-// repacked, and the launches are replayed from there.
+// (a batch). It owns every device buffer (stream-ordered allocations on its
+// stream, freed the same way) and enqueues all work on that one HIP stream.
+// Particles live in fixed-capacity per-tile slabs (see mpcd_kernels.hpp); the
+// tiles of all boxes share the slab arrays, and every launch covers all of
+// them. A call to mpcd_step launches, unless the last call left the binning
+// prepared, one stream+bin kernel and then, per step, the thermostat draws
+// (if on) and one tile kernel; it waits for the stream at its end to confirm
+// that no slab overflowed. If one did, the input of the failing launch is
+// still intact: the slabs are enlarged, that input is repacked, and the
+// launches are replayed from there.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -124,10 +125,16 @@ struct mpcd_ctx_s {
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[3];
 
+  // Device memory comes from the stream-ordered allocator on the context's
+  // stream: allocating and freeing never waits for the whole device, so
+  // contexts on other streams (concurrent requests) keep running.
+  hipError_t alloc(void** q, size_t bytes) { return hipMallocAsync(q, bytes ? bytes : 256, stream); }
+  void release(void* q) {
+    if (q) (void)hipFreeAsync(q, stream);
+  }
   void* dalloc(size_t bytes) {
     void* q = nullptr;
-    if (bytes == 0) bytes = 256;
-    if (hipMalloc(&q, bytes) != hipSuccess) return nullptr;
+    if (alloc(&q, bytes) != hipSuccess) return nullptr;
     allocs.push_back(q);
     return q;
   }
@@ -168,13 +175,12 @@ mpcd_status ensure_shifts(mpcd_ctx c, uint64_t n0, uint64_t count) {
   const uint64_t need = count * c->nbox;
   if (need > c->shift_cap) {
     if (c->shifts) {
-      HIP_TRY(hipStreamSynchronize(c->stream));
-      (void)hipFree(c->shifts);
+      c->release(c->shifts);  // stream-ordered: after the launches that read it
       c->shifts = nullptr;
       c->shift_cap = 0;
     }
     const uint64_t cap = std::max<uint64_t>(need, 64);
-    HIP_TRY(hipMalloc(&c->shifts, cap * sizeof(ShiftEntry)));
+    HIP_TRY(c->alloc((void**)&c->shifts, cap * sizeof(ShiftEntry)));
     c->shift_cap = cap;
   }
   k_shifts<<<blocks_for(need, 256), 256, 0, c->stream>>>(c->S.boxes, c->nbox, (uint32_t)n0,
@@ -346,7 +352,7 @@ mpcd_status alloc_slabs(mpcd_ctx c, uint32_t cap, Particles out[2], std::vector<
   const size_t S = (size_t)c->S.ntiles * cap;
   auto get = [&](size_t bytes) -> void* {
     void* q = nullptr;
-    if (hipMalloc(&q, bytes ? bytes : 256) != hipSuccess) return nullptr;
+    if (c->alloc(&q, bytes) != hipSuccess) return nullptr;
     owned.push_back(q);
     return q;
   };
@@ -371,8 +377,8 @@ mpcd_status alloc_slabs(mpcd_ctx c, uint32_t cap, Particles out[2], std::vector<
   return MPCD_OK;
 }
 
-void free_all(std::vector<void*>& v) {
-  for (void* q : v) (void)hipFree(q);
+void free_all(mpcd_ctx c, std::vector<void*>& v) {
+  for (void* q : v) c->release(q);
   v.clear();
 }
 
@@ -394,7 +400,7 @@ mpcd_status regrow(mpcd_ctx c, int in_cur, int in_ci) {
   std::vector<void*> owned;
   mpcd_status st = alloc_slabs(c, new_cap, nb, owned);
   if (st != MPCD_OK) {
-    free_all(owned);
+    free_all(c, owned);
     return st;
   }
   Slabs S = c->S;
@@ -414,7 +420,7 @@ mpcd_status regrow(mpcd_ctx c, int in_cur, int in_ci) {
   const uint32_t st_reset[2] = {0u, 0xFFFFFFFFu};
   HIP_TRY(hipMemcpyAsync(c->status + 1, st_reset, 8, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  free_all(c->slab_allocs);
+  free_all(c, c->slab_allocs);
   c->slab_allocs = owned;
   c->buf[0] = nb[0];
   c->buf[1] = nb[1];
@@ -693,14 +699,13 @@ mpcd_status create_impl(int32_t nbox, const mpcd_params* params, const int64_t* 
   auto free_tmp = [&]() {
     for (auto& s : src)
       if (s.tmp) {
-        (void)hipStreamSynchronize(c->stream);
-        (void)hipFree(s.tmp);
+        c->release(s.tmp);
         s.tmp = nullptr;
       }
   };
   for (auto& s : src) {
     if (s.n == 0 || pointers_on_device) continue;
-    if (hipMalloc(&s.tmp, (size_t)s.n * 48) != hipSuccess) {
+    if (c->alloc((void**)&s.tmp, (size_t)s.n * 48) != hipSuccess) {
       free_tmp();
       return cleanup(fail(MPCD_ENOMEM, "device allocation of the upload buffer failed"));
     }
@@ -875,9 +880,10 @@ mpcd_status mpcd_create_batch(int32_t n_boxes, const mpcd_params* params,
 void mpcd_destroy(mpcd_ctx c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  free_all(c->allocs);
-  free_all(c->slab_allocs);
-  if (c->shifts) (void)hipFree(c->shifts);
+  free_all(c, c->allocs);
+  free_all(c, c->slab_allocs);
+  c->release(c->shifts);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (auto& v : c->ev_used)
     for (auto& pr : v) {
       (void)hipEventDestroy(pr.first);
@@ -966,7 +972,7 @@ mpcd_status mpcd_get_state(mpcd_ctx c, double* pos, double* vel, int32_t on_devi
   double* dv = vel;
   double* tmp = nullptr;
   if (!on_device) {
-    HIP_TRY(hipMalloc(&tmp, (size_t)c->N * 48));
+    HIP_TRY(c->alloc((void**)&tmp, (size_t)c->N * 48));
     dp = tmp;
     dv = tmp + 3 * (size_t)c->N;
   }
@@ -981,7 +987,7 @@ mpcd_status mpcd_get_state(mpcd_ctx c, double* pos, double* vel, int32_t on_devi
     if (e == hipSuccess) e = hipMemcpyAsync(vel, dv, (size_t)c->N * 24, hipMemcpyDeviceToHost, c->stream);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  if (tmp) (void)hipFree(tmp);
+  if (tmp) c->release(tmp);
   if (e != hipSuccess) return fail(MPCD_EHIP, "get_state: %s", hipGetErrorString(e));
   return take_err(c);
 }
@@ -995,7 +1001,7 @@ mpcd_status mpcd_get_embedded(mpcd_ctx c, double* pos, double* vel, int32_t on_d
   double* dv = vel;
   double* tmp = nullptr;
   if (!on_device) {
-    HIP_TRY(hipMalloc(&tmp, n * 48));
+    HIP_TRY(c->alloc((void**)&tmp, n * 48));
     dp = tmp;
     dv = tmp + 3 * n;
   }
@@ -1015,7 +1021,7 @@ mpcd_status mpcd_get_embedded(mpcd_ctx c, double* pos, double* vel, int32_t on_d
   }
   if (e == hipSuccess) e = hipMemcpyAsync(&hflag, c->flag, 4, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  if (tmp) (void)hipFree(tmp);
+  if (tmp) c->release(tmp);
   if (e != hipSuccess) return fail(MPCD_EHIP, "get_embedded: %s", hipGetErrorString(e));
   if (hflag) return fail(MPCD_EHIP, "get_embedded: the embedded-particle index is out of date");
   return take_err(c);
@@ -1033,7 +1039,7 @@ mpcd_status mpcd_set_embedded(mpcd_ctx c, const double* pos, const double* vel, 
   double* tmp = nullptr;  // host arrays are staged through device memory
   hipError_t e = hipSuccess;
   if (!on_device) {
-    HIP_TRY(hipMalloc(&tmp, n * 48));
+    HIP_TRY(c->alloc((void**)&tmp, n * 48));
     e = hipMemcpyAsync(tmp, pos, n * 24, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(tmp + 3 * n, vel, n * 24, hipMemcpyHostToDevice, c->stream);
     dp = tmp;
@@ -1051,7 +1057,7 @@ mpcd_status mpcd_set_embedded(mpcd_ctx c, const double* pos, const double* vel, 
   uint32_t hbad = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&hbad, c->flag, 4, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  if (tmp) (void)hipFree(tmp);
+  if (tmp) c->release(tmp);
   if (e != hipSuccess) return fail(MPCD_EHIP, "set_embedded: %s", hipGetErrorString(e));
   if (hbad & 4u) return fail(MPCD_EHIP, "set_embedded: the embedded-particle index is out of date");
   if (hbad) return fail(MPCD_EINVAL, "an embedded position lies outside [0, L)");
@@ -1066,7 +1072,7 @@ mpcd_status mpcd_get_cells(mpcd_ctx c, int32_t* cell_of_tag, int32_t* counts, in
   int32_t* dcnt = counts;
   int32_t* tmp = nullptr;
   if (!on_device) {
-    HIP_TRY(hipMalloc(&tmp, ((size_t)c->N + C) * 4 + 16));
+    HIP_TRY(c->alloc((void**)&tmp, ((size_t)c->N + C) * 4 + 16));
     dcell = cell_of_tag ? tmp : nullptr;
     dcnt = counts ? tmp + c->N : nullptr;
   }
@@ -1074,7 +1080,7 @@ mpcd_status mpcd_get_cells(mpcd_ctx c, int32_t* cell_of_tag, int32_t* counts, in
   if (dcnt && C) e = hipMemsetAsync(dcnt, 0, C * 4, c->stream);
   if (e == hipSuccess && c->N && (dcell || dcnt)) {
     if (ensure_shifts(c, c->last_bin_step, 1) != MPCD_OK) {
-      if (tmp) (void)hipFree(tmp);
+      if (tmp) c->release(tmp);
       return MPCD_EHIP;
     }
     const uint32_t nb = slab_blocks(c, c->S.cap);
@@ -1090,7 +1096,7 @@ mpcd_status mpcd_get_cells(mpcd_ctx c, int32_t* cell_of_tag, int32_t* counts, in
     if (e == hipSuccess && counts && C) e = hipMemcpyAsync(counts, dcnt, C * 4, hipMemcpyDeviceToHost, c->stream);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  if (tmp) (void)hipFree(tmp);
+  if (tmp) c->release(tmp);
   if (e != hipSuccess) return fail(MPCD_EHIP, "get_cells: %s", hipGetErrorString(e));
   return take_err(c);
 }
@@ -1103,7 +1109,7 @@ static mpcd_status cell_diag(mpcd_ctx c, double* mass, double* mom, double* ek, 
   if (C == 0) return MPCD_OK;
   ST_TRY(ensure_shifts(c, c->step, 1));
   double* tmp = nullptr;
-  HIP_TRY(hipMalloc(&tmp, C * 8 * 9));
+  HIP_TRY(c->alloc((void**)&tmp, C * 8 * 9));
   TileArgs a = tile_args(c);
   a.cnt_out = nullptr;
   a.cnt_clear = nullptr;
@@ -1130,7 +1136,7 @@ static mpcd_status cell_diag(mpcd_ctx c, double* mass, double* mom, double* ek, 
   for (auto& q : cp)
     if (e == hipSuccess && q.dst) e = hipMemcpyAsync(q.dst, q.src, q.n * 8, kind, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  (void)hipFree(tmp);
+  c->release(tmp);
   if (e != hipSuccess) return fail(MPCD_EHIP, "cell diagnostics: %s", hipGetErrorString(e));
   return take_err(c);
 }
@@ -1172,7 +1178,7 @@ mpcd_status mpcd_get_velocity_field(mpcd_ctx c, double* u, double* mass, int32_t
   const size_t C = c->ncells;
   if (C == 0 || (!u && !mass)) return take_err(c);
   unsigned long long* acc = nullptr;
-  HIP_TRY(hipMalloc(&acc, C * 64 + (on_device ? 0 : C * 32)));
+  HIP_TRY(c->alloc((void**)&acc, C * 64 + (on_device ? 0 : C * 32)));
   double* du = on_device ? u : (u ? (double*)(acc + 8 * C) : nullptr);
   double* dm = on_device ? mass : (mass ? (double*)(acc + 8 * C) + 3 * C : nullptr);
   hipError_t e = hipMemsetAsync(acc, 0, C * 64, c->stream);
@@ -1199,7 +1205,7 @@ mpcd_status mpcd_get_velocity_field(mpcd_ctx c, double* u, double* mass, int32_t
     if (e == hipSuccess && mass) e = hipMemcpyAsync(mass, dm, C * 8, hipMemcpyDeviceToHost, c->stream);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  (void)hipFree(acc);
+  c->release(acc);
   if (e != hipSuccess) return fail(MPCD_EHIP, "velocity field: %s", hipGetErrorString(e));
   return take_err(c);
 }
