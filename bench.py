@@ -239,7 +239,7 @@ def bench_batch(m, workloads, cfg, args):
     print(json.dumps(out), flush=True)
 
 
-def bench_serve(m, workloads, cfg, args, workers=4, stop_after=75.0):
+def bench_serve(m, workloads, cfg, args, workers=8, stop_after=75.0):
     """Open-loop serving: requests (workloads.serve_requests) arrive at their
     Poisson times; `workers` host threads each take the oldest arrived
     request, create a context for it on its own HIP stream, run its steps,
@@ -409,6 +409,8 @@ def main():
     ap.add_argument("--workload", default=WORKLOAD,
                     choices=["srd_100c_rho10_mbthermo", "srd_400c_rho5_beads",
                              "srd_batch256_fp32", "srd_serve_poisson50", "srd_400c_rho5_md"])
+    ap.add_argument("--serve-workers", type=int, default=8,
+                    help="host threads serving requests (srd_serve_poisson50)")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the streaming copy kernel (1 GiB, 20 times)")
     args = ap.parse_args()
@@ -430,7 +432,7 @@ def main():
     if wl == "srd_batch256_fp32":
         return bench_batch(m, workloads, cfg, args)
     if wl == "srd_serve_poisson50":
-        return bench_serve(m, workloads, cfg, args)
+        return bench_serve(m, workloads, cfg, args, workers=args.serve_workers)
     if wl == "srd_400c_rho5_md":
         return bench_md(m, workloads, cfg, args)
     big = wl != WORKLOAD
