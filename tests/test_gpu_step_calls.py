@@ -210,3 +210,26 @@ def test_embedded_index_survives_regrow():
     opos, ovel, _ = srd.run(apos, avel, amass, p, 0, 6)
     assert vel_err_fp64(gvel, ovel, m=1.0) < FP64_REL
     assert periodic_dist(gpos, opos, p.L).max() < 1e-12
+
+
+def test_sampled_kernel_timing():
+    """mpcd_profile_enable(P) brackets the first launch of each kind and one
+    in every P after it; P = 0 turns timing off, P < 0 is refused."""
+    banner("sampled kernel timing")
+    p = srd.Params((8, 8, 8), seed=67, thermostat=True)
+    pos, vel = workloads.fluid(p.n_cells, 6, seed=68)
+    with _sim(pos, vel, p) as s:
+        s.step(1)
+        s.profile(True, every=3)
+        s.step(10)
+        ms, n = s.profile_read(0)
+        dms, dn = s.profile_read(2)
+        assert n == 4 and dn == 4 and ms > 0.0 and dms > 0.0   # launches 0, 3, 6, 9
+        s.profile(True, every=1)
+        s.step(5)
+        assert s.profile_read(0)[1] == 5
+        s.profile(False)
+        s.step(2)
+        assert s.profile_read(0)[1] == 0
+        with pytest.raises(m.MpcdError):
+            s.profile(True, every=-1)
