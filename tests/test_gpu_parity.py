@@ -391,3 +391,35 @@ def test_full_size_benchmark_fluid_two_steps(form):
         d = ulp_diff_f32(gvel.astype(np.float32), v)
         assert np.median(d) == 0 and np.percentile(d[same], 99.9) <= 1
     assert gcounts.sum() == pos.shape[0]
+
+
+@pytest.mark.parametrize("rho,n_cells", [(2.5, (17, 9, 10)), (12.5, (9, 10, 7))])
+def test_extreme_tile_shapes(rho, n_cells):
+    """The sparsest tile shape (8x8x4 cells, 256-cell kernels, density below
+    3.5) and the densest (4x4x2, density 11 and up), each with partial tiles
+    on every axis: three thermostatted FP64 steps against the oracle, and one
+    FP32 step from a shared state against its emulation."""
+    banner(f"tile shapes rho={rho} {n_cells}")
+    p = srd.Params(n_cells, seed=81, thermostat=True)
+    pos, vel = workloads.fluid(n_cells, rho, seed=82)
+    mass = np.ones(pos.shape[0])
+    with _sim(pos, vel, p) as s:
+        tile = s.layout()[0]
+        s.step(3)
+        gpos, gvel = s.get_state()
+        gcells, gcounts = s.get_cells()
+    assert tile == ((8, 8, 4) if rho < 3.5 else (4, 4, 2))
+    opos, ovel, info = srd.run(pos, vel, mass, p, 0, 3)
+    assert np.array_equal(gcells, info["cell"])
+    assert np.array_equal(gcounts, info["count"])
+    assert vel_err_fp64(gvel, ovel) < FP64_REL
+    assert periodic_dist(gpos, opos, p.L).max() < 1e-12
+    h, o, v = fp32form.from_double(pos, vel, p)
+    with _sim(pos, vel, p, precision=m.FP32) as s:
+        s.step(1)
+        gpos, gvel = s.get_state()
+        gcells, _ = s.get_cells()
+    h1, o1, v1, info = fp32form.step32(h, o, v, mass, p, 0)
+    assert np.array_equal(gcells, info["cell"])
+    assert np.array_equal(gpos, fp32form.to_double(h1, o1, p))
+    assert ulp_diff_f32(gvel.astype(np.float32), v1).max() <= 1
