@@ -416,7 +416,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(independent boxes shard one per GPU; see DESIGN.md)", file=sys.stderr)
+              "(this measurement covers one GPU's share)", file=sys.stderr)
         sys.exit(2)
 
     import torch

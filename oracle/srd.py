@@ -6,7 +6,7 @@ sec. 3.4) -> cell properties (sec. 3.5, eq. 3) -> per-cell rotation axis and,
 optionally, the Maxwell-Boltzmann scale factor (sec. 3.6) -> rotation of the
 velocities relative to the cell centre-of-mass velocity (eq. 2, Alg. 1).
 
-Readings of points the paper leaves open (each is listed in the design doc):
+Readings of points the paper leaves open:
 * box [0, L) per axis with L = n*a, periodic;
 * stream uses one FP64 multiply then one FP64 add (no fused multiply-add);
 * a wrapped coordinate that rounds to L is set to 0;

@@ -17,7 +17,7 @@ LIB = binding.LIB_PATH
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(LIB):
-        pytest.fail("libmpcd.so is not built (run __graft_entry__.build())")
+        pytest.fail("libmpcd.so is not built (run python -m paper_1801_10187_amd.build)")
     return m.load()
 
 
