@@ -1,0 +1,40 @@
+"""The bench's contract pieces that need no GPU: it refuses more than one
+GPU, and its byte counts are the ones its roofline states."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_algorithmic_bytes():
+    # state read once and written once, with the 4-byte tag
+    assert bench.collide_bytes_per_particle("fp32", 10) == 64.0
+    assert bench.collide_bytes_per_particle("fp64", 10) == 104.0
+    # whole-step floor: 2 x state + one occupancy word per cell
+    assert bench.floor_bytes_per_update("fp32", 10) == pytest.approx(56.8)
+    assert bench.floor_bytes_per_update("fp64", 5) == pytest.approx(97.6)
+
+
+def test_measured_traffic_is_tied_to_the_sources():
+    rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+    from paper_1801_10187_amd.build import source_hash
+    got = bench.measured_traffic("fp32")
+    if rec.get("source_hash") == source_hash():
+        assert got == rec["bytes_per_launch"]["srd_100c_rho10_mbthermo"]["fp32"]
+        # the counters read close to the algorithmic bytes (no wasted re-reads)
+        assert 1.0 < got / (64.0 * 1e7) < 1.1
+    else:
+        assert got is None
