@@ -161,9 +161,10 @@ mpcd_status mpcd_collide(mpcd_ctx ctx);
  * entry points nsteps times: one launch per step, each step's collision
  * fused with the next step's stream and binning. nsteps >= 0. Waits for the
  * device at its end (see mpcd_bin about slab overflow).
- * The last launch also leaves the next step's stream and binning prepared
- * beside the collided state, so that the next mpcd_step starts with its
- * collision; the state every get_* reads is the collided one either way.
+ * The last launch leaves the next step's stream and binning prepared (the
+ * collided velocities, streamed and binned) beside the collided positions,
+ * so that the next mpcd_step starts with its collision; every get_* reads the
+ * collided state, joining the two copies where needed.
  * mpcd_stream, mpcd_set_embedded and a changed step counter give the
  * prepared binning up (the next mpcd_step then streams and bins first), as
  * does a slab overflow in that launch; with MPCD_FLAG_MD_SOLUTE, where the

@@ -56,10 +56,11 @@ mpcd_status fail(mpcd_status st, const char* fmt, ...) {
 enum class Phase { Idle, Streamed, Binned };
 
 // One queued kernel of a stepping call.
-// CollideKeep: collide + scatter whose input slots also receive the
-// collided velocities, so that the input holds the state after the collision
-// and the output the same state streamed and binned for the next step.
-enum class Op { BinStream, Bin, Draw, CollideScatter, Collide, CollideKeep };
+// CollideLast: the collide + scatter that ends a call. The input buffer stays
+// current: it keeps the positions (and cells) of the state after the
+// collision, while the output holds that state's velocities, streamed and
+// binned for the next step (see `split`).
+enum class Op { BinStream, Bin, Draw, CollideScatter, Collide, CollideLast };
 struct Launch {
   Op op;
   uint64_t step;
@@ -118,6 +119,11 @@ struct mpcd_ctx_s {
   // binned for step `step` (left by the last mpcd_step), so the next
   // mpcd_step starts with its collision
   bool pre = false;
+  // the current state is split over the buffers: positions and cells in
+  // buf[cur], velocities (by tag) only in buf[1 - cur] (pre is then true);
+  // readbacks join the two, and materialize() copies the velocities back
+  // before anything needs buf[cur] whole
+  bool split = false;
   int64_t regrows = 0;
 
   int32_t prof_every = 0;          // time one launch in every prof_every of a kind (0: off)
@@ -325,10 +331,9 @@ mpcd_status launch_tile(mpcd_ctx c, Op op, uint64_t n, uint32_t seq) {
     case Op::BinStream: mode = MODE_BIN; stream_in = true; break;
     case Op::Bin: mode = MODE_BIN; break;
     case Op::CollideScatter: mode = MODE_COLLIDE_SCATTER; a.shn = shift_at(c, n + 1); break;
-    case Op::CollideKeep:
+    case Op::CollideLast:
       mode = MODE_COLLIDE_SCATTER;
       a.shn = shift_at(c, n + 1);
-      a.keep = 1u;
       break;
     default: mode = MODE_COLLIDE; break;
   }
@@ -338,8 +343,9 @@ mpcd_status launch_tile(mpcd_ctx c, Op op, uint64_t n, uint32_t seq) {
     else tile_dispatch<1>(c, a, mode, stream_in);
     HIP_TRY(hipGetLastError());
   }
-  if (op == Op::CollideKeep) {  // the input stays current; the output is the prepared next binning
+  if (op == Op::CollideLast) {  // the input stays current; the output is the prepared next binning
     c->pre = true;
+    c->split = true;
     return MPCD_OK;
   }
   c->cur = 1 - c->cur;
@@ -428,26 +434,50 @@ mpcd_status regrow(mpcd_ctx c, int in_cur, int in_ci) {
   c->cur = 0;
   c->ci = 0;
   c->pre = false;
+  c->split = false;
   c->regrows += 1;
   return MPCD_OK;
 }
 
-// Give up the binning prepared by the last mpcd_step. Its counts sit in
-// cnt[(ci + 1) % 3], which the next scatter would add to, while the counts
-// the last collide + scatter cleared sit in cnt[(ci + 2) % 3]: swapping the
-// two pointers hands the next scatter clean counts and leaves the stale
-// ones to be cleared by it.
-void drop_prepared(mpcd_ctx c) {
-  if (!c->pre) return;
+// Join a split state in buf[cur]: the velocities of the prepared buffer
+// are copied, by tag, into the slots of the current one.
+mpcd_status materialize(mpcd_ctx c) {
+  if (!c->split) return MPCD_OK;
+  c->split = false;
+  if (c->N == 0) return MPCD_OK;
+  void* tmp = nullptr;
+  HIP_TRY(c->alloc(&tmp, (size_t)c->N * 3 * (c->form == 0 ? 8 : 4)));
+  const uint32_t nb = slab_blocks(c, c->S.cap);
+  const Particles in = c->buf[c->cur], out = c->buf[1 - c->cur];
+  const uint32_t *cn_in = c->cnt[c->ci], *cn_out = c->cnt[(c->ci + 1) % 3];
+  if (c->form == 0) {
+    k_vel_by_tag<0><<<nb, kGrid, 0, c->stream>>>(out, c->S, cn_out, (double*)tmp);
+    k_vel_from_tag<0><<<nb, kGrid, 0, c->stream>>>(in, c->S, cn_in, (const double*)tmp);
+  } else {
+    k_vel_by_tag<1><<<nb, kGrid, 0, c->stream>>>(out, c->S, cn_out, (float*)tmp);
+    k_vel_from_tag<1><<<nb, kGrid, 0, c->stream>>>(in, c->S, cn_in, (const float*)tmp);
+  }
+  const hipError_t e = hipGetLastError();
+  c->release(tmp);
+  if (e != hipSuccess) return fail(MPCD_EHIP, "materialize: %s", hipGetErrorString(e));
+  return MPCD_OK;
+}
+
+// Give up the binning prepared by the last mpcd_step (after joining a split
+// state). Its counts sit in cnt[(ci + 1) % 3], which the next scatter would
+// add to, while the counts the last collide + scatter cleared sit in
+// cnt[(ci + 2) % 3]: swapping the two pointers hands the next scatter clean
+// counts and leaves the stale ones to be cleared by it.
+mpcd_status drop_prepared(mpcd_ctx c) {
+  if (!c->pre) return MPCD_OK;
+  ST_TRY(materialize(c));
   std::swap(c->cnt[(c->ci + 1) % 3], c->cnt[(c->ci + 2) % 3]);
   c->pre = false;
+  return MPCD_OK;
 }
 
 // Run a list of tile launches, then confirm that no slab overflowed; replay
-// from the failing launch after enlarging the slabs if one did. A failing
-// CollideKeep is not replayed: all its blocks ran, so its input holds the
-// collided state, which the enlarged slabs now hold; only the prepared
-// binning is given up.
+// from the failing launch after enlarging the slabs if one did.
 mpcd_status run_launches(mpcd_ctx c, const std::vector<Launch>& L) {
   size_t from = 0;
   for (int attempt = 0; attempt < 16; ++attempt) {
@@ -463,7 +493,6 @@ mpcd_status run_launches(mpcd_ctx c, const std::vector<Launch>& L) {
     if (st[1] == 0) return MPCD_OK;
     const size_t bad = std::min<size_t>(st[2], in_state.size() - 1);
     ST_TRY(regrow(c, in_state[bad].first, in_state[bad].second));
-    if (L[from + bad].op == Op::CollideKeep) return MPCD_OK;
     from += bad;
   }
   return fail(MPCD_ENOMEM, "slab capacity kept overflowing");
@@ -835,8 +864,10 @@ mpcd_status read_totals(mpcd_ctx c, std::vector<long long>& h) {
   HIP_TRY(hipMemsetAsync(c->tot, 0, (size_t)c->nbox * 80, c->stream));
   const uint32_t nb = slab_blocks(c, c->S.cap);
   const bool em = c->n_emb > 0;
-  const Particles P = c->buf[c->cur];
-  const uint32_t* cn = c->cnt[c->ci];
+  // sums of velocities and masses: the prepared buffer holds them when the
+  // state is split
+  const Particles P = c->split ? c->buf[1 - c->cur] : c->buf[c->cur];
+  const uint32_t* cn = c->split ? c->cnt[(c->ci + 1) % 3] : c->cnt[c->ci];
   if (c->form == 0) {
     if (em) k_totals<0, true><<<nb, 256, 0, c->stream>>>(P, c->S, cn, c->emb_mass, c->tot, c->status);
     else k_totals<0, false><<<nb, 256, 0, c->stream>>>(P, c->S, cn, c->emb_mass, c->tot, c->status);
@@ -897,7 +928,7 @@ void mpcd_destroy(mpcd_ctx c) {
 mpcd_status mpcd_stream(mpcd_ctx c) {
   ST_TRY(check_ctx(c));
   if (c->phase != Phase::Idle) return fail(MPCD_ESTATE, "mpcd_stream: expected the state after create or collide");
-  drop_prepared(c);  // the binning that follows overwrites the prepared one
+  ST_TRY(drop_prepared(c));  // the binning that follows overwrites the prepared one
   if (c->N) {
     ProfScope ps(c, 1);
     const uint32_t nb = slab_blocks(c, c->S.cap);
@@ -945,13 +976,15 @@ mpcd_status mpcd_step(mpcd_ctx c, int64_t nsteps) {
     c->cur = 1 - c->cur;
     c->ci = (c->ci + 1) % 3;
     c->pre = false;
+    c->split = false;
   } else {
     L.push_back({Op::BinStream, c->step});
   }
   // With solutes coupled to an MD integrator the caller hands their new state
   // over before every collision, which gives a prepared binning up: such a
-  // call ends with the plain collision, which writes less.
-  const Op last = (c->p.flags & MPCD_FLAG_MD_SOLUTE) ? Op::Collide : Op::CollideKeep;
+  // call ends with the plain collision, which leaves the state whole in one
+  // buffer (no velocities to copy back before the next stream and binning).
+  const Op last = (c->p.flags & MPCD_FLAG_MD_SOLUTE) ? Op::Collide : Op::CollideLast;
   for (int64_t k = 0; k < nsteps; ++k) {
     if (c->p.thermostat) L.push_back({Op::Draw, c->step + (uint64_t)k});
     L.push_back({k + 1 < nsteps ? Op::CollideScatter : last, c->step + (uint64_t)k});
@@ -977,10 +1010,18 @@ mpcd_status mpcd_get_state(mpcd_ctx c, double* pos, double* vel, int32_t on_devi
     dv = tmp + 3 * (size_t)c->N;
   }
   const uint32_t nb = slab_blocks(c, c->S.cap);
+  // a split state: positions from the current buffer, velocities from the
+  // prepared one
+  double* dv_cur = c->split ? nullptr : dv;
   if (c->form == 0)
-    k_export<0><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->S, c->cnt[c->ci], dp, dv);
+    k_export<0><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->S, c->cnt[c->ci], dp, dv_cur);
   else
-    k_export<1><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->S, c->cnt[c->ci], dp, dv);
+    k_export<1><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->S, c->cnt[c->ci], dp, dv_cur);
+  if (c->split) {
+    const uint32_t* cn = c->cnt[(c->ci + 1) % 3];
+    if (c->form == 0) k_export<0><<<nb, kGrid, 0, c->stream>>>(c->buf[1 - c->cur], c->S, cn, nullptr, dv);
+    else k_export<1><<<nb, kGrid, 0, c->stream>>>(c->buf[1 - c->cur], c->S, cn, nullptr, dv);
+  }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && tmp) {
     e = hipMemcpyAsync(pos, dp, (size_t)c->N * 24, hipMemcpyDeviceToHost, c->stream);
@@ -1008,10 +1049,20 @@ mpcd_status mpcd_get_embedded(mpcd_ctx c, double* pos, double* vel, int32_t on_d
   const uint32_t nb = blocks_for(n, kGrid);
   hipError_t e = hipMemsetAsync(c->flag, 0, 4, c->stream);
   if (e == hipSuccess) {
-    if (c->form == 0)
-      k_emb_export<0><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->boxes[0], c->eslot[c->cur], (uint32_t)n, (size_t)c->S.ntiles * c->S.cap, dp, dv, c->flag);
-    else
-      k_emb_export<1><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->boxes[0], c->eslot[c->cur], (uint32_t)n, (size_t)c->S.ntiles * c->S.cap, dp, dv, c->flag);
+    // a split state: positions from the current buffer, velocities from the
+    // prepared one, each through its own slot index
+    const size_t ns = (size_t)c->S.ntiles * c->S.cap;
+    struct {
+      int b;
+      double *p, *v;
+    } part[2] = {{c->cur, dp, c->split ? nullptr : dv}, {1 - c->cur, nullptr, c->split ? dv : nullptr}};
+    for (const auto& q : part) {
+      if (!q.p && !q.v) continue;
+      if (c->form == 0)
+        k_emb_export<0><<<nb, kGrid, 0, c->stream>>>(c->buf[q.b], c->boxes[0], c->eslot[q.b], (uint32_t)n, ns, q.p, q.v, c->flag);
+      else
+        k_emb_export<1><<<nb, kGrid, 0, c->stream>>>(c->buf[q.b], c->boxes[0], c->eslot[q.b], (uint32_t)n, ns, q.p, q.v, c->flag);
+    }
     e = hipGetLastError();
   }
   uint32_t hflag = 0;
@@ -1032,7 +1083,7 @@ mpcd_status mpcd_set_embedded(mpcd_ctx c, const double* pos, const double* vel, 
   if (c->n_emb == 0) return fail(MPCD_EINVAL, "no embedded particles");
   if (!pos || !vel) return fail(MPCD_EINVAL, "pos/vel NULL");
   if (c->phase != Phase::Idle) return fail(MPCD_ESTATE, "mpcd_set_embedded: only between steps");
-  drop_prepared(c);  // the new positions are binned afresh by the next step
+  ST_TRY(drop_prepared(c));  // the new positions are binned afresh by the next step
   const size_t n = c->n_emb;
   const double* dp = pos;
   const double* dv = vel;
@@ -1175,6 +1226,7 @@ mpcd_status mpcd_get_box(mpcd_ctx c, int32_t box, int64_t* first_tag, int64_t* n
 
 mpcd_status mpcd_get_velocity_field(mpcd_ctx c, double* u, double* mass, int32_t on_device) {
   ST_TRY(check_ctx(c));
+  ST_TRY(materialize(c));  // the field pairs each particle's position with its velocity
   const size_t C = c->ncells;
   if (C == 0 || (!u && !mass)) return take_err(c);
   unsigned long long* acc = nullptr;
@@ -1221,7 +1273,7 @@ mpcd_status mpcd_set_step(mpcd_ctx c, uint64_t n) {
   ST_TRY(check_ctx(c));
   if (c->phase != Phase::Idle) return fail(MPCD_ESTATE, "mpcd_set_step: only between steps");
   if (n >= 0xFFFFFFFFull) return fail(MPCD_ERANGE, "step counter beyond 2^32 - 1");
-  if (n != c->step) drop_prepared(c);  // the prepared binning used step `step`'s shift
+  if (n != c->step) ST_TRY(drop_prepared(c));  // the prepared binning used step `step`'s shift
   c->step = n;
   return MPCD_OK;
 }

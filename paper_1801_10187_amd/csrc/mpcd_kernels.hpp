@@ -444,8 +444,6 @@ struct TileArgs {
   double* d_ek;
   double* d_axis;
   double* d_xi;
-  uint32_t keep;            // collide + scatter: also write the collided
-                            // velocities back into the input slots
   uint32_t* eslot_out;      // slot of each embedded particle in the output
                             // buffer (null without embedded particles)
 };
@@ -849,7 +847,6 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
             st(Out.lc, k, (uint8_t)lcs[q]);
             if (A.eslot_out) note_slot(A.eslot_out, B, tg[q], tbase + k);
           } else {
-            if (A.keep) store_vel<FORM>(In, k, r[q], v[q], tg[q]);
             if (streamed(B, tg[q])) r[q].stream(B, v[q], err);
           }
         }
@@ -870,7 +867,6 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
           st(Out.lc, k, (uint8_t)lc);
           if (A.eslot_out) note_slot(A.eslot_out, B, tag, tbase + k);
         } else {
-          if (A.keep) store_vel<FORM>(In, k, rr, ww, tag);
           if (streamed(B, tag)) rr.stream(B, ww, err);
           scatter_one(rr, sh1.s, sh1.s32, ww, tag);
         }
@@ -1246,6 +1242,7 @@ __global__ __launch_bounds__(256) void k_import(Particles P, Box B, uint32_t cap
 
 // Internal form -> row-major N x 3 doubles in tag order.
 template <int FORM>
+// pos (if non-null) and vel (if non-null) of every particle, in tag order
 __global__ __launch_bounds__(256) void k_export(Particles P, Slabs S, const uint32_t* cnt,
                                                 double* __restrict__ pos,
                                                 double* __restrict__ vel) {
@@ -1256,21 +1253,51 @@ __global__ __launch_bounds__(256) void k_export(Particles P, Slabs S, const uint
   uint32_t t;
   Pos<FORM> r;
   load_part<FORM>(P, s.i, r, v, t);
-  if constexpr (FORM == 0) {
+  if (pos) {
+    if constexpr (FORM == 0) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      pos[3ull * t + d] = r.x[d];
-      vel[3ull * t + d] = v[d];
-    }
-  } else {
-    int h[3];
-    unpack_home(r.hp, h[0], h[1], h[2]);
+      for (int d = 0; d < 3; ++d) pos[3ull * t + d] = r.x[d];
+    } else {
+      int h[3];
+      unpack_home(r.hp, h[0], h[1], h[2]);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      pos[3ull * t + d] = (double)h[d] * B.a + (double)r.o[d];
-      vel[3ull * t + d] = (double)v[d];
+      for (int d = 0; d < 3; ++d) pos[3ull * t + d] = (double)h[d] * B.a + (double)r.o[d];
     }
   }
+  if (vel) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) vel[3ull * t + d] = (double)v[d];
+  }
+}
+
+// Velocities handed from one buffer to the other through a tag-indexed
+// array tmp (3 per tag, storage precision): k_vel_by_tag fills tmp from the
+// slots of one buffer, k_vel_from_tag writes them into the slots that hold
+// the same tags in the other.
+template <int FORM>
+__global__ __launch_bounds__(256) void k_vel_by_tag(Particles P, Slabs S, const uint32_t* cnt,
+                                                    typename VelT<FORM>::T* __restrict__ tmp) {
+  const SlabIter s = slab_slot(S, cnt);
+  if (!s.valid) return;
+  typename VelT<FORM>::T v[3];
+  uint32_t t;
+  load_vt<FORM>(P, s.i, v, t);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) tmp[3ull * t + d] = v[d];
+}
+
+template <int FORM>
+__global__ __launch_bounds__(256) void k_vel_from_tag(Particles P, Slabs S, const uint32_t* cnt,
+                                                      const typename VelT<FORM>::T* __restrict__ tmp) {
+  const SlabIter s = slab_slot(S, cnt);
+  if (!s.valid) return;
+  typename VelT<FORM>::T v[3];
+  uint32_t t;
+  Pos<FORM> r;
+  load_part<FORM>(P, s.i, r, v, t);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) v[d] = tmp[3ull * t + d];
+  store_vel<FORM>(P, s.i, r, v, t);
 }
 
 // Embedded particles (box 0) out of / into the slabs, rows tag - n_solvent of
@@ -1278,7 +1305,8 @@ __global__ __launch_bounds__(256) void k_export(Particles P, Slabs S, const uint
 // between collisions. The update writes in place; the next binning moves a
 // particle to the tile of its new position.
 // Embedded particles of box B (the only box that has them), one thread
-// each, found through the slot index of the current buffer (nslots slots).
+// each, found through the slot index of a buffer (nslots slots); export
+// writes pos and vel where they are non-null.
 // A slot out of range or not holding the expected tag sets bit 2 of *flag
 // and is left alone.
 template <int FORM>
@@ -1301,17 +1329,21 @@ __global__ __launch_bounds__(256) void k_emb_export(Particles P, Box B, const ui
     return;
   }
   const size_t row = 3ull * i;
-  if constexpr (FORM == 0) {
+  if (pos) {
+    if constexpr (FORM == 0) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) pos[row + d] = r.x[d];
-  } else {
-    int h[3];
-    unpack_home(r.hp, h[0], h[1], h[2]);
+      for (int d = 0; d < 3; ++d) pos[row + d] = r.x[d];
+    } else {
+      int h[3];
+      unpack_home(r.hp, h[0], h[1], h[2]);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) pos[row + d] = (double)h[d] * B.a + (double)r.o[d];
+      for (int d = 0; d < 3; ++d) pos[row + d] = (double)h[d] * B.a + (double)r.o[d];
+    }
   }
+  if (vel) {
 #pragma unroll
-  for (int d = 0; d < 3; ++d) vel[row + d] = (double)v[d];
+    for (int d = 0; d < 3; ++d) vel[row + d] = (double)v[d];
+  }
 }
 
 // Positions outside [0, L) set bit 0 of *flag and are not stored.

@@ -124,7 +124,7 @@ def test_step_counter_change_between_calls():
 def test_overflow_in_the_last_launch_of_a_call():
     """Single-step calls on a converging flow with slabs sized to the initial
     maximum: scatters into the prepared binning overflow, the slabs grow and
-    the collided state is kept; the run still matches the oracle."""
+    the launch is replayed; the run still matches the oracle."""
     banner("overflow at the end of a call")
     p = srd.Params((12, 12, 12), seed=59, thermostat=True)
     pos, vel = workloads.fluid(p.n_cells, 9, seed=60)
@@ -233,3 +233,32 @@ def test_sampled_kernel_timing():
         assert s.profile_read(0)[1] == 0
         with pytest.raises(m.MpcdError):
             s.profile(True, every=-1)
+
+
+@pytest.mark.parametrize("form", ["fp32", "fp64"])
+def test_split_state_reads(form):
+    """Between calls the collided velocities live in the prepared binning and
+    the positions in the current buffer; state, embedded rows and totals read
+    there equal those of a context that stepped with separate calls (state
+    whole in one buffer), and the run goes on unchanged."""
+    banner(f"split-state reads {form}")
+    p = srd.Params((10, 11, 9), seed=69, thermostat=True)
+    pos, vel = workloads.fluid(p.n_cells, 6, seed=70)
+    bpos, bvel, bmass = workloads.beads(p.n_cells, 3, 10, seed=71)
+    prec = m.FP64 if form == "fp64" else m.FP32
+    kw = dict(emb_pos=bpos, emb_vel=bvel, emb_mass=bmass)
+    with _sim(pos, vel, p, prec, **kw) as a, _sim(pos, vel, p, prec, **kw) as b, \
+            _sim(pos, vel, p, prec, **kw) as c:
+        a.step(5)
+        b.step(2)
+        sb, eb, tb = b.get_state(), b.get_embedded(), b.totals()
+        b.step(3)
+        for _ in range(2):
+            c.stream()
+            c.bin()
+            c.collide()
+        sc, ec, tc = c.get_state(), c.get_embedded(), c.totals()
+        for x, y in zip(sb + eb, sc + ec):
+            assert np.array_equal(x, y)
+        assert np.array_equal(tb[0], tc[0]) and tb[1] == tc[1] and tb[2] == tc[2]
+        _same(a, b)
