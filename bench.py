@@ -240,16 +240,19 @@ def bench_batch(m, workloads, cfg, args):
 
 
 def bench_serve(m, workloads, cfg, args, workers=8, stop_after=75.0):
-    """Open-loop serving: requests (workloads.serve_requests) arrive at their
-    Poisson times; `workers` host threads each take the oldest arrived
-    request, create a context for it on its own HIP stream, run its steps,
-    read its cell-averaged velocity field and destroy the context. No request
-    is started after `stop_after` seconds; those are reported as unserved.
-    Particles of a request are a slice, at a seeded offset, of one pool of
-    uniform and Gaussian numbers scaled to the request's box and kT (drawing
-    10^9 fresh numbers per second on the host would be the bottleneck)."""
+    """Open-loop serving through paper_1801_10187_amd.serve.Server: requests
+    (workloads.serve_requests) are submitted at their Poisson arrival times;
+    the server admits them in arrival order as a worker is free and their
+    device memory fits beside the requests in flight, each in its own context
+    and HIP stream, and returns its cell-averaged velocity field. Requests not
+    started `stop_after` seconds after the first arrival are cancelled and
+    reported as unserved. Particles of a request are a slice, at a seeded
+    offset, of one pool of uniform and Gaussian numbers scaled to the
+    request's box and kT (drawing 10^9 fresh numbers per second on the host
+    would be the bottleneck)."""
     import threading
     import torch
+    from paper_1801_10187_amd.serve import Request, Server
     reqs = workloads.serve_requests(rate=cfg["rate"], duration=cfg["duration"], seed=cfg["seed"])
     npool = int(max(r["density"] * np.prod(r["n_cells"]) for r in reqs)) + 1
     rng = np.random.default_rng(cfg["seed"])
@@ -257,52 +260,54 @@ def bench_serve(m, workloads, cfg, args, workers=8, stop_after=75.0):
     gpool = rng.normal(size=(2 * npool, 3))
     torch.cuda.init()
     lock = threading.Lock()
-    nxt = [0]
     done = []
-    t0 = time.perf_counter()
 
-    def worker():
-        while True:
-            with lock:
-                i = nxt[0]
-                if i >= len(reqs):
-                    return
-                nxt[0] += 1
-            r = reqs[i]
-            now = time.perf_counter() - t0
-            if now < r["t"]:
-                time.sleep(r["t"] - now)
-            if time.perf_counter() - t0 > stop_after:
-                return
-            n = int(round(r["density"] * np.prod(r["n_cells"])))
+    def particles(i, r, n):
+        def make():
             off = int(np.random.default_rng(5000 + i).integers(0, npool))
             L = np.array(r["n_cells"], dtype=np.float64)
             pos = upool[off:off + n] * L
             pos = np.where(pos >= L, 0.0, pos)
             vel = gpool[off:off + n] * math.sqrt(cfg["kT"])
-            vel -= vel.mean(axis=0)
-            sim = m.Sim(pos, vel, r["n_cells"], kT=cfg["kT"], seed=r["seed"], precision=m.FP32,
-                        thermostat=cfg["thermostat"])
-            try:
-                sim.step(r["steps"])
-                u, _ = sim.velocity_field()
-            finally:
-                sim.close()
-            t_end = time.perf_counter() - t0
-            with lock:
-                done.append((r["t"], t_end, n * r["steps"], u.shape[0]))
-                if len(done) % 250 == 0:
-                    print(f"[serve] {len(done)} requests done at {t_end:.1f} s", file=sys.stderr,
-                          flush=True)
+            return pos, vel - vel.mean(axis=0)
+        return make
 
-    threads = [threading.Thread(target=worker) for _ in range(workers)]
-    for th in threads:
-        th.start()
-    for th in threads:
-        th.join()
+    server = Server(workers=workers)
+    futs = []
+    t0 = time.perf_counter()
+    try:
+        for i, r in enumerate(reqs):
+            now = time.perf_counter() - t0
+            if now < r["t"]:
+                time.sleep(r["t"] - now)
+            n = int(round(r["density"] * np.prod(r["n_cells"])))
+            req = Request(r["n_cells"], n, r["steps"], particles(i, r, n), precision=m.FP32,
+                          kT=cfg["kT"], seed=r["seed"], thermostat=cfg["thermostat"])
+            fut = server.submit(req)
+
+            def finished(f, a=r["t"], w=n * r["steps"]):
+                if f.cancelled() or f.exception() is not None:
+                    return
+                with lock:
+                    done.append((a, time.perf_counter() - t0, w))
+                    if len(done) % 250 == 0:
+                        print(f"[serve] {len(done)} requests done at {done[-1][1]:.1f} s",
+                              file=sys.stderr, flush=True)
+            fut.add_done_callback(finished)
+            futs.append(fut)
+        left = stop_after - (time.perf_counter() - t0)
+        if left > 0:
+            time.sleep(left)
+        for f in futs:
+            f.cancel()              # only requests not started yet
+    finally:
+        server.close()
     wall = time.perf_counter() - t0
-    lat = np.array([e - a for a, e, _, _ in done])
-    served = sum(w for _, _, w, _ in done)
+    errors = [f.exception() for f in futs if not f.cancelled() and f.exception() is not None]
+    if errors:
+        raise errors[0]
+    lat = np.array([e - a for a, e, _ in done])
+    served = sum(w for _, _, w in done)
     offered = sum(r["density"] * np.prod(r["n_cells"]) * r["steps"] for r in reqs) / cfg["duration"]
     out = {
         "metric": "particle-updates/s (stream+bin+SRD collide) FP32 vs FP64; p99 batch latency",
@@ -314,10 +319,12 @@ def bench_serve(m, workloads, cfg, args, workers=8, stop_after=75.0):
                    "duration_s": cfg["duration"], "requests": len(reqs),
                    "particles": "log-uniform 1e4..1e7", "steps": "uniform 100..2000",
                    "density": [5, 10], "kT": cfg["kT"], "thermostat": "maxwell-boltzmann",
-                   "form": "fp32", "workers": workers, "stop_after_s": stop_after},
+                   "form": "fp32", "workers": workers, "stop_after_s": stop_after,
+                   "admission": "FIFO by worker slot and device-memory budget"},
         "served_requests": len(done), "unserved_requests": len(reqs) - len(done),
         "offered_updates_per_s": offered, "served_updates_per_s": served / wall,
-        "wall_s": wall,
+        "wall_s": wall, "max_requests_in_flight": server.max_inflight,
+        "max_bytes_in_flight": server.max_inflight_bytes, "memory_budget": server.budget,
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3) if len(lat) else None,
                        "p99": float(np.percentile(lat, 99) * 1e3) if len(lat) else None,
                        "what": "request completion minus arrival, completed requests"},
