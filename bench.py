@@ -181,6 +181,31 @@ def cpu_baseline(inp, n_cells, cfg, nsteps, what):
                        f"{dt:.1f} s, numpy, single thread)")
 
 
+def fp32_accuracy(m, inp, cfg):
+    """The FP32 form's error against the FP64 form, both stepped once on
+    the GPU from the same input (the FP64 form agrees with the FP64 oracle
+    to 1e-12): per-particle velocity and position differences, and the
+    observables after the timed runs (kT and net momentum, in `forms`)."""
+    pos, vel, bpos, bvel, bmass = inp
+    st = {}
+    for name, prec in (("fp32", m.FP32), ("fp64", m.FP64)):
+        with m.Sim(pos, vel, cfg["n_cells"], kT=cfg["kT"], seed=cfg["seed"], precision=prec,
+                   thermostat=cfg["thermostat"], emb_pos=bpos, emb_vel=bvel,
+                   emb_mass=bmass) as s:
+            s.step(1)
+            st[name] = s.get_state()
+    L = np.array(cfg["n_cells"], dtype=np.float64)
+    dx = st["fp32"][0] - st["fp64"][0]
+    dx -= L * np.round(dx / L)
+    dv = st["fp32"][1] - st["fp64"][1]
+    vs = np.abs(st["fp64"][1])
+    return {"what": "one step from the same input, FP32 form minus FP64 form",
+            "velocity_max_abs": float(np.abs(dv).max()),
+            "velocity_rms": float(np.sqrt(np.mean(dv * dv))),
+            "velocity_max_rel": float((np.abs(dv) / np.maximum(vs, 1.0)).max()),
+            "position_max_abs": float(np.abs(dx).max())}
+
+
 def bench_batch(m, workloads, cfg, args):
     """Throughput and single-step latency of a batch of independent boxes."""
     import torch
@@ -517,6 +542,7 @@ def main():
     out["roofline"]["frac_of_copy_ceiling"] = head["collide_GBs"] / out["copy_ceiling_GBs"]
     if "fp32" in res and "fp64" in res:
         out["fp32_over_fp64"] = res["fp32"]["updates_per_s"] / res["fp64"]["updates_per_s"]
+        out["fp32_accuracy"] = fp32_accuracy(m, inp, cfg)
     for base in ("fp32", "fp64"):  # the AT rule against the thermostatted SRD step
         if base in res and base + "_at" in res:
             out[base + "_at_over_srd"] = res[base + "_at"]["updates_per_s"] / res[base]["updates_per_s"]
