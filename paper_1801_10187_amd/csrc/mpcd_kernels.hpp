@@ -510,6 +510,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
   __shared__ uint32_t s_cnt[CC];
   __shared__ double s_u[3][CC];
   __shared__ double s_R[9][CC];
+  __shared__ double s_xi[THERMO && MODE != MODE_DIAG ? CC : 1];
   __shared__ uint32_t s_bincnt[27];
   __shared__ uint32_t s_base[27];
   __shared__ uint32_t s_btile[27];
@@ -604,8 +605,9 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
       }
   }
 
-  // cell thread: the rotation axis needs only (cell, step), so it is drawn
-  // while the gathers are in flight; it waits in s_R until R is formed
+  // cell thread: the rotation axis, and with it R(alpha, n), needs only
+  // (cell, step), so both are formed while the gathers are in flight (the
+  // diagnostic mode keeps the axis itself in s_R)
   const bool cthr = COLL && tid < (uint32_t)CPT;
   bool cok = false;
   const uint32_t gcell = cthr ? cell_of(tid, cok) : 0u;
@@ -616,9 +618,17 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
     if (cthr && !AT) {
       double n[3] = {0.0, 0.0, 0.0};
       if (cok) cell_axis(gcell, A.step, B.k0, B.k1, n);
-      s_R[0][tid] = n[0];
-      s_R[1][tid] = n[1];
-      s_R[2][tid] = n[2];
+      if constexpr (MODE == MODE_DIAG) {
+        s_R[0][tid] = n[0];
+        s_R[1][tid] = n[1];
+        s_R[2][tid] = n[2];
+      } else {
+        // R(alpha, n), unscaled: it needs only the axis
+        double R[9];
+        rotation_matrix(n, B.ca, B.sa, B.omc, 1.0, R);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) s_R[q][tid] = R[q];
+      }
     }
   }
   __syncthreads();
@@ -783,14 +793,14 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
       if (cthr) ek = 0.5 * AC::value(s_acc[RE][tid], s_acc[RE + NL - 1][tid]);
     }
 
-    // ---- per cell: xi and the scaled rotation matrix (cell threads)
+    // ---- per cell: xi (cell threads)
     if (cthr) {
       double xi = 1.0;
       if constexpr (THERMO)
         if (nc >= 2u && ek > 0.0) xi = sqrt(ehat / ek);
-      const double n[3] = {nc > 0u ? s_R[0][tid] : 0.0, nc > 0u ? s_R[1][tid] : 0.0,
-                           nc > 0u ? s_R[2][tid] : 0.0};
       if constexpr (MODE == MODE_DIAG) {
+        const double n[3] = {nc > 0u ? s_R[0][tid] : 0.0, nc > 0u ? s_R[1][tid] : 0.0,
+                             nc > 0u ? s_R[2][tid] : 0.0};
         if (cok) {
           const size_t oc = (size_t)B.cell0 + gcell;
           A.d_mass[oc] = nc > 0u ? cell_mass(tid, nc) : 0.0;
@@ -802,18 +812,15 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
           A.d_ek[oc] = ek;
           A.d_xi[oc] = xi;
         }
-      } else if constexpr (!AT) {
-        double R[9];
-        rotation_matrix(n, B.ca, B.sa, B.omc, xi, R);
-#pragma unroll
-        for (int q = 0; q < 9; ++q) s_R[q][tid] = R[q];
+      } else if constexpr (THERMO) {
+        s_xi[tid] = xi;
       }
     }
 
     if constexpr (MODE != MODE_DIAG) {
       __syncthreads();
-      // ---- rotate (Alg. 1): v <- u + xi R (v - u) in FP64, rounded once to
-      // the storage precision
+      // ---- rotate (Alg. 1): v <- u + xi (R (v - u)) in FP64, rounded once
+      // to the storage precision
       auto rotate = [&](uint32_t lc, const VT vv[3], VT w[3], const double* kv) {
         if constexpr (AT) {
           // AT rule (eq. 4): u + dv - mean dv, rounded once
@@ -823,9 +830,18 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
         }
         const double ux = s_u[0][lc], uy = s_u[1][lc], uz = s_u[2][lc];
         const double dx = (double)vv[0] - ux, dy = (double)vv[1] - uy, dz = (double)vv[2] - uz;
-        w[0] = (VT)(ux + (s_R[0][lc] * dx + s_R[1][lc] * dy + s_R[2][lc] * dz));
-        w[1] = (VT)(uy + (s_R[3][lc] * dx + s_R[4][lc] * dy + s_R[5][lc] * dz));
-        w[2] = (VT)(uz + (s_R[6][lc] * dx + s_R[7][lc] * dy + s_R[8][lc] * dz));
+        double r0 = s_R[0][lc] * dx + s_R[1][lc] * dy + s_R[2][lc] * dz;
+        double r1 = s_R[3][lc] * dx + s_R[4][lc] * dy + s_R[5][lc] * dz;
+        double r2 = s_R[6][lc] * dx + s_R[7][lc] * dy + s_R[8][lc] * dz;
+        if constexpr (THERMO) {
+          const double xi = s_xi[lc];
+          r0 *= xi;
+          r1 *= xi;
+          r2 *= xi;
+        }
+        w[0] = (VT)(ux + r0);
+        w[1] = (VT)(uy + r1);
+        w[2] = (VT)(uz + r2);
       };
 #pragma unroll
       for (int q = 0; q < TQ; ++q) {
