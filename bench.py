@@ -11,6 +11,13 @@ collision rule (eq. 4) in both forms (without the cell thermostat, which that
 rule replaces). A step is one whole pass of the hot
 path: stream, grid shift, binning, cell reduction, draws and rotation.
 
+    python bench.py --workload srd_20c_rho5_fp64
+
+times the small parity box: 20^3 cells at 5 particles per cell (40 000),
+plain FP64, no thermostat, 100 steps (its state fits in cache, so the figure
+is launch- and latency-bound, not a roofline number); the oracle runs all 100
+steps beside it.
+
     python bench.py --workload srd_400c_rho5_beads
 
 times the largest single-GPU machine instead: 400^3 cells at 5 particles per cell
@@ -439,7 +446,7 @@ def main():
                     help="storage forms to time, a suffix _at for the Andersen-thermostat "
                          "rule (default fp32,fp64,fp32_at,fp64_at; fp32 for the large box)")
     ap.add_argument("--workload", default=WORKLOAD,
-                    choices=["srd_100c_rho10_mbthermo", "srd_400c_rho5_beads",
+                    choices=["srd_100c_rho10_mbthermo", "srd_20c_rho5_fp64", "srd_400c_rho5_beads",
                              "srd_batch256_fp32", "srd_serve_poisson50", "srd_400c_rho5_md"])
     ap.add_argument("--serve-workers", type=int, default=8,
                     help="host threads serving requests (srd_serve_poisson50)")
@@ -468,14 +475,15 @@ def main():
     if wl == "srd_400c_rho5_md":
         return bench_md(m, workloads, cfg, args)
     big = wl != WORKLOAD
+    small = wl == "srd_20c_rho5_fp64"   # the 40 000-particle parity box, plain FP64
     if big and args.steps == 1000:
         args.steps = cfg["steps"]
     inp = make_input(cfg)
     N = inp[0].shape[0] + (0 if inp[2] is None else inp[2].shape[0])
     rho = cfg["density"]
     torch.cuda.init()
-    forms = [f.strip() for f in (args.forms or ("fp32" if big else "fp32,fp64,fp32_at,fp64_at"))
-             .split(",") if f.strip()]
+    default_forms = "fp64" if small else ("fp32" if big else "fp32,fp64,fp32_at,fp64_at")
+    forms = [f.strip() for f in (args.forms or default_forms).split(",") if f.strip()]
     res = {}
     for form in forms:
         base = form.split("_")[0]
@@ -547,12 +555,13 @@ def main():
         if base in res and base + "_at" in res:
             out[base + "_at_over_srd"] = res[base + "_at"]["updates_per_s"] / res[base]["updates_per_s"]
     if not args.no_cpu_baseline:
-        if big:
+        if big and not small:
             out["cpu_baseline"] = cpu_baseline(make_input(cfg, scale=60), (60, 60, 60), cfg,
                                                args.cpu_steps,
                                                "a 60^3-cell sample box of the same recipe")
         else:
-            out["cpu_baseline"] = cpu_baseline(inp, cfg["n_cells"], cfg, args.cpu_steps,
+            out["cpu_baseline"] = cpu_baseline(inp, cfg["n_cells"], cfg,
+                                               cfg["steps"] if small else args.cpu_steps,
                                                "the full workload")
     print(json.dumps(out), flush=True)
 
