@@ -277,19 +277,15 @@ __device__ inline void at_kick(uint32_t tag, uint32_t step, uint32_t k0, uint32_
   dv[2] = scale * (r2 * cospi(2.0 * u01(w.w)));
 }
 
-// xi * R(alpha, n) in row-major order, R = cos a I + sin a [n]x +
-// (1 - cos a) n n^T (Rodrigues; right-handed rotation by +alpha).
-__device__ inline void rotation_matrix(const double n[3], double ca, double sa,
-                                       double omc, double xi, double R[9]) {
-  R[0] = xi * (ca + omc * n[0] * n[0]);
-  R[1] = xi * (-sa * n[2] + omc * n[0] * n[1]);
-  R[2] = xi * (sa * n[1] + omc * n[0] * n[2]);
-  R[3] = xi * (sa * n[2] + omc * n[1] * n[0]);
-  R[4] = xi * (ca + omc * n[1] * n[1]);
-  R[5] = xi * (-sa * n[0] + omc * n[1] * n[2]);
-  R[6] = xi * (-sa * n[1] + omc * n[2] * n[0]);
-  R[7] = xi * (sa * n[0] + omc * n[2] * n[1]);
-  R[8] = xi * (ca + omc * n[2] * n[2]);
+// Right-handed rotation of d by the angle a (cos a, sin a, 1 - cos a given)
+// about the unit axis n, by Rodrigues' formula evaluated in this order:
+// (d cos a + (n x d) sin a) + n ((n . d)(1 - cos a)).
+__device__ inline void rodrigues(const double n[3], double ca, double sa, double omc,
+                                 const double d[3], double r[3]) {
+  const double nd = (n[0] * d[0] + n[1] * d[1]) + n[2] * d[2];
+  const double c[3] = {n[1] * d[2] - n[2] * d[1], n[2] * d[0] - n[0] * d[2], n[0] * d[1] - n[1] * d[0]};
+  const double q = nd * omc;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) r[k] = (d[k] * ca + c[k] * sa) + n[k] * q;
 }
-
 }  // namespace mpcd

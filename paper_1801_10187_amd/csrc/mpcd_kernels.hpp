@@ -509,7 +509,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
   __shared__ unsigned long long s_acc[NROW][CC];
   __shared__ uint32_t s_cnt[CC];
   __shared__ double s_u[3][CC];
-  __shared__ double s_R[9][CC];
+  __shared__ double s_ax[3][CC];  // per cell: the rotation axis (SRD) or the mean kick (AT)
   __shared__ double s_xi[THERMO && MODE != MODE_DIAG ? CC : 1];
   __shared__ uint32_t s_bincnt[27];
   __shared__ uint32_t s_base[27];
@@ -605,9 +605,8 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
       }
   }
 
-  // cell thread: the rotation axis, and with it R(alpha, n), needs only
-  // (cell, step), so both are formed while the gathers are in flight (the
-  // diagnostic mode keeps the axis itself in s_R)
+  // cell thread: the rotation axis needs only (cell, step), so it is drawn
+  // while the gathers are in flight; it waits in s_ax
   const bool cthr = COLL && tid < (uint32_t)CPT;
   bool cok = false;
   const uint32_t gcell = cthr ? cell_of(tid, cok) : 0u;
@@ -618,17 +617,9 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
     if (cthr && !AT) {
       double n[3] = {0.0, 0.0, 0.0};
       if (cok) cell_axis(gcell, A.step, B.k0, B.k1, n);
-      if constexpr (MODE == MODE_DIAG) {
-        s_R[0][tid] = n[0];
-        s_R[1][tid] = n[1];
-        s_R[2][tid] = n[2];
-      } else {
-        // R(alpha, n), unscaled: it needs only the axis
-        double R[9];
-        rotation_matrix(n, B.ca, B.sa, B.omc, 1.0, R);
-#pragma unroll
-        for (int q = 0; q < 9; ++q) s_R[q][tid] = R[q];
-      }
+      s_ax[0][tid] = n[0];
+      s_ax[1][tid] = n[1];
+      s_ax[2][tid] = n[2];
     }
   }
   __syncthreads();
@@ -765,11 +756,11 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
       s_u[1][tid] = u[1];
       s_u[2][tid] = u[2];
       if constexpr (AT) {
-        // mass-weighted mean random velocity of the cell, in s_R[0..2]
+        // mass-weighted mean random velocity of the cell, in s_ax
         const double M = nc > 0u ? cell_mass(tid, nc) : 1.0;
 #pragma unroll
         for (int d = 0; d < 3; ++d)
-          s_R[d][tid] = nc > 0u ? AC::value(s_acc[RQ + NL * d][tid], s_acc[RQ + NL * d + NL - 1][tid]) / M : 0.0;
+          s_ax[d][tid] = nc > 0u ? AC::value(s_acc[RQ + NL * d][tid], s_acc[RQ + NL * d + NL - 1][tid]) / M : 0.0;
       }
     }
 
@@ -799,8 +790,8 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
       if constexpr (THERMO)
         if (nc >= 2u && ek > 0.0) xi = sqrt(ehat / ek);
       if constexpr (MODE == MODE_DIAG) {
-        const double n[3] = {nc > 0u ? s_R[0][tid] : 0.0, nc > 0u ? s_R[1][tid] : 0.0,
-                             nc > 0u ? s_R[2][tid] : 0.0};
+        const double n[3] = {nc > 0u ? s_ax[0][tid] : 0.0, nc > 0u ? s_ax[1][tid] : 0.0,
+                             nc > 0u ? s_ax[2][tid] : 0.0};
         if (cok) {
           const size_t oc = (size_t)B.cell0 + gcell;
           A.d_mass[oc] = nc > 0u ? cell_mass(tid, nc) : 0.0;
@@ -819,29 +810,28 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
 
     if constexpr (MODE != MODE_DIAG) {
       __syncthreads();
-      // ---- rotate (Alg. 1): v <- u + xi (R (v - u)) in FP64, rounded once
-      // to the storage precision
+      // ---- rotate (Alg. 1): v <- u + xi R(alpha, n) (v - u) in FP64, the
+      // rotation by Rodrigues' formula from the axis, rounded once to the
+      // storage precision
       auto rotate = [&](uint32_t lc, const VT vv[3], VT w[3], const double* kv) {
         if constexpr (AT) {
           // AT rule (eq. 4): u + dv - mean dv, rounded once
 #pragma unroll
-          for (int d = 0; d < 3; ++d) w[d] = (VT)((s_u[d][lc] + kv[d]) - s_R[d][lc]);
+          for (int d = 0; d < 3; ++d) w[d] = (VT)((s_u[d][lc] + kv[d]) - s_ax[d][lc]);
           return;
         }
-        const double ux = s_u[0][lc], uy = s_u[1][lc], uz = s_u[2][lc];
-        const double dx = (double)vv[0] - ux, dy = (double)vv[1] - uy, dz = (double)vv[2] - uz;
-        double r0 = s_R[0][lc] * dx + s_R[1][lc] * dy + s_R[2][lc] * dz;
-        double r1 = s_R[3][lc] * dx + s_R[4][lc] * dy + s_R[5][lc] * dz;
-        double r2 = s_R[6][lc] * dx + s_R[7][lc] * dy + s_R[8][lc] * dz;
+        const double u[3] = {s_u[0][lc], s_u[1][lc], s_u[2][lc]};
+        const double n[3] = {s_ax[0][lc], s_ax[1][lc], s_ax[2][lc]};
+        const double d[3] = {(double)vv[0] - u[0], (double)vv[1] - u[1], (double)vv[2] - u[2]};
+        double r[3];
+        rodrigues(n, B.ca, B.sa, B.omc, d, r);
         if constexpr (THERMO) {
           const double xi = s_xi[lc];
-          r0 *= xi;
-          r1 *= xi;
-          r2 *= xi;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) r[k] *= xi;
         }
-        w[0] = (VT)(ux + r0);
-        w[1] = (VT)(uy + r1);
-        w[2] = (VT)(uz + r2);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) w[k] = (VT)(u[k] + r[k]);
       };
 #pragma unroll
       for (int q = 0; q < TQ; ++q) {
