@@ -25,5 +25,22 @@ def ulp_diff_f32(a, b):
     return np.abs(ai - bi)
 
 
+# Absolute resolution of the FP32 form's fixed-point cell sums (one limb,
+# 2^-40): a term that is an FP64 value (an AT kick, a relative kinetic energy)
+# is rounded to it, so a cell mean carries an absolute error of at most 2^-41.
+# Against the oracle's FP64 sums an FP32 result is then within one ulp, or,
+# for results within ~1e-6 of zero, where an ulp is below that error, within
+# 2^-40 absolute.
+FP32_FIXED_ABS = 2.0 ** -40
+
+
+def f32_close(a, b, abs_tol=FP32_FIXED_ABS):
+    """Elementwise: within one FP32 ulp, or within abs_tol absolute."""
+    a = np.asarray(a, dtype=np.float32)
+    b = np.asarray(b, dtype=np.float32)
+    absd = np.abs(a.astype(np.float64) - b.astype(np.float64))
+    return (ulp_diff_f32(a, b) <= 1) | (absd <= abs_tol)
+
+
 def banner(msg):
     print(f"[gpu-test] {msg}", flush=True)

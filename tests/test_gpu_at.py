@@ -6,7 +6,7 @@ import pytest
 
 import paper_1801_10187_amd as m
 import workloads
-from helpers import FP64_REL, banner, periodic_dist, ulp_diff_f32, vel_err_fp64
+from helpers import FP64_REL, banner, f32_close, periodic_dist, ulp_diff_f32, vel_err_fp64
 from oracle import fp32form, srd
 
 pytestmark = pytest.mark.gpu
@@ -99,3 +99,34 @@ def test_at_crowded_cell():
         gpos, gvel = s.get_state()
     opos, ovel, _ = srd.run(pos, vel, np.ones(pos.shape[0]), p, 0, 2)
     assert vel_err_fp64(gvel, ovel) < FP64_REL
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32"])
+def test_at_full_size_benchmark_fluid(form):
+    """The 10^7-particle fluid of the benchmark under the AT rule, in the
+    launch configuration the benchmark times: one step against the oracle
+    element by element (FP32: its emulation; cells and positions exact,
+    velocities within one ulp or, for the few within ~1e-6 of zero, within
+    the 2^-40 resolution of the FP32 form's kick sums)."""
+    cfg = workloads.CONFIGS["srd_100c_rho10_mbthermo"]
+    banner(f"AT full size {form}")
+    p = srd.Params(cfg["n_cells"], seed=cfg["seed"], kT=cfg["kT"], rule="at")
+    pos, vel = workloads.fluid(cfg["n_cells"], cfg["density"], seed=cfg["seed"])
+    mass = np.ones(pos.shape[0])
+    prec = m.FP64 if form == "fp64" else m.FP32
+    with _sim(pos, vel, p, precision=prec) as s:
+        s.step(1)
+        gpos, gvel = s.get_state()
+        gcells, gcounts = s.get_cells()
+    assert gcounts.sum() == pos.shape[0]
+    if form == "fp64":
+        opos, ovel, info = srd.run(pos, vel, mass, p, 0, 1)
+        assert np.array_equal(gcells, info["cell"])
+        assert vel_err_fp64(gvel, ovel) < FP64_REL
+        assert periodic_dist(gpos, opos, p.L).max() < 1e-12
+    else:
+        h, o, v = fp32form.from_double(pos, vel, p)
+        h1, o1, v1, info = fp32form.step32(h, o, v, mass, p, 0)
+        assert np.array_equal(gcells, info["cell"])
+        assert np.array_equal(gpos, fp32form.to_double(h1, o1, p))
+        assert np.all(f32_close(gvel, v1))
