@@ -47,3 +47,39 @@ def test_results_alone_and_in_the_mix(budget):
     for (u0, m0), (u1, m1) in zip(alone, got):
         assert np.array_equal(m0, m1)
         assert np.array_equal(u0, u1)
+
+
+def test_serving_stream_full_range():
+    """Requests of the served stream itself, from the smallest (~9 x 10^3
+    particles) to the two largest (~10^7), with their own step counts (130 to
+    1226), FP32 and thermostatted as served: run in the mix they equal the
+    same requests run alone, bit for bit; every field holds each particle
+    once and the zero net momentum the request started with, up to the FP32
+    rounding of the stored velocities (a random walk of ~2^-24 per component
+    per particle and step)."""
+    banner("serving stream, full size range")
+    cfg = workloads.CONFIGS["srd_serve_poisson50"]
+    stream = workloads.serve_requests(rate=cfg["rate"], duration=cfg["duration"], seed=cfg["seed"])
+    N = np.array([int(round(r["density"] * np.prod(r["n_cells"]))) for r in stream])
+    order = np.argsort(N, kind="stable")
+    pick = sorted({int(order[int(f * (len(order) - 1))]) for f in (0.0, 0.2, 0.4, 0.6, 0.8, 0.95)}
+                  | {int(order[-1]), int(order[-2])})
+    reqs = []
+    for i in pick:
+        r = stream[i]
+
+        def make(r=r, i=i):
+            return workloads.fluid(r["n_cells"], r["density"], kT=cfg["kT"], seed=5000 + i)
+        reqs.append(Request(r["n_cells"], int(N[i]), r["steps"], make, precision=m.FP32,
+                            kT=cfg["kT"], seed=r["seed"], thermostat=cfg["thermostat"]))
+    assert max(q.n_particles for q in reqs) > 9_000_000 and min(q.n_particles for q in reqs) < 10_000
+    alone = [run_request(q) for q in reqs]
+    with Server(workers=8) as srv:
+        futs = [srv.submit(q) for q in reqs]
+        got = [f.result(timeout=200) for f in futs]
+    assert srv.max_inflight > 1
+    for q, (u0, m0), (u1, m1) in zip(reqs, alone, got):
+        assert np.array_equal(m0, m1) and np.array_equal(u0, u1)
+        assert m0.sum() == q.n_particles
+        P = (u0 * m0[:, None]).sum(axis=0)
+        assert np.abs(P).max() < 1e-6 * np.sqrt(q.steps * q.n_particles)
