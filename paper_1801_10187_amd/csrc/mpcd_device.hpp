@@ -1,7 +1,7 @@
 // Device building blocks of the SRD step: Philox4x32-10, the word -> uniform
 // map, exact fixed-point accumulation, periodic wrap and binning in both
 // storage forms, the per-cell draws (axis, Maxwell-Boltzmann factor) and the
-// rotation matrix. Everything here is compiled with -ffp-contract=off so each
+// rotation about the cell axis (Rodrigues' formula). Everything here is compiled with -ffp-contract=off so each
 // floating-point operation rounds once, in the order written.
 #pragma once
 
@@ -63,7 +63,7 @@ __host__ __device__ inline void grid_shift(uint32_t k0, uint32_t k1, uint32_t n,
 // (|x - hi 2^-20| <= 2^-21 and the operands are within a factor two, or hi is
 // 0). Sums of limbs are exact integer sums, so a cell total does not depend on
 // the order its particles are visited in: results are deterministic although
-// the count sort places particles of a cell in a run-dependent order. The
+// the scatter into the slabs leaves a cell's particles in a run-dependent order. The
 // resolution is 2^-72 and the range |x| < 2^30 per term.
 struct Fx {
   long long hi, lo;

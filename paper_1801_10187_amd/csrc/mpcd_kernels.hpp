@@ -902,8 +902,8 @@ __global__ __launch_bounds__(DT) void k_draw(Particles P, Slabs S, const uint32_
   constexpr int TPB = DT / CPT;  // tiles per block (boxes start at multiples of 4 tiles)
   __shared__ uint32_t s_n[DT];
   __shared__ uint32_t s_qn;
-  __shared__ uint32_t s_qc[DT];  // pending: global cell index | rejected flag in bit 31 of s_qr
-  __shared__ uint32_t s_qs[DT];  // pending: slot (thread) and "rejected" flag
+  __shared__ uint32_t s_qc[DT];  // pending: global cell index
+  __shared__ uint32_t s_qs[DT];  // pending: slot (thread), "rejected" flag in bit 31
   __shared__ double s_qg[DT], s_qV[DT], s_qu[DT];
   __shared__ uint32_t s_quit;
   const uint32_t tid = threadIdx.x;
@@ -1306,15 +1306,14 @@ __global__ __launch_bounds__(256) void k_vel_from_tag(Particles P, Slabs S, cons
   store_vel<FORM>(P, s.i, r, v, t);
 }
 
-// Embedded particles (box 0) out of / into the slabs, rows tag - n_solvent of
+// Embedded particles out of / into the slabs, rows tag - n_solvent of
 // row-major n_emb x 3 doubles: the exchange with an external MD integrator
-// between collisions. The update writes in place; the next binning moves a
-// particle to the tile of its new position.
-// Embedded particles of box B (the only box that has them), one thread
-// each, found through the slot index of a buffer (nslots slots); export
-// writes pos and vel where they are non-null.
-// A slot out of range or not holding the expected tag sets bit 2 of *flag
-// and is left alone.
+// between collisions. One thread per embedded particle of box B (the only
+// box that has them), found through the slot index of a buffer (nslots
+// slots); export writes pos and vel where they are non-null, import updates
+// the slot in place, and the next binning moves the particle to the tile of
+// its new position. A slot out of range or not holding the expected tag sets
+// bit 2 of *flag and is left alone.
 template <int FORM>
 __global__ __launch_bounds__(256) void k_emb_export(Particles P, Box B, const uint32_t* __restrict__ eslot,
                                                     uint32_t n, size_t nslots, double* __restrict__ pos,
