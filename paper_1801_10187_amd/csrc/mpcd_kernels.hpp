@@ -482,6 +482,16 @@ struct Acc {
   }
 };
 
+// AT kick of a particle beyond the register-resident part of its tile. Kept
+// out of line: drawn inline there, its FP64 Box-Muller chain would be
+// scheduled around the live register-resident particles and raise every
+// wave's register count (FP32 form 88 -> 74 VGPRs), although only crowded
+// tiles take that path.
+__device__ __noinline__ void at_kick_tail(uint32_t i, uint32_t step, uint32_t k0, uint32_t k1,
+                                          double scale, double dv[3]) {
+  at_kick(i, step, k0, k1, scale, dv);
+}
+
 // One block per tile. In the per-cell phases thread l < CPT works for cell
 // l: it draws the axis, forms u, xi and the rotation. The thermostat's Gamma
 // draws come from k_draw, launched just before.
@@ -734,7 +744,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
       load_vt<FORM>(In, k, vv, tag);
       const double m = mass_of(tag);
       double kv[3] = {0.0, 0.0, 0.0};
-      if constexpr (AT) kick(tag, m, kv);
+      if constexpr (AT) at_kick_tail(tag - B.tag0, A.step, B.k0, B.k1, sqrt(B.kT / m), kv);
       sum_mom((uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1), vv, m, kv);
     }
     __syncthreads();
@@ -865,7 +875,7 @@ __global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
         load_part<FORM>(In, k, rr, vv, tag);
         const uint32_t lc = (uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1);
         double kv[3] = {0.0, 0.0, 0.0};
-        if constexpr (AT) kick(tag, mass_of(tag), kv);
+        if constexpr (AT) at_kick_tail(tag - B.tag0, A.step, B.k0, B.k1, sqrt(B.kT / mass_of(tag)), kv);
         rotate(lc, vv, ww, kv);
         if constexpr (MODE == MODE_COLLIDE) {
           const Particles Out = tile_view<FORM>(A.out, tbase);
