@@ -498,8 +498,17 @@ __device__ __noinline__ void at_kick_tail(uint32_t i, uint32_t step, uint32_t k0
 // ATR: the Andersen-thermostat rule (eq. 4) instead of the rotation; every
 // particle draws a random velocity dv in the gather, the cell sums gain
 // sum m dv, and the update is v <- (u + dv) - sum m dv / M.
+// Register target: the FP32 rotation kernels of 64-cell tiles are scheduled for
+// seven waves per SIMD (72 VGPRs); the schedule the compiler then picks runs
+// the thermostatted step ~3 % faster than its default at the same occupancy.
 template <int FORM, int CPT, int MODE, bool STREAM_IN, bool THERMO, bool EMB, bool ATR>
-__global__ __launch_bounds__(TT) void k_tile(TileArgs A) {
+constexpr int tile_waves_per_eu() {
+  return (FORM == MPCD_FP32 && CPT == 64 && !ATR) ? 7 : 1;
+}
+
+template <int FORM, int CPT, int MODE, bool STREAM_IN, bool THERMO, bool EMB, bool ATR>
+__global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
+    tile_waves_per_eu<FORM, CPT, MODE, STREAM_IN, THERMO, EMB, ATR>()))) void k_tile(TileArgs A) {
   using VT = typename VelT<FORM>::T;
   using AC = Acc<FORM>;
   constexpr bool COLL = MODE != MODE_BIN;
