@@ -498,12 +498,16 @@ __device__ __noinline__ void at_kick_tail(uint32_t i, uint32_t step, uint32_t k0
 // ATR: the Andersen-thermostat rule (eq. 4) instead of the rotation; every
 // particle draws a random velocity dv in the gather, the cell sums gain
 // sum m dv, and the update is v <- (u + dv) - sum m dv / M.
-// Register target: the FP32 rotation kernels of 64-cell tiles are scheduled for
-// seven waves per SIMD (72 VGPRs); the schedule the compiler then picks runs
-// the thermostatted step ~3 % faster than its default at the same occupancy.
+// Register targets (waves per SIMD) of the FP32 rotation kernels, measured:
+// 64-cell tiles seven (72 VGPRs; at the same occupancy the schedule the
+// compiler then picks runs the thermostatted step ~3 % faster), thermostatted
+// 128-cell tiles six (86 -> 80 VGPRs, a few spilled dwords; ~3 % faster).
 template <int FORM, int CPT, int MODE, bool STREAM_IN, bool THERMO, bool EMB, bool ATR>
 constexpr int tile_waves_per_eu() {
-  return (FORM == MPCD_FP32 && CPT == 64 && !ATR) ? 7 : 1;
+  if (FORM != MPCD_FP32 || ATR) return 1;
+  if (CPT == 64) return 7;
+  if (CPT == 128 && THERMO) return 6;
+  return 1;
 }
 
 template <int FORM, int CPT, int MODE, bool STREAM_IN, bool THERMO, bool EMB, bool ATR>
