@@ -64,11 +64,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "srd_100c_rho10_mbthermo"
 
-# Algorithmic bytes per particle of one step kernel (what its contract reads
-# once and writes once): the particle state and its 4-byte tag in, the same
-# out. Left out: the per-tile counters (a few bytes per ~640 particles) and
-# the one-byte local cell the kernel keeps beside each particle (an
-# implementation cache, 2 bytes per particle per step moved on top).
+# Particle state per storage form (bytes): FP32 home cell 4 + offsets 12 +
+# velocity 12; FP64 position 24 + velocity 24.
 STATE_BYTES = {"fp32": 28, "fp64": 48}
 
 # The timed run brackets the first launch of each kernel and then one in
@@ -77,13 +74,39 @@ STATE_BYTES = {"fp32": 28, "fp64": 48}
 PROFILE_EVERY = 10
 
 
-def collide_bytes_per_particle(form, rho):
+def floor_bytes_per_update(form, rho):
+    """Algorithmic bytes of one particle-update: the state read once and
+    written once, and each cell's occupancy written and read once (8 bytes
+    per cell, 8 / rho per particle). The roofline's `achieved` is this times
+    the particles one step launch updates, over the launch's duration."""
+    return 2 * STATE_BYTES[form] + 8.0 / rho
+
+
+def layout_bytes_per_particle(form):
+    """Bytes the step kernel's layout moves per particle by design: state and
+    its 4-byte tag read once and written once (the one-byte local cell and
+    the per-tile counters on top)."""
     return 2.0 * (STATE_BYTES[form] + 4)
 
 
-def floor_bytes_per_update(form, rho):
-    """Whole-step floor: state read once and written once, occupancy once."""
-    return 2 * STATE_BYTES[form] + 8.0 / rho
+def roofline(form, n_particles, n_cells, avg_us, traffic=None):
+    """Roofline entry of the step kernel (HBM-bound): achieved = algorithmic
+    bytes of one launch (floor_bytes_per_update per particle: 2 x state per
+    particle + 8 bytes per cell) / the launch's average duration; the layout's
+    own figure (state and tag in and out) beside it; `traffic` the measured
+    HBM bytes per launch (or None) and its ratio to the algorithmic bytes."""
+    alg = 2.0 * STATE_BYTES[form] * n_particles + 8.0 * n_cells
+    lay = layout_bytes_per_particle(form) * n_particles
+    sec = avg_us * 1e-6
+    gbs = alg / sec / 1e9
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "k_tile (collide + stream + bin + scatter)", "kernel_avg_us": avg_us,
+            "algorithmic_bytes_per_launch": alg,
+            "bytes_per_update": alg / max(n_particles, 1),
+            "layout_bytes_per_particle": layout_bytes_per_particle(form),
+            "layout_GBs": lay / sec / 1e9,
+            "traffic_over_algorithmic": None if traffic is None else traffic / alg}
 
 
 def measured_traffic(form, workload=WORKLOAD):
@@ -145,33 +168,61 @@ def make_input(cfg, scale=None):
         chains = max(1, int(round(cfg["chains"] * frac)))
         bpos, bvel, bmass = workloads.beads(n_cells, chains, cfg["chain_len"], kT=cfg["kT"],
                                             mass=cfg["bead_mass"], seed=cfg["seed"] + 1)
+        # solvent and beads start with zero total momentum together (sec. 4.1)
+        vel, bvel = workloads.zero_net_momentum([vel, bvel], [np.ones(len(vel)), bmass])
     return pos, vel, bpos, bvel, bmass
 
 
 def copy_ceiling(m, nbytes=1 << 30, reps=20):
-    """Bandwidth of the library's plain streaming copy kernel (read + write
-    bytes per second) on two device buffers of `nbytes`: the practical HBM
-    ceiling the step kernel is compared with."""
+    """Practical HBM ceiling: read + write bytes per second of a plain copy
+    between two device buffers of `nbytes`, by three copies -- the library's
+    grid-stride streaming kernel (one 16-byte vector per thread and
+    iteration), its unrolled variant (four vectors per thread, loads before
+    stores) and the runtime's device-to-device copy (hipMemcpyAsync, through
+    torch's copy_). Returns the figures and their maximum, the ceiling the
+    step kernel is compared with."""
     import torch
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
     src.fill_(1)
     stream = torch.cuda.current_stream().cuda_stream
-    for _ in range(3):
-        m.copy_kernel(src.data_ptr(), dst.data_ptr(), nbytes, stream)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        m.copy_kernel(src.data_ptr(), dst.data_ptr(), nbytes, stream)
-    e1.record()
-    torch.cuda.synchronize()
-    sec = e0.elapsed_time(e1) / 1e3 / reps
+    copies = {
+        "library_kernel": lambda: m.copy_kernel(src.data_ptr(), dst.data_ptr(), nbytes, stream),
+        "library_kernel_unrolled": lambda: m.copy_kernel(src.data_ptr(), dst.data_ptr(), nbytes,
+                                                         stream, unrolled=True),
+        "hipMemcpyAsync_d2d": lambda: dst.copy_(src),
+    }
+    out = {}
+    for name, fn in copies.items():
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3 / reps
+        out[name] = 2.0 * nbytes / sec / 1e9
     del src, dst
-    return 2.0 * nbytes / sec / 1e9
+    out["max"] = max(out.values())
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(inp, n_cells, cfg, nsteps, what):
+    """The FP64 oracle on one core (numpy limited to one thread)."""
+    from threadpoolctl import threadpool_limits
     from oracle import srd
     pos, vel, bpos, bvel, bmass = inp
     p = srd.Params(n_cells, seed=cfg["seed"], thermostat=cfg["thermostat"], kT=cfg["kT"])
@@ -179,13 +230,51 @@ def cpu_baseline(inp, n_cells, cfg, nsteps, what):
     if bpos is not None:
         pos, vel = np.concatenate([pos, bpos]), np.concatenate([vel, bvel])
         mass = np.concatenate([mass, bmass])
-    t0 = time.perf_counter()
-    srd.run(pos, vel, mass, p, 0, nsteps)
-    dt = time.perf_counter() - t0
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        srd.run(pos, vel, mass, p, 0, nsteps)
+        dt = time.perf_counter() - t0
     return dict(value=pos.shape[0] * nsteps / dt, unit="particle-updates/s", cores=1,
                 kind="oracle",
                 sample=f"{nsteps} FP64 oracle steps of {what} ({pos.shape[0]} particles, "
                        f"{dt:.1f} s, numpy, single thread)")
+
+
+def _oracle_replica(job):
+    """One worker of the all-core baseline: the FP64 oracle on its own box
+    (numpy limited to one thread), started together with the other workers
+    (barrier); returns (updates, start, end)."""
+    from threadpoolctl import threadpool_limits
+    import workloads
+    from oracle import srd
+    (n_cells, density, kT, seed, thermostat, nsteps), barrier = job
+    pos, vel = workloads.fluid(n_cells, density, kT=kT, seed=1000 + seed)
+    p = srd.Params(n_cells, seed=seed, thermostat=thermostat, kT=kT)
+    with threadpool_limits(1):
+        barrier.wait()
+        t0 = time.time()
+        srd.run(pos, vel, np.ones(pos.shape[0]), p, 0, nsteps)
+        t1 = time.time()
+    return pos.shape[0] * nsteps, t0, t1
+
+
+def cpu_baseline_all_cores(jobs, what, max_workers=16):
+    """The FP64 oracle on every host core: independent boxes (`jobs`) in a
+    process pool of min(cores available, 16) workers, one thread each;
+    value = all updates / (last end - first start)."""
+    import multiprocessing
+    ctx = multiprocessing.get_context("spawn")
+    cores = min(len(os.sched_getaffinity(0)), max_workers, len(jobs))
+    with ctx.Manager() as mgr:
+        barrier = mgr.Barrier(cores)
+        with ctx.Pool(cores) as pool:
+            res = pool.map(_oracle_replica, [(j, barrier) for j in jobs[:cores]], chunksize=1)
+    ups = sum(r[0] for r in res)
+    wall = max(r[2] for r in res) - min(r[1] for r in res)
+    return dict(value=ups / wall, unit="particle-updates/s", cores=cores, kind="oracle",
+                cpu_model=cpu_model(),
+                sample=f"{what}: {len(jobs)} independent boxes in a pool of {cores} processes "
+                       f"(one thread each), {ups} updates in {wall:.1f} s, FP64 numpy")
 
 
 def fp32_accuracy(m, inp, cfg):
@@ -219,6 +308,7 @@ def bench_batch(m, workloads, cfg, args):
     steps = cfg["steps"] if args.steps == 1000 else args.steps
     boxes = workloads.replica_inputs(workloads.replica_boxes(cfg["n_rep"], seed=cfg["seed"]))
     N = sum(b["pos"].shape[0] for b in boxes)
+    ncells = sum(int(np.prod(b["n_cells"])) for b in boxes)
     torch.cuda.init()
     bt = m.Batch(boxes, precision=m.FP32, thermostat=cfg["thermostat"])
     del boxes
@@ -246,7 +336,6 @@ def bench_batch(m, workloads, cfg, args):
         bt.close()
     ups = N * steps / (t1 - t0)
     avg_us = 1e3 * coll_ms / max(coll_n, 1)
-    gbs = collide_bytes_per_particle("fp32", 7.5) * N / (avg_us * 1e-6) / 1e9
     lat_ms = 1e3 * np.array(lat)
     out = {
         "metric": "particle-updates/s (stream+bin+SRD collide) FP32 vs FP64; p99 batch latency",
@@ -261,10 +350,8 @@ def bench_batch(m, workloads, cfg, args):
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
                        "p99": float(np.percentile(lat_ms, 99)),
                        "what": "one mpcd_step(1) call on the whole batch, waited for"},
-        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic("fp32", "srd_batch256_fp32"),
-                     "kernel": "k_tile (collide + stream + bin + scatter)",
-                     "kernel_avg_us": avg_us, "bytes_per_particle": collide_bytes_per_particle("fp32", 7.5)},
+        "roofline": roofline("fp32", N, ncells, avg_us,
+                             measured_traffic("fp32", "srd_batch256_fp32")),
         "draw_avg_us": 1e3 * draw_ms / max(draw_n, 1),
         "kT_range_end": [float(kT.min()), float(kT.max())],
     }
@@ -414,7 +501,6 @@ def bench_md(m, workloads, cfg, args):
     cyc = (t1 - t0) / steps
     plain = (t3 - t2) / steps
     avg_us = 1e3 * coll_ms / max(coll_n, 1)
-    gbs = collide_bytes_per_particle("fp32", cfg["density"]) * N / (avg_us * 1e-6) / 1e9
     out = {
         "metric": "particle-updates/s (stream+bin+SRD collide) FP32 vs FP64; p99 batch latency",
         "value": N / cyc, "unit": "particle-updates/s", "n_gpus": 1, "steps": steps,
@@ -424,10 +510,7 @@ def bench_md(m, workloads, cfg, args):
                    "particles": N, "density": cfg["density"], "embedded_beads": int(bpos.shape[0]),
                    "coupling": "external MD, state exchanged on device every collision",
                    "thermostat": "none", "form": "fp32"},
-        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_tile (collide + stream + bin + scatter)", "kernel_avg_us": avg_us,
-                     "bytes_per_particle": collide_bytes_per_particle("fp32", cfg["density"])},
+        "roofline": roofline("fp32", N, int(np.prod(cfg["n_cells"])), avg_us),
         "bin_kernel_avg_us": 1e3 * bin_ms / max(bin_n, 1),
         "ms_per_step_without_exchange": 1e3 * plain,
         "exchange_overhead_ms": 1e3 * (cyc - plain),
@@ -481,6 +564,7 @@ def main():
     inp = make_input(cfg)
     N = inp[0].shape[0] + (0 if inp[2] is None else inp[2].shape[0])
     rho = cfg["density"]
+    ncells = int(np.prod(cfg["n_cells"]))
     torch.cuda.init()
     default_forms = "fp64" if small else ("fp32" if big else "fp32,fp64,fp32_at,fp64_at")
     forms = [f.strip() for f in (args.forms or default_forms).split(",") if f.strip()]
@@ -496,8 +580,7 @@ def main():
         r["ms_per_step"] = 1e3 * r["seconds"] / args.steps
         avg_us = 1e3 * r["collide_ms"] / max(r["collide_launches"], 1)
         r["collide_avg_us"] = avg_us
-        per_launch = collide_bytes_per_particle(base, rho) * N
-        r["collide_GBs"] = per_launch / (avg_us * 1e-6) / 1e9
+        r["collide_GBs"] = roofline(base, N, ncells, avg_us)["achieved"]
         r["step_floor_frac"] = r["updates_per_s"] * floor_bytes_per_update(base, rho) / (HBM_PEAK_GBS * 1e9)
         r["rule"] = "at" if rule == m.AT else "srd"
         r["thermostat"] = "maxwell-boltzmann" if (cfg["thermostat"] and rule == m.SRD) else "none"
@@ -528,17 +611,8 @@ def main():
                    "thermostat": "maxwell-boltzmann" if cfg["thermostat"] else "none",
                    "embedded_beads": 0 if inp[2] is None else int(inp[2].shape[0]),
                    "grid_shift": True, "form": head_form},
-        "roofline": {
-            "bound": "hbm",
-            "achieved": head["collide_GBs"],
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": head["collide_GBs"] / HBM_PEAK_GBS,
-            "traffic": measured_traffic(head_form, wl) if head_form in STATE_BYTES else None,
-            "kernel": "k_tile (collide + stream + bin + scatter)",
-            "kernel_avg_us": head["collide_avg_us"],
-            "bytes_per_particle": collide_bytes_per_particle(head_form.split("_")[0], rho),
-        },
+        "roofline": roofline(head_form.split("_")[0], N, ncells, head["collide_avg_us"],
+                             measured_traffic(head_form, wl) if head_form in STATE_BYTES else None),
         "step_floor_frac": head["step_floor_frac"],
         "forms": {f: {"updates_per_s": r["updates_per_s"], "ms_per_step": r["ms_per_step"],
                       "collide_avg_us": r["collide_avg_us"], "collide_GBs": r["collide_GBs"],
@@ -546,8 +620,10 @@ def main():
                       "step_floor_frac": r["step_floor_frac"], "kT_end": r["kT"],
                       "net_momentum_end": r["net_momentum"]} for f, r in res.items()},
     }
-    out["copy_ceiling_GBs"] = copy_ceiling(m)
-    out["roofline"]["frac_of_copy_ceiling"] = head["collide_GBs"] / out["copy_ceiling_GBs"]
+    copies = copy_ceiling(m)
+    out["copy_ceiling_GBs"] = copies["max"]
+    out["copies_GBs"] = copies
+    out["roofline"]["frac_of_copy_ceiling"] = head["collide_GBs"] / copies["max"]
     if "fp32" in res and "fp64" in res:
         out["fp32_over_fp64"] = res["fp32"]["updates_per_s"] / res["fp64"]["updates_per_s"]
         out["fp32_accuracy"] = fp32_accuracy(m, inp, cfg)
@@ -556,13 +632,22 @@ def main():
             out[base + "_at_over_srd"] = res[base + "_at"]["updates_per_s"] / res[base]["updates_per_s"]
     if not args.no_cpu_baseline:
         if big and not small:
-            out["cpu_baseline"] = cpu_baseline(make_input(cfg, scale=60), (60, 60, 60), cfg,
-                                               args.cpu_steps,
-                                               "a 60^3-cell sample box of the same recipe")
+            single = cpu_baseline(make_input(cfg, scale=60), (60, 60, 60), cfg, args.cpu_steps,
+                                  "a 60^3-cell sample box of the same recipe")
         else:
-            out["cpu_baseline"] = cpu_baseline(inp, cfg["n_cells"], cfg,
-                                               cfg["steps"] if small else args.cpu_steps,
-                                               "the full workload")
+            single = cpu_baseline(inp, cfg["n_cells"], cfg,
+                                  cfg["steps"] if small else args.cpu_steps, "the full workload")
+        if small:
+            single["cpu_model"] = cpu_model()
+            out["cpu_baseline"] = single
+        else:
+            # every core: independent 60^3-cell boxes of the workload's recipe
+            # (density, kT, thermostat), one per worker, seeds 1, 2, ...
+            jobs = [((60, 60, 60), rho, cfg["kT"], 1 + i, cfg["thermostat"], args.cpu_steps)
+                    for i in range(min(len(os.sched_getaffinity(0)), 16))]
+            allc = cpu_baseline_all_cores(jobs, f"{args.cpu_steps} oracle steps per box")
+            allc["single_core"] = single
+            out["cpu_baseline"] = allc
     print(json.dumps(out), flush=True)
 
 

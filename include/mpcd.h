@@ -54,6 +54,20 @@ typedef enum {
   MPCD_ESTATE = 5  /* call out of order                                           */
 } mpcd_status;
 
+/* Storage forms (sec. 4.1, mixed precision). Both compute the cell sums,
+ * the draws and the rotation in FP64 and keep the cell sums in integer fixed
+ * point, so results do not depend on the order the particles are summed in.
+ *  MPCD_FP64  positions and velocities in double precision; two-limb sums of
+ *             resolution 2^-72; every term (m v_d, and m |v - u|^2 with the
+ *             thermostat, m dv_d under the AT rule) must satisfy
+ *             |term| < 2^30, and every displacement |v_d dt| < L_d.
+ *  MPCD_FP32  position = home cell (10 bits per axis: at most 1024 cells per
+ *             axis) plus an FP32 offset inside it, FP32 velocities; one-limb
+ *             sums of resolution 2^-40 with |term| < 2^11 = 2048. With unit
+ *             mass that bounds a velocity component by 2048 (and
+ *             |v - u| by 45 with the thermostat); a strongly boosted flow or
+ *             heavy, fast embedded particles can exceed it in this form only.
+ * A term outside its range makes the step report MPCD_ERANGE. */
 typedef enum { MPCD_FP64 = 0, MPCD_FP32 = 1 } mpcd_precision;
 
 /* Collision rule: stochastic rotation (eq. 2, Alg. 1), or the Andersen
@@ -293,6 +307,12 @@ mpcd_status mpcd_philox4x32_10(const uint32_t* ctr, int64_t n, uint64_t key,
  * Asynchronous on the stream. */
 mpcd_status mpcd_copy_kernel(const void* src, void* dst, int64_t bytes,
                              void* hip_stream);
+
+/* The same copy with four 16-byte vectors per thread and iteration, all
+ * loaded before any is stored; a second estimate of the achievable HBM
+ * bandwidth. Same arguments and behaviour as mpcd_copy_kernel. */
+mpcd_status mpcd_copy_kernel_unrolled(const void* src, void* dst, int64_t bytes,
+                                      void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -94,6 +94,7 @@ def load():
         "mpcd_last_error": (ctypes.c_char_p, []),
         "mpcd_philox4x32_10": (st, [_P, ctypes.c_int64, ctypes.c_uint64, _P]),
         "mpcd_copy_kernel": (st, [_P, _P, ctypes.c_int64, _P]),
+        "mpcd_copy_kernel_unrolled": (st, [_P, _P, ctypes.c_int64, _P]),
         "mpcd_create_batch": (st, [ctypes.c_int32, ctypes.POINTER(Params), _P, _P, _P,
                                    ctypes.c_int32, _P, ctypes.POINTER(_P)]),
         "mpcd_get_n_boxes": (st, [_P, ctypes.POINTER(ctypes.c_int32)]),
@@ -375,7 +376,9 @@ def philox(ctr, key):
     return out
 
 
-def copy_kernel(src_ptr, dst_ptr, nbytes, hip_stream=None):
-    """Device copy with the library's streaming kernel (device pointers)."""
-    _check(load().mpcd_copy_kernel(ctypes.c_void_p(src_ptr), ctypes.c_void_p(dst_ptr),
-                                   int(nbytes), None if hip_stream is None else ctypes.c_void_p(hip_stream)))
+def copy_kernel(src_ptr, dst_ptr, nbytes, hip_stream=None, unrolled=False):
+    """Device copy with the library's streaming kernel (device pointers);
+    `unrolled` selects the four-vectors-per-thread variant."""
+    fn = load().mpcd_copy_kernel_unrolled if unrolled else load().mpcd_copy_kernel
+    _check(fn(ctypes.c_void_p(src_ptr), ctypes.c_void_p(dst_ptr), int(nbytes),
+              None if hip_stream is None else ctypes.c_void_p(hip_stream)))

@@ -1372,7 +1372,10 @@ mpcd_status mpcd_philox4x32_10(const uint32_t* ctr, int64_t n, uint64_t key, uin
   return MPCD_OK;
 }
 
-mpcd_status mpcd_copy_kernel(const void* src, void* dst, int64_t bytes, void* hip_stream) {
+}  // extern "C"
+
+static mpcd_status copy_impl(const void* src, void* dst, int64_t bytes, void* hip_stream,
+                             bool unrolled) {
   g_err.clear();
   if (bytes < 0 || (!src && bytes) || (!dst && bytes)) return fail(MPCD_EINVAL, "bad copy arguments");
   if (bytes == 0) return MPCD_OK;
@@ -1380,8 +1383,13 @@ mpcd_status mpcd_copy_kernel(const void* src, void* dst, int64_t bytes, void* hi
   const bool aligned = ((uintptr_t)src % 16 == 0) && ((uintptr_t)dst % 16 == 0);
   const size_t n16 = aligned ? (size_t)bytes / 16 : 0;
   if (n16) {
-    const uint32_t nb = (uint32_t)std::min<size_t>((n16 + 255) / 256, 256u * 256u);
-    k_copy16<<<nb, 256, 0, s>>>((const uint4*)src, (uint4*)dst, n16);
+    if (unrolled) {
+      const uint32_t nb = (uint32_t)std::min<size_t>((n16 + 1023) / 1024, 256u * 256u);
+      k_copy16x4<<<nb, 256, 0, s>>>((const uint4*)src, (uint4*)dst, n16);
+    } else {
+      const uint32_t nb = (uint32_t)std::min<size_t>((n16 + 255) / 256, 256u * 256u);
+      k_copy16<<<nb, 256, 0, s>>>((const uint4*)src, (uint4*)dst, n16);
+    }
   }
   const size_t tail = (size_t)bytes - n16 * 16;
   if (tail)
@@ -1389,6 +1397,16 @@ mpcd_status mpcd_copy_kernel(const void* src, void* dst, int64_t bytes, void* hi
                                                   (unsigned char*)dst + n16 * 16, tail);
   HIP_TRY(hipGetLastError());
   return MPCD_OK;
+}
+
+extern "C" {
+
+mpcd_status mpcd_copy_kernel(const void* src, void* dst, int64_t bytes, void* hip_stream) {
+  return copy_impl(src, dst, bytes, hip_stream, false);
+}
+
+mpcd_status mpcd_copy_kernel_unrolled(const void* src, void* dst, int64_t bytes, void* hip_stream) {
+  return copy_impl(src, dst, bytes, hip_stream, true);
 }
 
 }  // extern "C"

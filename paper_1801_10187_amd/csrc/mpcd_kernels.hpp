@@ -1440,6 +1440,23 @@ __global__ __launch_bounds__(256) void k_copy16(const uint4* __restrict__ src,
     nt_store(dst + i, nt_load(src + i));
 }
 
+// The same copy with four vectors per thread and iteration, all four loaded
+// before any is stored (more loads in flight per wave).
+__global__ __launch_bounds__(256) void k_copy16x4(const uint4* __restrict__ src,
+                                                  uint4* __restrict__ dst, size_t n16) {
+  const size_t stride = (size_t)gridDim.x * 256u;
+  size_t i = (size_t)blockIdx.x * 256u + threadIdx.x;
+  for (; i + 3 * stride < n16; i += 4 * stride) {
+    const uint4 a = nt_load(src + i), b = nt_load(src + i + stride);
+    const uint4 c = nt_load(src + i + 2 * stride), d = nt_load(src + i + 3 * stride);
+    nt_store(dst + i, a);
+    nt_store(dst + i + stride, b);
+    nt_store(dst + i + 2 * stride, c);
+    nt_store(dst + i + 3 * stride, d);
+  }
+  for (; i < n16; i += stride) nt_store(dst + i, nt_load(src + i));
+}
+
 __global__ void k_copy1(const unsigned char* __restrict__ src,
                         unsigned char* __restrict__ dst, size_t n) {
   const size_t i = (size_t)blockIdx.x * 256u + threadIdx.x;

@@ -42,5 +42,32 @@ def f32_close(a, b, abs_tol=FP32_FIXED_ABS):
     return (ulp_diff_f32(a, b) <= 1) | (absd <= abs_tol)
 
 
+def fp32_step_matches(gpos0, gvel0, gpos1, gvel1, gcells1, mass, p, step, fp32form):
+    """One FP32-form step checked element by element from the GPU's own state
+    before it (read back exactly: h a + o and FP32 velocities are exact in
+    FP64 for a = 1): cells and positions bit-exact, every velocity component
+    within one FP32 ulp of the oracle's emulation of that step, or within
+    2^-40 absolute (the resolution of the form's one-limb cell sums, which
+    exceeds an ulp only for results within ~1e-6 of zero). Checking each
+    step from the GPU's state keeps the check strict over many steps, where a
+    one-ulp difference could otherwise move a particle across a cell face and
+    part the two trajectories."""
+    h, o, v = fp32form.from_double(gpos0, gvel0, p)
+    assert np.array_equal(fp32form.to_double(h, o, p), gpos0), "FP32 state does not round-trip"
+    assert np.array_equal(v.astype(np.float64), gvel0)
+    h1, o1, v1, info = fp32form.step32(h, o, v, mass, p, step)
+    assert np.array_equal(gcells1, info["cell"])
+    assert np.array_equal(gpos1, fp32form.to_double(h1, o1, p))
+    close = f32_close(gvel1, v1)
+    if not np.all(close):
+        bad = ~close
+        g32 = np.asarray(gvel1, dtype=np.float32)
+        raise AssertionError(
+            f"step {step}: {bad.sum()} velocity components beyond one ulp and 2^-40: "
+            f"ulps {ulp_diff_f32(g32[bad], v1[bad])[:8]}, oracle {v1[bad][:8]}, "
+            f"gpu {g32[bad][:8]}")
+    return info
+
+
 def banner(msg):
     print(f"[gpu-test] {msg}", flush=True)

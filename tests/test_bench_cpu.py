@@ -20,12 +20,20 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_algorithmic_bytes():
-    # state read once and written once, with the 4-byte tag
-    assert bench.collide_bytes_per_particle("fp32", 10) == 64.0
-    assert bench.collide_bytes_per_particle("fp64", 10) == 104.0
-    # whole-step floor: 2 x state + one occupancy word per cell
+    # per update: the state read once and written once + one occupancy word
+    # per cell written and read once (8 / rho per particle)
     assert bench.floor_bytes_per_update("fp32", 10) == pytest.approx(56.8)
     assert bench.floor_bytes_per_update("fp64", 5) == pytest.approx(97.6)
+    # the roofline entry of one launch of the 10^7-particle fluid
+    r = bench.roofline("fp32", 10_000_000, 1_000_000, 100.0, traffic=6.0e8)
+    assert r["algorithmic_bytes_per_launch"] == pytest.approx(5.68e8)
+    assert r["achieved"] == pytest.approx(5680.0)
+    assert r["frac"] == pytest.approx(0.71)
+    assert r["traffic_over_algorithmic"] == pytest.approx(6.0e8 / 5.68e8)
+    # the layout's own figure: state and 4-byte tag read once and written once
+    assert bench.layout_bytes_per_particle("fp32") == 64.0
+    assert bench.layout_bytes_per_particle("fp64") == 104.0
+    assert r["layout_GBs"] == pytest.approx(6400.0)
 
 
 def test_measured_traffic_is_tied_to_the_sources():
@@ -34,7 +42,7 @@ def test_measured_traffic_is_tied_to_the_sources():
     got = bench.measured_traffic("fp32")
     if rec.get("source_hash") == source_hash():
         assert got == rec["bytes_per_launch"]["srd_100c_rho10_mbthermo"]["fp32"]
-        # the counters read close to the algorithmic bytes (no wasted re-reads)
+        # the counters read close to the layout's bytes (no wasted re-reads)
         assert 1.0 < got / (64.0 * 1e7) < 1.1
     else:
         assert got is None
