@@ -137,7 +137,7 @@ def run_form(m, inp, cfg, precision, steps, warmup, collision=0):
         sim.step(warmup)
         sim.sync()
         sim.profile(True, every=PROFILE_EVERY)
-        for w in (0, 1, 2):
+        for w in (0, 1):
             sim.profile_read(w)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -146,13 +146,11 @@ def run_form(m, inp, cfg, precision, steps, warmup, collision=0):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         coll_ms, coll_n = sim.profile_read(0)
-        draw_ms, draw_n = sim.profile_read(2)
         sim.profile(False)
         P, ke, kT = sim.totals()
     finally:
         sim.close()
     return dict(seconds=t1 - t0, collide_ms=coll_ms, collide_launches=coll_n,
-                draw_us=1e3 * draw_ms / max(draw_n, 1),
                 net_momentum=float(np.abs(P).max()), kT=kT)
 
 
@@ -316,14 +314,13 @@ def bench_batch(m, workloads, cfg, args):
         bt.step(args.warmup)
         bt.sync()
         bt.profile(True, every=PROFILE_EVERY)
-        for w in (0, 1, 2):
+        for w in (0, 1):
             bt.profile_read(w)
         t0 = time.perf_counter()
         bt.step(steps)
         bt.sync()
         t1 = time.perf_counter()
         coll_ms, coll_n = bt.profile_read(0)
-        draw_ms, draw_n = bt.profile_read(2)
         bt.profile(False)
         lat = []
         for _ in range(100):
@@ -352,7 +349,6 @@ def bench_batch(m, workloads, cfg, args):
                        "what": "one mpcd_step(1) call on the whole batch, waited for"},
         "roofline": roofline("fp32", N, ncells, avg_us,
                              measured_traffic("fp32", "srd_batch256_fp32")),
-        "draw_avg_us": 1e3 * draw_ms / max(draw_n, 1),
         "kT_range_end": [float(kT.min()), float(kT.max())],
     }
     print(json.dumps(out), flush=True)
@@ -587,7 +583,7 @@ def main():
         res[form] = r
         print(f"[bench] {form}: {r['updates_per_s']:.4g} updates/s, "
               f"{r['ms_per_step']:.4f} ms/step, collide {avg_us:.1f} us "
-              f"({r['collide_GBs']:.0f} GB/s), draws {r['draw_us']:.1f} us",
+              f"({r['collide_GBs']:.0f} GB/s)",
               file=sys.stderr, flush=True)
 
     head = res.get("fp32") or res[forms[0]]
@@ -616,7 +612,7 @@ def main():
         "step_floor_frac": head["step_floor_frac"],
         "forms": {f: {"updates_per_s": r["updates_per_s"], "ms_per_step": r["ms_per_step"],
                       "collide_avg_us": r["collide_avg_us"], "collide_GBs": r["collide_GBs"],
-                      "draw_avg_us": r["draw_us"], "rule": r["rule"], "thermostat": r["thermostat"],
+                      "rule": r["rule"], "thermostat": r["thermostat"],
                       "step_floor_frac": r["step_floor_frac"], "kT_end": r["kT"],
                       "net_momentum_end": r["net_momentum"]} for f, r in res.items()},
     }

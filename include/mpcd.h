@@ -94,8 +94,8 @@ typedef struct {
 } mpcd_params;
 
 /* Test-only layout flag: size the per-tile particle slabs to the initial
- * maximum occupancy rounded up to a multiple of 4 (no other headroom), so
- * that the first steps overflow them and the enlarge-and-replay path runs.
+ * maximum occupancy (no headroom), so that the first steps overflow them
+ * and the enlarge-and-replay path runs.
  * Results are unchanged. */
 #define MPCD_FLAG_TIGHT_SLABS 1
 
@@ -274,10 +274,9 @@ mpcd_status mpcd_get_layout(mpcd_ctx ctx, int32_t tile[3], int64_t* n_tiles,
                             int64_t* capacity, int64_t* regrows);
 
 /* Kernel timing with HIP events on the context's stream. which: 0 the
- * collision kernel (collide, stream and bin of the next step), 1 the
- * stream / stream+bin kernels, 2 the thermostat draw kernel (Gamma draws of
- * every cell, launched before each collision when the thermostat is on;
- * sec. 3.6). on = 0 disables; on = P >= 1 brackets the first launch of each
+ * collision kernel (collide with its per-cell draws, stream and bin of the
+ * next step), 1 the stream / stream+bin kernels; MPCD_EINVAL for any other
+ * value. on = 0 disables; on = P >= 1 brackets the first launch of each
  * kind and then one in every P with two events (P = 1: every launch; each
  * bracketed launch costs a few microseconds of stream time, so a larger P
  * disturbs a timed run less). mpcd_profile_read synchronises, returns the

@@ -6,8 +6,8 @@
 // Particles live in fixed-capacity per-tile slabs (see mpcd_kernels.hpp); the
 // tiles of all boxes share the slab arrays, and every launch covers all of
 // them. A call to mpcd_step launches, unless the last call left the binning
-// prepared, one stream+bin kernel and then, per step, the thermostat draws
-// (if on) and one tile kernel; it waits for the stream at its end to confirm
+// prepared, one stream+bin kernel and then one tile kernel per step (the
+// thermostat's draws included); it waits for the stream at its end to confirm
 // that no slab overflowed. If one did, the input of the failing launch is
 // still intact: the slabs are enlarged, that input is repacked, and the
 // launches are replayed from there.
@@ -60,7 +60,7 @@ enum class Phase { Idle, Streamed, Binned };
 // current: it keeps the positions (and cells) of the state after the
 // collision, while the output holds that state's velocities, streamed and
 // binned for the next step (see `split`).
-enum class Op { BinStream, Bin, Draw, CollideScatter, Collide, CollideLast };
+enum class Op { BinStream, Bin, CollideScatter, Collide, CollideLast };
 struct Launch {
   Op op;
   uint64_t step;
@@ -70,9 +70,6 @@ constexpr uint32_t kGrid = 256;  // threads per block of the elementwise kernels
 // slots per tile stay below 2^28: a slot's byte offset inside its tile's
 // slab then fits 32 bits for every element size
 constexpr uint32_t kMaxCap = 1u << 28;
-// every box starts at a multiple of this many tiles (k_draw takes up to 4
-// consecutive tiles per block, all of one box)
-constexpr uint32_t kTileAlign = 4;
 
 inline uint32_t blocks_for(uint64_t n, uint32_t per) {
   return (uint32_t)((n + per - 1) / per);
@@ -105,7 +102,6 @@ struct mpcd_ctx_s {
   uint32_t* flag = nullptr;        // one word a host call checks after a kernel (range errors)
   uint32_t* eslot[2] = {nullptr, nullptr};  // slot of each embedded particle in buf[0], buf[1]
   uint32_t* status = nullptr;      // [0] errors, [1] overflow, [2] failing launch
-  double* ehat = nullptr;          // thermostat draws of the next collision, [tile][cpt]
   long long* tot = nullptr;        // fixed-point totals, 10 words per box
 
   ShiftEntry* shifts = nullptr;    // grid shifts of steps shift_n0 .., [step][box]
@@ -127,9 +123,9 @@ struct mpcd_ctx_s {
   int64_t regrows = 0;
 
   int32_t prof_every = 0;          // time one launch in every prof_every of a kind (0: off)
-  uint64_t prof_seen[3] = {0, 0, 0};
+  uint64_t prof_seen[2] = {0, 0};
   std::vector<hipEvent_t> ev_pool;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[3];
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[2];
 
   // Device memory comes from the stream-ordered allocator on the context's
   // stream: allocating and freeing never waits for the whole device, so
@@ -291,36 +287,13 @@ TileArgs tile_args(mpcd_ctx c) {
   a.cnt_clear = c->cnt[(c->ci + 2) % 3];
   a.emb_mass = c->emb_mass;
   a.status = c->status;
-  a.ehat = c->ehat;
   a.eslot_out = c->n_emb ? c->eslot[1 - c->cur] : nullptr;
   return a;
-}
-
-template <int CPT>
-void draw_inst(mpcd_ctx c, uint64_t n, uint32_t seq) {
-  constexpr uint32_t tpb = DT / CPT;
-  const uint32_t nb = (c->S.ntiles + tpb - 1) / tpb;
-  k_draw<CPT><<<nb, DT, 0, c->stream>>>(c->buf[c->cur], c->S, c->cnt[c->ci], (uint32_t)n, c->ehat,
-                                        c->status, seq);
-}
-
-// Thermostat draws for the collision of step n on the current slabs.
-mpcd_status launch_draw(mpcd_ctx c, uint64_t n, uint32_t seq) {
-  if (!c->p.thermostat || c->S.ntiles == 0) return MPCD_OK;
-  ProfScope ps(c, 2);
-  switch (c->cpt) {
-    case 64: draw_inst<64>(c, n, seq); break;
-    case 128: draw_inst<128>(c, n, seq); break;
-    default: draw_inst<256>(c, n, seq); break;
-  }
-  HIP_TRY(hipGetLastError());
-  return MPCD_OK;
 }
 
 // One tile-kernel launch for step n. The shift table must hold step n (and
 // n + 1 for a collision fused with the next binning).
 mpcd_status launch_tile(mpcd_ctx c, Op op, uint64_t n, uint32_t seq) {
-  if (op == Op::Draw) return launch_draw(c, n, seq);
   TileArgs a = tile_args(c);
   a.step = (uint32_t)n;
   a.seq = seq;
@@ -528,17 +501,21 @@ mpcd_status validate(const mpcd_params* p, int64_t ns, int64_t ne) {
   return MPCD_OK;
 }
 
-// Tile shape of one box: about 350-770 particles per tile at the box's mean
-// density (the kernels hold up to 768 particles of a 64-cell tile and 1024
-// of a larger one in registers). Returns the cells per tile, rounded up to
-// the kernel sizes 64/128/256.
+// Tile shape of one box: 64-cell tiles (224-768 particles per tile at the
+// box's mean density) wherever the density allows, since their step kernel
+// keeps the particles' positions in LDS and runs at the highest occupancy
+// (measured on the 256-box batch: 64-cell tiles down to density 3.5 step it
+// 15 % faster than 128-cell tiles from density 7 down); sparser boxes take
+// larger tiles. The kernels hold up to 768 particles of a 64-cell tile and
+// 1024 of a larger one in registers; more are read again from memory.
+// Returns the cells per tile, rounded up to the kernel sizes 64/128/256.
 int choose_tiles(Box& B, double rho) {
   int td[3], cpt;
   if (rho >= 11.0) {
     td[0] = 4; td[1] = 4; td[2] = 2; cpt = 64;
-  } else if (rho >= 7.0) {
-    td[0] = 4; td[1] = 4; td[2] = 4; cpt = 64;
   } else if (rho >= 3.5) {
+    td[0] = 4; td[1] = 4; td[2] = 4; cpt = 64;
+  } else if (rho >= 1.75) {
     td[0] = 8; td[1] = 4; td[2] = 4; cpt = 128;
   } else {
     td[0] = 8; td[1] = 8; td[2] = 4; cpt = 256;
@@ -656,9 +633,7 @@ mpcd_status create_impl(int32_t nbox, const mpcd_params* params, const int64_t* 
     Box B = make_box(params[b]);
     const uint32_t nb = (uint32_t)n_solv[b] + (b == 0 ? c->n_emb : 0u);
     cpt = std::max(cpt, choose_tiles(B, B.ncells ? (double)nb / (double)B.ncells : 0.0));
-    // padding up to a multiple of kTileAlign belongs to the box before it
-    const uint32_t t0 = round_up(tile, kTileAlign);
-    tile_box.resize(t0, b == 0 ? 0u : (uint32_t)(b - 1));
+    const uint32_t t0 = tile;
     B.tile0 = t0;
     B.tag0 = tag;
     B.cell0 = (uint32_t)cell;
@@ -671,8 +646,7 @@ mpcd_status create_impl(int32_t nbox, const mpcd_params* params, const int64_t* 
     c->boxes.push_back(B);
     c->box_n.push_back(nb);
   }
-  const uint32_t NT = round_up(tile, kTileAlign);
-  tile_box.resize(NT, (uint32_t)(nbox - 1));
+  const uint32_t NT = tile;
   c->cpt = cpt;
   c->ncells = cell;
   c->S.ntiles = NT;
@@ -700,10 +674,6 @@ mpcd_status create_impl(int32_t nbox, const mpcd_params* params, const int64_t* 
   if (!c->cnt[0] || !c->cnt[1] || !c->cnt[2] || !c->status || !c->tot || !c->emb_mass || !dboxes ||
       !dtb || !bad)
     return cleanup(fail(MPCD_ENOMEM, "device allocation failed"));
-  if (params[0].thermostat) {
-    c->ehat = (double*)c->dalloc((size_t)NT * c->cpt * 8);
-    if (!c->ehat) return cleanup(fail(MPCD_ENOMEM, "device allocation failed"));
-  }
   c->S.boxes = dboxes;
   c->S.tile_box = dtb;
   const uint32_t st_init[8] = {0u, 0u, 0xFFFFFFFFu, 0u, 0u, 0u, 0u, 0u};
@@ -791,7 +761,7 @@ mpcd_status create_impl(int32_t nbox, const mpcd_params* params, const int64_t* 
   for (uint32_t v : cnt_h) mx = std::max(mx, v);
   uint32_t cap;
   if ((uint32_t)params[0].flags & MPCD_FLAG_TIGHT_SLABS) {
-    cap = round_up(std::max<uint32_t>(mx, 1u), 4);  // the draw kernel reads 4 local-cell bytes at once
+    cap = std::max<uint32_t>(mx, 1u);
   } else {
     const uint64_t want = std::max<uint64_t>((uint64_t)mx + mx / 5,
                                              (uint64_t)(max_mean + 8.0 * std::sqrt(max_mean) + 64.0));
@@ -956,7 +926,6 @@ mpcd_status mpcd_collide(mpcd_ctx c) {
   ST_TRY(check_ctx(c));
   if (c->phase != Phase::Binned) return fail(MPCD_ESTATE, "mpcd_collide: expected a preceding mpcd_bin");
   ST_TRY(ensure_shifts(c, c->step, 1));
-  ST_TRY(launch_draw(c, c->step, 0));
   ST_TRY(launch_tile(c, Op::Collide, c->step, 0));
   c->step += 1;
   c->phase = Phase::Idle;
@@ -971,7 +940,7 @@ mpcd_status mpcd_step(mpcd_ctx c, int64_t nsteps) {
   if (c->step + (uint64_t)nsteps > 0xFFFFFFFFull) return fail(MPCD_ERANGE, "step counter beyond 2^32 - 1");
   ST_TRY(ensure_shifts(c, c->step, (uint64_t)nsteps + 1));
   std::vector<Launch> L;
-  L.reserve(2 * (size_t)nsteps + 1);
+  L.reserve((size_t)nsteps + 1);
   if (c->pre) {  // the last call left this step's binning ready
     c->cur = 1 - c->cur;
     c->ci = (c->ci + 1) % 3;
@@ -986,7 +955,6 @@ mpcd_status mpcd_step(mpcd_ctx c, int64_t nsteps) {
   // buffer (no velocities to copy back before the next stream and binning).
   const Op last = (c->p.flags & MPCD_FLAG_MD_SOLUTE) ? Op::Collide : Op::CollideLast;
   for (int64_t k = 0; k < nsteps; ++k) {
-    if (c->p.thermostat) L.push_back({Op::Draw, c->step + (uint64_t)k});
     L.push_back({k + 1 < nsteps ? Op::CollideScatter : last, c->step + (uint64_t)k});
   }
   ST_TRY(run_launches(c, L));
@@ -1172,7 +1140,6 @@ static mpcd_status cell_diag(mpcd_ctx c, double* mass, double* mom, double* ek, 
   a.d_axis = tmp + 5 * C;
   a.d_xi = tmp + 8 * C;
   hipError_t e = hipMemsetAsync(tmp, 0, C * 8 * 9, c->stream);
-  if (e == hipSuccess && launch_draw(c, c->step, 0) != MPCD_OK) e = hipGetLastError();
   if (e == hipSuccess) {
     if (c->form == 0) tile_dispatch<0>(c, a, MODE_DIAG, false);
     else tile_dispatch<1>(c, a, MODE_DIAG, false);
@@ -1335,7 +1302,7 @@ mpcd_status mpcd_profile_enable(mpcd_ctx c, int32_t on) {
 
 mpcd_status mpcd_profile_read(mpcd_ctx c, int32_t which, double* total_ms, int64_t* launches) {
   ST_TRY(check_ctx(c));
-  if (which < 0 || which > 2) return fail(MPCD_EINVAL, "which must be 0, 1 or 2");
+  if (which < 0 || which > 1) return fail(MPCD_EINVAL, "which must be 0 or 1");
   HIP_TRY(hipStreamSynchronize(c->stream));
   double ms = 0.0;
   auto& v = c->ev_used[which];

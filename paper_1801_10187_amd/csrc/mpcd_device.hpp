@@ -217,13 +217,18 @@ __device__ inline void gamma_numbers(uint32_t cell, uint32_t step, uint32_t j, u
   g = sqrt(-2.0 * log(u0)) * cospi(2.0 * u1);
 }
 
+// The squeeze U < 1 - 0.0331 g^4. It does not depend on k (so not on N_c).
+__device__ inline bool gamma_squeeze(double g, double u2) {
+  const double sq = g * g;
+  return u2 < 1.0 - 0.0331 * (sq * sq);
+}
+
 // The decision that needs no logarithm of U, from the attempt's numbers.
 __device__ inline int gamma_decide(double g, double u2, double c, double& V) {
   const double t = 1.0 + c * g;
   V = t * t * t;
   if (t <= 0.0) return GQ_REJECT;
-  const double sq = g * g;
-  return u2 < 1.0 - 0.0331 * (sq * sq) ? GQ_ACCEPT : GQ_FULL;
+  return gamma_squeeze(g, u2) ? GQ_ACCEPT : GQ_FULL;
 }
 
 __device__ inline int gamma_quick(uint32_t cell, uint32_t step, uint32_t j, double c,
@@ -233,8 +238,13 @@ __device__ inline int gamma_quick(uint32_t cell, uint32_t step, uint32_t j, doub
   return gamma_decide(g, u2, c, V);
 }
 
+// The full test with log U given (lu).
+__device__ inline bool gamma_full_log(double g, double V, double lu, double d) {
+  return lu < 0.5 * g * g + d - d * V + d * log(V);
+}
+
 __device__ inline bool gamma_full(double g, double V, double u2, double d) {
-  return log(u2) < 0.5 * g * g + d - d * V + d * log(V);
+  return gamma_full_log(g, V, log(u2), d);
 }
 
 __device__ inline double gamma_attempt(uint32_t cell, uint32_t step, uint32_t j,
@@ -253,6 +263,8 @@ __device__ inline double gamma_mt(double k, uint32_t cell, uint32_t step,
                                   bool& cap_hit, uint32_t j0 = 0u) {
   const double d = k - 1.0 / 3.0;
   const double c = 1.0 / sqrt(9.0 * d);
+  // attempts one at a time: an unrolled loop would only hold more registers
+#pragma nounroll
   for (uint32_t j = j0; j < (uint32_t)GAMMA_MAX_ATTEMPTS; ++j) {
     const double e = gamma_attempt(cell, step, j, d, c, theta, k0, k1);
     if (e >= 0.0) return e;

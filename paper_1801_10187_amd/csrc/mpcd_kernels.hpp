@@ -69,12 +69,11 @@ __device__ inline bool streamed(const Box& B, uint32_t tag) {
 }
 
 // Several independent boxes share one set of slabs: box b owns the tiles
-// [tile0, tile0 + ntiles) (padded so that every box starts at a multiple of
-// 4 tiles), its particles carry the tags [tag0, tag0 + n).
+// [tile0, tile0 + ntiles), its particles carry the tags [tag0, tag0 + n).
 struct Slabs {
   const Box* boxes;          // per box, device memory
   const uint32_t* tile_box;  // tile -> box
-  uint32_t ntiles;           // all tiles, padding included
+  uint32_t ntiles;           // tiles of all boxes
   uint32_t cap;              // slots per tile
 };
 
@@ -325,6 +324,57 @@ struct Pos<1> {
   __device__ void home3(const Box&, int c[3]) const { unpack_home(hp, c[0], c[1], c[2]); }
 };
 
+// Position records staged in LDS (16 bytes per particle): the FP32 form's
+// whole position word {home cell, offset x, y, z}; the FP64 form's {x, y},
+// whose z travels in the velocity word and stays in a register.
+__device__ inline void pos_from_lds(const uint4& a, double, Pos<1>& r) {
+  r.hp = a.x;
+  r.o[0] = __uint_as_float(a.y);
+  r.o[1] = __uint_as_float(a.z);
+  r.o[2] = __uint_as_float(a.w);
+}
+__device__ inline void pos_from_lds(const uint4& a, double z, Pos<0>& r) {
+  r.x[0] = __hiloint2double((int)a.y, (int)a.x);
+  r.x[1] = __hiloint2double((int)a.w, (int)a.z);
+  r.x[2] = z;
+}
+__device__ inline uint4 pos_to_lds(const Pos<1>& r) {
+  return make_uint4(r.hp, __float_as_uint(r.o[0]), __float_as_uint(r.o[1]), __float_as_uint(r.o[2]));
+}
+__device__ inline uint4 pos_to_lds(const Pos<0>& r) {
+  return make_uint4((uint32_t)__double2loint(r.x[0]), (uint32_t)__double2hiint(r.x[0]),
+                    (uint32_t)__double2loint(r.x[1]), (uint32_t)__double2hiint(r.x[1]));
+}
+
+// Issue the load of the 16-byte position record of slot k of a tile straight
+// into LDS (global_load_lds_dwordx4): lane l of the wave writes
+// lds_wave + l. Completion is awaited with s_waitcnt before the LDS is read.
+// The FP32 form's records are read nontemporally, as its other loads are.
+template <int FORM>
+__device__ inline void stage_pos(const Particles& P, uint32_t k, uint4* lds_wave) {
+  const char* base = FORM == 0 ? reinterpret_cast<const char*>(P.wa) : reinterpret_cast<const char*>(P.ra);
+  constexpr int NT = FORM == 1 ? 2 : 0;  // cache policy: the nt bit
+  __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(base + (uint32_t)(k * 16u)),
+                                   (__attribute__((address_space(3))) void*)(lds_wave), 16, 0, NT);
+}
+
+// Velocity and tag of slot k, and the FP64 form's z (in the same word).
+template <int FORM>
+__device__ inline void load_vt_z(const Particles& P, uint32_t k, typename VelT<FORM>::T v[3],
+                                 uint32_t& tag, double& z) {
+  if constexpr (FORM == 0) {
+    const double2 b = ld(P.wb, k), c = ld(P.wc, k);
+    z = b.x;
+    v[0] = b.y;
+    v[1] = c.x;
+    v[2] = c.y;
+    tag = ld(P.tag, k);
+  } else {
+    load_vt<FORM>(P, k, v, tag);
+    z = 0.0;
+  }
+}
+
 // A whole particle: position, velocity and tag.
 template <int FORM, class I>
 __device__ inline void load_part(const Particles& P, I i, Pos<FORM>& r, typename VelT<FORM>::T v[3],
@@ -421,6 +471,7 @@ __device__ inline uint32_t dest_bin(const Box& B, const int t[3], const int c[3]
 enum { MODE_BIN = 0, MODE_COLLIDE = 1, MODE_COLLIDE_SCATTER = 2, MODE_DIAG = 3 };
 
 constexpr int TT = 256;         // threads per tile block
+constexpr uint32_t LC_PEND = 0x100u;  // in a particle's local cell: its cell's draw is pending
 // particles per thread held in registers (beyond TT * TQ a tile's particles
 // are re-read from memory): 3 for 64-cell tiles (up to 768 particles, used
 // at densities 7..11), 4 otherwise
@@ -438,7 +489,6 @@ struct TileArgs {
   const ShiftEntry* shn;    // per box: shift of the next step (collide + scatter)
   uint32_t* status;
   uint32_t seq;             // launch sequence number within one API call
-  const double* ehat;       // thermostat draws of this collision, [tile][CPT]
   double* d_mass;           // per-cell outputs of MODE_DIAG (global cell index)
   double* d_mom;
   double* d_ek;
@@ -492,9 +542,46 @@ __device__ __noinline__ void at_kick_tail(uint32_t i, uint32_t step, uint32_t k0
   at_kick(i, step, k0, k1, scale, dv);
 }
 
+// Maxwell-Boltzmann draw of a cell with nc >= 2 particles (sec. 3.6):
+// E_hat ~ Gamma(3 (nc - 1) / 2, kT) by Marsaglia and Tsang's sampler.
+// The numbers of an attempt depend on (cell, step, attempt) only, so those of
+// attempts 0 and 1 are drawn before N_c is known: the normal g and lu =
+// log U, or -inf where the squeeze (which needs no N_c either) accepts.
+// gamma_first2 decides these two attempts as gamma_mt would; it returns -1
+// when both are rejected (about one cell in 10^3), and gamma_mt from attempt
+// 2 finishes the draw.
+constexpr int GPRE = 2;  // attempts drawn ahead
+
+__device__ inline double gamma_first2(uint32_t nc, const double g[GPRE], const double lu[GPRE],
+                                      double theta) {
+  const double k = 1.5 * (double)(nc - 1u);
+  const double d = k - 1.0 / 3.0;
+  const double c = 1.0 / sqrt(9.0 * d);
+#pragma unroll
+  for (int j = 0; j < GPRE; ++j) {
+    const double t = 1.0 + c * g[j];
+    const double V = t * t * t;
+    if (t > 0.0 && (lu[j] == -INFINITY || gamma_full_log(g[j], V, lu[j], d))) return d * V * theta;
+  }
+  return -1.0;
+}
+
+__device__ inline double gamma_finish(uint32_t nc, uint32_t cell, uint32_t step, const Box& B,
+                                      uint32_t& err) {
+  bool cap = false;
+  const double e = gamma_mt(1.5 * (double)(nc - 1u), cell, step, B.k0, B.k1, B.kT, cap, (uint32_t)GPRE);
+  if (cap) err |= ERR_GAMMA_CAP;
+  return e;
+}
+
 // One block per tile. In the per-cell phases thread l < CPT works for cell
-// l: it draws the axis, forms u, xi and the rotation. The thermostat's Gamma
-// draws come from k_draw, launched just before.
+// l: it draws the axis (and the numbers of the first attempts of the
+// thermostat's Gamma draw) while the tile's particles load, and once the cell
+// sums are in, decides the Gamma draw and forms u, xi and the rotation. The
+// particles of the rare cells whose draw needs a third attempt are left out
+// of the main pass: once it is done and the registers holding the tile are
+// free, their cell threads finish the draw, and those particles are read
+// again from the input slab, rotated and scattered one by one.
 // ATR: the Andersen-thermostat rule (eq. 4) instead of the rotation; every
 // particle draws a random velocity dv in the gather, the cell sums gain
 // sum m dv, and the update is v <- (u + dv) - sum m dv / M.
@@ -519,6 +606,11 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
   constexpr bool SCAT = MODE == MODE_BIN || MODE == MODE_COLLIDE_SCATTER;
   constexpr bool EK = THERMO || MODE == MODE_DIAG;
   constexpr bool AT = ATR && COLL && MODE != MODE_DIAG;
+  // 64-cell step kernels of the SRD rule keep the register-resident
+  // particles' position records in LDS (loaded there directly) instead of
+  // registers: positions are needed only after the rotation, and the
+  // registers go to occupancy (the AT rule's kicks already fill its LDS)
+  constexpr bool LPOS = (MODE == MODE_COLLIDE || MODE == MODE_COLLIDE_SCATTER) && CPT == 64 && !ATR;
   constexpr int NL = AC::NL;
   constexpr int TQ = tq_for(CPT);
   constexpr int TREG = TT * TQ;
@@ -534,6 +626,13 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
   __shared__ double s_u[3][CC];
   __shared__ double s_ax[3][CC];  // per cell: the rotation axis (SRD) or the mean kick (AT)
   __shared__ double s_xi[THERMO && MODE != MODE_DIAG ? CC : 1];
+  // thermostat: attempts 0 and 1 of the cell's Gamma draw, normal g and log U
+  // (-inf where the squeeze accepts), drawn before N_c is known; cells whose
+  // draw is not decided by them (pending) and whether the block has any
+  __shared__ double s_gam[THERMO ? 2 * GPRE : 1][THERMO ? CC : 1];
+  __shared__ double s_ehat[THERMO ? CC : 1];
+  __shared__ uint32_t s_pend[THERMO ? CC : 1];
+  __shared__ uint32_t s_anyp;
   __shared__ uint32_t s_bincnt[27];
   __shared__ uint32_t s_base[27];
   __shared__ uint32_t s_btile[27];
@@ -546,7 +645,6 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
   const uint32_t cap = A.S.cap;
   int t3[3];
   tile_coords(B, T - B.tile0, t3);
-  const bool real_tile = T - B.tile0 < B.ntiles;  // else padding between boxes (empty)
   // this box's shifts, copied once: binning the input (or the output in
   // MODE_BIN), and binning the next step's input (MODE_COLLIDE_SCATTER)
   const ShiftEntry sh0 = A.sh[bx];
@@ -559,7 +657,10 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
   // before the first barrier, so their latencies overlap. A block quits
   // after it if an earlier launch of this call overflowed a slab (launches
   // of the failing one itself run to the end, so its counts are complete).
-  if (tid == 0) s_quit = (A.status[1] != 0u && A.status[2] < A.seq) ? 1u : 0u;
+  if (tid == 0) {
+    s_quit = (A.status[1] != 0u && A.status[2] < A.seq) ? 1u : 0u;
+    if constexpr (THERMO) s_anyp = 0u;
+  }
   const uint32_t cnt = min(A.cnt_in[T], cap);
   const uint32_t nreg = min(cnt, (uint32_t)TREG);
   const size_t tbase = (size_t)T * cap;
@@ -590,16 +691,58 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
     uint32_t l3[3];
     local_coords(B, l, l3);
     const int g[3] = {t3[0] * B.td[0] + (int)l3[0], t3[1] * B.td[1] + (int)l3[1], t3[2] * B.td[2] + (int)l3[2]};
-    ok = real_tile && l < (uint32_t)CPT && l3[2] < (uint32_t)B.td[2] && g[0] < B.n[0] && g[1] < B.n[1] &&
+    ok = l < (uint32_t)CPT && l3[2] < (uint32_t)B.td[2] && g[0] < B.n[0] && g[1] < B.n[1] &&
          g[2] < B.n[2];
     return ok ? cell_index(B, g) : 0u;
   };
+
+  // cell thread: the rotation axis and the numbers of the first attempts of
+  // the thermostat draw need only (cell, step), so they are drawn while the
+  // tile's count is in flight, before the gather (drawn after the gather is
+  // issued, they would be scheduled against the registers the loads fill);
+  // they wait in LDS. With tiles of at most 128 cells the thermostat's lanes
+  // (gthr, cell tid - CPT) are the waves after the cell threads' own, so the
+  // two chains run side by side on different waves.
+  const bool cthr = COLL && tid < (uint32_t)CPT;
+  bool cok = false;
+  const uint32_t gcell = cthr ? cell_of(tid, cok) : 0u;
+  constexpr bool GSPLIT = 2 * CPT <= TT;
+  const uint32_t gl = GSPLIT ? tid - (uint32_t)CPT : tid;  // cell of a thermostat lane
+  const bool gthr = THERMO && COLL && (GSPLIT ? (tid >= (uint32_t)CPT && tid < 2u * CPT) : cthr);
+  bool gok = false;
+  const uint32_t ggcell = gthr ? cell_of(gl, gok) : 0u;
+  if constexpr (COLL) {
+    if (cthr && !AT) {
+      double n[3] = {0.0, 0.0, 0.0};
+      if (cok) cell_axis(gcell, A.step, B.k0, B.k1, n);
+      s_ax[0][tid] = n[0];
+      s_ax[1][tid] = n[1];
+      s_ax[2][tid] = n[2];
+    }
+    if constexpr (THERMO) {
+      if (gthr) {
+#pragma unroll
+        for (int j = 0; j < GPRE; ++j) {
+          double g = 0.0, lu = -INFINITY;
+          if (gok) {
+            double u2;
+            gamma_numbers(ggcell, A.step, (uint32_t)j, B.k0, B.k1, g, u2);
+            if (!gamma_squeeze(g, u2)) lu = log(u2);
+          }
+          s_gam[2 * j][gl] = g;
+          s_gam[2 * j + 1][gl] = lu;
+        }
+      }
+    }
+  }
 
   // ---- gather this tile's particles (register-resident part)
   VT v[TQ][3];
   uint32_t tg[TQ];
   uint32_t lcs[TQ];
-  Pos<FORM> r[TQ];
+  Pos<FORM> r[TQ];                             // positions in registers (not with LPOS)
+  __shared__ uint4 s_pos[LPOS ? TREG : 1];     // LPOS: position records, slot k at k
+  double zq[LPOS && FORM == 0 ? TQ : 1];       // LPOS, FP64 form: z of each position
   // AT rule: each register-resident particle's kick, drawn once and used by
   // the cell sums and the update, waits in LDS (in registers it would hold 6
   // VGPRs per particle slot through the whole kernel and cut occupancy)
@@ -613,7 +756,16 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
     lcs[q] = 0u;
     tg[q] = 0u;
     if (k < nreg) {
-      load_part<FORM>(In, k, r[q], v[q], tg[q]);
+      if constexpr (LPOS) {
+        stage_pos<FORM>(In, k, &s_pos[(uint32_t)(q * TT) + (tid & ~63u)]);
+        double z;
+        load_vt_z<FORM>(In, k, v[q], tg[q], z);
+        if constexpr (FORM == 0) zq[q] = z;
+      } else if constexpr (MODE == MODE_DIAG) {
+        load_vt<FORM>(In, k, v[q], tg[q]);  // the cell sums need no position
+      } else {
+        load_part<FORM>(In, k, r[q], v[q], tg[q]);
+      }
       if constexpr (COLL) lcs[q] = (uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1);
     }
   }
@@ -628,23 +780,6 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
       }
   }
 
-  // cell thread: the rotation axis needs only (cell, step), so it is drawn
-  // while the gathers are in flight; it waits in s_ax
-  const bool cthr = COLL && tid < (uint32_t)CPT;
-  bool cok = false;
-  const uint32_t gcell = cthr ? cell_of(tid, cok) : 0u;
-  double ehat = -1.0;
-  if constexpr (THERMO)
-    if (cthr) ehat = A.ehat[(size_t)T * CPT + tid];
-  if constexpr (COLL) {
-    if (cthr && !AT) {
-      double n[3] = {0.0, 0.0, 0.0};
-      if (cok) cell_axis(gcell, A.step, B.k0, B.k1, n);
-      s_ax[0][tid] = n[0];
-      s_ax[1][tid] = n[1];
-      s_ax[2][tid] = n[2];
-    }
-  }
   __syncthreads();
   if (s_quit) return;
   if (SCAT && tid == 0 && A.cnt_clear) A.cnt_clear[T] = 0u;
@@ -667,7 +802,7 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
     for (int q = 0; q < TQ; ++q) {
       const uint32_t k = tid + (uint32_t)(q * TT);
       info[q] = 0u;
-      if (k < nreg) {
+      if (k < nreg && !(lcs[q] & LC_PEND)) {
         int c[3];
         r[q].cell3(B, sd, sd32, c);
         uint32_t lcell;
@@ -682,7 +817,7 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
     for (int q = 0; q < TQ; ++q) {
       const uint32_t k = tid + (uint32_t)(q * TT);
-      if (k < nreg) {
+      if (k < nreg && !(lcs[q] & LC_PEND)) {
         const uint32_t b = (info[q] >> 8) & 31u;
         uint32_t dt, slot;
         if (b < 27u) {
@@ -768,6 +903,30 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
       else return (double)nc * B.mass;
     };
     const uint32_t nc = cthr && cok ? s_cnt[tid] : 0u;
+    // the cell's Gamma draw, now that N_c is known (on its own waves beside
+    // the centre-of-mass velocities when the tile allows)
+    if constexpr (THERMO) {
+      if (gthr) {
+        const uint32_t ng = s_cnt[gl];  // 0 for a cell outside the box
+        uint32_t pend = 0u;
+        double eh = -1.0;
+        if (ng >= 2u) {
+          double g[GPRE], lu[GPRE];
+#pragma unroll
+          for (int j = 0; j < GPRE; ++j) {
+            g[j] = s_gam[2 * j][gl];
+            lu[j] = s_gam[2 * j + 1][gl];
+          }
+          eh = gamma_first2(ng, g, lu, B.kT);
+          if (eh < 0.0) {
+            pend = 1u;
+            s_anyp = 1u;
+          }
+        }
+        s_ehat[gl] = eh;
+        s_pend[gl] = pend;
+      }
+    }
     if (cthr) {
       double u[3] = {0.0, 0.0, 0.0};
       if (nc > 0u) {
@@ -810,8 +969,14 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
     // ---- per cell: xi (cell threads)
     if (cthr) {
       double xi = 1.0;
-      if constexpr (THERMO)
+      if constexpr (THERMO) {
+        // a pending draw is finished here when no particle follows (MODE_DIAG),
+        // else after the main pass
+        double ehat = s_ehat[tid];
+        if constexpr (MODE == MODE_DIAG)
+          if (s_pend[tid]) ehat = gamma_finish(nc, gcell, A.step, B, err);
         if (nc >= 2u && ek > 0.0) xi = sqrt(ehat / ek);
+      }
       if constexpr (MODE == MODE_DIAG) {
         const double n[3] = {nc > 0u ? s_ax[0][tid] : 0.0, nc > 0u ? s_ax[1][tid] : 0.0,
                              nc > 0u ? s_ax[2][tid] : 0.0};
@@ -833,6 +998,15 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
 
     if constexpr (MODE != MODE_DIAG) {
       __syncthreads();
+      // particles of pending cells wait for the pass after the main one
+      const bool anyp = THERMO && s_anyp != 0u;
+      if constexpr (THERMO) {
+        if (anyp) {
+#pragma unroll
+          for (int q = 0; q < TQ; ++q)
+            if (tid + (uint32_t)(q * TT) < nreg && s_pend[lcs[q]]) lcs[q] |= LC_PEND;
+        }
+      }
       // ---- rotate (Alg. 1): v <- u + xi R(alpha, n) (v - u) in FP64, the
       // rotation by Rodrigues' formula from the axis, rounded once to the
       // storage precision
@@ -856,10 +1030,31 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
         for (int k = 0; k < 3; ++k) w[k] = (VT)(u[k] + r[k]);
       };
+      // the staged position records have arrived (each lane reads the slot
+      // its own wave filled)
+      if constexpr (LPOS) __builtin_amdgcn_s_waitcnt(0);
+      // LPOS scatter: per particle the local cell in the destination (bits
+      // 0-7), bin (8-12) and rank within the bin (13-31), taken in the rotate
+      // loop while the streamed position is in registers
+      uint32_t info[LPOS ? TQ : 1];
+      // a particle rotated outside the register-resident pass: stored in place
+      // (MODE_COLLIDE), or streamed, binned and placed with one atomic
+      auto finish_one = [&](uint32_t k, uint32_t lc, Pos<FORM>& rr, VT ww[3], uint32_t tag) {
+        if constexpr (MODE == MODE_COLLIDE) {
+          const Particles Out = tile_view<FORM>(A.out, tbase);
+          store_part<FORM>(Out, k, rr, ww, tag);
+          st(Out.lc, k, (uint8_t)lc);
+          if (A.eslot_out) note_slot(A.eslot_out, B, tag, tbase + k);
+        } else {
+          if (streamed(B, tag)) rr.stream(B, ww, err);
+          scatter_one(rr, sh1.s, sh1.s32, ww, tag);
+        }
+      };
 #pragma unroll
       for (int q = 0; q < TQ; ++q) {
         const uint32_t k = tid + (uint32_t)(q * TT);
-        if (k < nreg) {
+        if constexpr (LPOS) info[q] = 0u;
+        if (k < nreg && !(lcs[q] & LC_PEND)) {
           VT w[3];
           double kv[3] = {0.0, 0.0, 0.0};
           if constexpr (AT) {
@@ -870,7 +1065,26 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
           v[q][0] = w[0];
           v[q][1] = w[1];
           v[q][2] = w[2];
-          if constexpr (MODE == MODE_COLLIDE) {
+          if constexpr (LPOS) {
+            Pos<FORM> rr;
+            pos_from_lds(s_pos[k], FORM == 0 ? zq[q] : 0.0, rr);
+            if constexpr (MODE == MODE_COLLIDE) {
+              const Particles Out = tile_view<FORM>(A.out, tbase);
+              store_part<FORM>(Out, k, rr, v[q], tg[q]);
+              st(Out.lc, k, (uint8_t)lcs[q]);
+              if (A.eslot_out) note_slot(A.eslot_out, B, tg[q], tbase + k);
+            } else {
+              if (streamed(B, tg[q])) rr.stream(B, v[q], err);
+              int c[3];
+              rr.cell3(B, sh1.s, sh1.s32, c);
+              uint32_t lcell;
+              const uint32_t b = dest_bin(B, t3, c, lcell);
+              const uint32_t rank = b < 27u ? atomicAdd(&s_bincnt[b], 1u) : 0u;
+              info[q] = lcell | (b << 8) | (rank << 13);
+              s_pos[k] = pos_to_lds(rr);
+              if constexpr (FORM == 0) zq[q] = rr.x[2];
+            }
+          } else if constexpr (MODE == MODE_COLLIDE) {
             const Particles Out = tile_view<FORM>(A.out, tbase);
             store_part<FORM>(Out, k, r[q], v[q], tg[q]);
             st(Out.lc, k, (uint8_t)lcs[q]);
@@ -880,151 +1094,81 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
           }
         }
       }
-      if constexpr (MODE == MODE_COLLIDE_SCATTER) scatter(sh1.s, sh1.s32, v);
+      if constexpr (MODE == MODE_COLLIDE_SCATTER) {
+        if constexpr (LPOS) {
+          // reserve the destination slots (one global atomic per bin), then
+          // write each particle with its streamed position from LDS
+          __syncthreads();
+          if (tid < 27u && s_bincnt[tid] > 0u) s_base[tid] = atomicAdd(&A.cnt_out[s_btile[tid]], s_bincnt[tid]);
+          __syncthreads();
+#pragma unroll
+          for (int q = 0; q < TQ; ++q) {
+            const uint32_t k = tid + (uint32_t)(q * TT);
+            if (k < nreg && !(lcs[q] & LC_PEND)) {
+              Pos<FORM> rr;
+              pos_from_lds(s_pos[k], FORM == 0 ? zq[q] : 0.0, rr);
+              const uint32_t b = (info[q] >> 8) & 31u;
+              uint32_t dt, slot;
+              if (b < 27u) {
+                dt = s_btile[b];
+                slot = s_base[b] + (info[q] >> 13);
+              } else {
+                int c[3];
+                rr.cell3(B, sh1.s, sh1.s32, c);
+                dt = B.tile0 + tile_index(B, c);
+                slot = atomicAdd(&A.cnt_out[dt], 1u);
+              }
+              if (slot < cap) put((size_t)dt * cap + slot, v[q], tg[q], rr, info[q] & 255u);
+              else overflow();
+            }
+          }
+        } else {
+          scatter(sh1.s, sh1.s32, v);
+        }
+      }
       for (uint32_t k = TREG + tid; k < cnt; k += TT) {
         VT vv[3], ww[3];
         uint32_t tag;
         Pos<FORM> rr;
-        load_part<FORM>(In, k, rr, vv, tag);
         const uint32_t lc = (uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1);
+        if (THERMO && anyp && s_pend[lc]) continue;
+        load_part<FORM>(In, k, rr, vv, tag);
         double kv[3] = {0.0, 0.0, 0.0};
         if constexpr (AT) at_kick_tail(tag - B.tag0, A.step, B.k0, B.k1, sqrt(B.kT / mass_of(tag)), kv);
         rotate(lc, vv, ww, kv);
-        if constexpr (MODE == MODE_COLLIDE) {
-          const Particles Out = tile_view<FORM>(A.out, tbase);
-          store_part<FORM>(Out, k, rr, ww, tag);
-          st(Out.lc, k, (uint8_t)lc);
-          if (A.eslot_out) note_slot(A.eslot_out, B, tag, tbase + k);
-        } else {
-          if (streamed(B, tag)) rr.stream(B, ww, err);
-          scatter_one(rr, sh1.s, sh1.s32, ww, tag);
+        finish_one(k, lc, rr, ww, tag);
+      }
+
+      // ---- pending cells: the cell threads finish their draws (the tile's
+      // registers are free now), then the particles of those cells are read
+      // again, rotated and placed one by one
+      if constexpr (THERMO) {
+        if (anyp) {
+          if (cthr && s_pend[tid]) {
+            bool ok;
+            const uint32_t gc = cell_of(tid, ok);
+            const double e = gamma_finish(s_cnt[tid], gc, A.step, B, err);
+            const double ekc = 0.5 * AC::value(s_acc[RE][tid], s_acc[RE + NL - 1][tid]);
+            s_xi[tid] = ekc > 0.0 ? sqrt(e / ekc) : 1.0;
+          }
+          __syncthreads();
+          for (uint32_t k = tid; k < cnt; k += TT) {
+            const uint32_t lc = (uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1);
+            if (!s_pend[lc]) continue;
+            VT vv[3], ww[3];
+            uint32_t tag;
+            Pos<FORM> rr;
+            load_part<FORM>(In, k, rr, vv, tag);
+            const double kv[3] = {0.0, 0.0, 0.0};
+            rotate(lc, vv, ww, kv);
+            finish_one(k, lc, rr, ww, tag);
+          }
         }
       }
     }
   }
   if (bad) err |= ERR_FIXED_RANGE;
   if (err) atomicOr(&A.status[0], err);
-}
-
-// Maxwell-Boltzmann draws of one collision (sec. 3.6). A block of DT = 256
-// threads takes 256 / CPT consecutive tiles (all of one box), one thread per
-// cell. It counts the occupancy N_c of each cell from the local-cell bytes of
-// the tiles' slabs, then runs Marsaglia and Tsang's sampler for
-// E_hat ~ Gamma(3 (N_c - 1) / 2, kT) on every cell with N_c >= 2 in two
-// stages: attempt 0 up to the squeeze on every thread; then the few cells
-// that need the logarithmic test or another attempt (a few per cent) are
-// compacted through LDS onto the first threads, which finish them in attempt
-// order. The result is the sequential sampler's either way. Output
-// ehat[T * CPT + l]; -1 for a cell with fewer than two particles.
-constexpr int DT = 256;
-
-template <int CPT>
-__global__ __launch_bounds__(DT) void k_draw(Particles P, Slabs S, const uint32_t* __restrict__ cnt_in,
-                                             uint32_t step, double* __restrict__ ehat,
-                                             uint32_t* status, uint32_t seq) {
-  constexpr int TPB = DT / CPT;  // tiles per block (boxes start at multiples of 4 tiles)
-  __shared__ uint32_t s_n[DT];
-  __shared__ uint32_t s_qn;
-  __shared__ uint32_t s_qc[DT];  // pending: global cell index
-  __shared__ uint32_t s_qs[DT];  // pending: slot (thread), "rejected" flag in bit 31
-  __shared__ double s_qg[DT], s_qV[DT], s_qu[DT];
-  __shared__ uint32_t s_quit;
-  const uint32_t tid = threadIdx.x;
-  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
-  const uint32_t bx = S.tile_box[min(b * TPB, S.ntiles - 1u)];
-  const Box B = S.boxes[bx];
-  if (tid == 0) {
-    s_quit = (status[1] != 0u && status[2] < seq) ? 1u : 0u;
-    s_qn = 0u;
-  }
-  s_n[tid] = 0u;
-
-  // occupancies: the tiles' counts and the first local-cell bytes of their
-  // slabs (one 32-bit word of 4 bytes per thread; cap is a multiple of 4) are
-  // loaded together, and the bytes at or beyond a tile's count are dropped
-  // once the count is known
-  const uint32_t nw = min((uint32_t)DT, S.cap / 4u);
-  uint32_t cnt[TPB];
-  uint32_t v[TPB];
-#pragma unroll
-  for (int i = 0; i < TPB; ++i) {
-    const uint32_t T = b * TPB + i;
-    cnt[i] = T < S.ntiles ? min(cnt_in[T], S.cap) : 0u;
-    const uint32_t* lw = reinterpret_cast<const uint32_t*>(P.lc + (size_t)T * S.cap);
-    v[i] = (T < S.ntiles && tid < nw) ? ld(lw, tid) : 0u;
-  }
-  // this thread's cell
-  const uint32_t T = b * TPB + tid / (uint32_t)CPT, l = tid % (uint32_t)CPT;
-  const size_t slot = (size_t)T * CPT + l;
-  __syncthreads();
-  if (s_quit) return;
-#pragma unroll
-  for (int i = 0; i < TPB; ++i) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (tid < nw && 4u * tid + (uint32_t)j < cnt[i])
-        atomicAdd(&s_n[i * CPT + ((v[i] >> (8 * j)) & (uint32_t)(CPT - 1))], 1u);
-    const uint8_t* lc = P.lc + (size_t)(b * TPB + i) * S.cap;
-    for (uint32_t k = 4u * nw + tid; k < cnt[i]; k += DT)
-      atomicAdd(&s_n[i * CPT + ((uint32_t)ld(lc, k) & (uint32_t)(CPT - 1))], 1u);
-  }
-  __syncthreads();
-
-  const uint32_t Tl = T - B.tile0;  // tile within the box (pad tiles: >= B.ntiles)
-  int t3[3];
-  tile_coords(B, Tl, t3);
-  uint32_t l3[3];
-  local_coords(B, l, l3);
-  const int g3[3] = {t3[0] * B.td[0] + (int)l3[0], t3[1] * B.td[1] + (int)l3[1], t3[2] * B.td[2] + (int)l3[2]};
-  const bool ok = T < S.ntiles && Tl < B.ntiles && l3[2] < (uint32_t)B.td[2] && g3[0] < B.n[0] &&
-                  g3[1] < B.n[1] && g3[2] < B.n[2];
-  const uint32_t nc = ok ? s_n[tid] : 0u;
-  const uint32_t gc = ok ? cell_index(B, g3) : 0u;
-  double e = -1.0, g = 0.0, V = 0.0, u2 = 0.0;
-  int r = GQ_ACCEPT;
-  if (nc >= 2u) {
-    const double d = 1.5 * (double)(nc - 1u) - 1.0 / 3.0;
-    const double c = 1.0 / sqrt(9.0 * d);
-    gamma_numbers(gc, step, 0u, B.k0, B.k1, g, u2);
-    r = gamma_decide(g, u2, c, V);
-    if (r == GQ_ACCEPT) e = d * V * B.kT;
-  }
-  const bool pend = nc >= 2u && r != GQ_ACCEPT;
-  // compact the pending cells onto the first threads: one LDS atomic per wave
-  const unsigned long long m = __ballot(pend);
-  if (m) {
-    const uint32_t lane = tid & 63u;
-    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-    const uint32_t leader = (uint32_t)__ffsll((long long)m) - 1u;
-    uint32_t base = 0u;
-    if (lane == leader) base = atomicAdd(&s_qn, (uint32_t)__popcll(m));
-    base = (uint32_t)__builtin_amdgcn_readlane((int)base, (int)leader);
-    if (pend) {
-      const uint32_t i = base + below;
-      s_qs[i] = tid | (r == GQ_REJECT ? 0x80000000u : 0u);
-      s_qc[i] = gc;
-      s_qg[i] = g;
-      s_qV[i] = V;
-      s_qu[i] = u2;
-    }
-  }
-  if (ok && !pend) ehat[slot] = e;
-  __syncthreads();
-  // finish the pending cells in attempt order: the full test of attempt 0,
-  // then attempts 1, 2, ... as the sequential sampler would
-  if (tid < s_qn) {
-    const uint32_t q = s_qs[tid] & 0x7FFFFFFFu;
-    const bool rejected = (s_qs[tid] >> 31) != 0u;
-    const uint32_t nq = s_n[q];
-    const double k = 1.5 * (double)(nq - 1u);
-    const double d = k - 1.0 / 3.0;
-    double res;
-    bool cap = false;
-    if (!rejected && gamma_full(s_qg[tid], s_qV[tid], s_qu[tid], d)) res = d * s_qV[tid] * B.kT;
-    else res = gamma_mt(k, s_qc[tid], step, B.k0, B.k1, B.kT, cap, 1u);
-    ehat[(size_t)(b * TPB + q / (uint32_t)CPT) * CPT + q % (uint32_t)CPT] = res;
-    if (cap) atomicOr(&status[0], ERR_GAMMA_CAP);
-  }
 }
 
 // ------------------------------------------------- elementwise over slabs

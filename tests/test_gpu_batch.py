@@ -12,11 +12,11 @@ from oracle import fp32form, srd
 pytestmark = pytest.mark.gpu
 
 # sizes that exercise every tile shape: a box smaller than a tile along an
-# axis, densities on both sides of the 64-/128-cell tile threshold, partial
-# tiles at the far faces
+# axis, densities on both sides of the 64-/128-cell tile threshold (3.5),
+# partial tiles at the far faces
 BOXES = [
     dict(n_cells=(9, 7, 5), density=8.0, kT=1.0, seed=11),
-    dict(n_cells=(3, 10, 12), density=5.5, kT=0.7, seed=12),
+    dict(n_cells=(3, 10, 12), density=2.5, kT=0.7, seed=12),
     dict(n_cells=(16, 16, 16), density=6.5, kT=1.6, seed=13),
     dict(n_cells=(5, 5, 5), density=9.0, kT=1.2, seed=14, a=0.8),
 ]

@@ -27,7 +27,7 @@ def _lib():
 # box, particles in one crowded cell, particles spread over the box, the
 # tile shape the density rule picks and the register-resident part per tile
 CROWD = {"cpt64": ((4, 4, 4), 3000, 500, (4, 4, 2), 768),
-         "cpt128": ((8, 8, 8), 1100, 2000, (8, 4, 4), 1024)}
+         "cpt128": ((8, 8, 8), 1100, 600, (8, 4, 4), 1024)}
 
 
 def _crowd(layout, seed):

@@ -408,12 +408,16 @@ def test_full_size_benchmark_fluid_fp32_each_step():
             gpos, gvel = gpos1, gvel1
 
 
-@pytest.mark.parametrize("rho,n_cells", [(2.5, (17, 9, 10)), (12.5, (9, 10, 7))])
+TILE_SHAPES = {1.2: (8, 8, 4), 2.5: (8, 4, 4), 12.5: (4, 4, 2)}
+
+
+@pytest.mark.parametrize("rho,n_cells", [(1.2, (19, 11, 10)), (2.5, (17, 9, 10)), (12.5, (9, 10, 7))])
 def test_extreme_tile_shapes(rho, n_cells):
-    """The sparsest tile shape (8x8x4 cells, 256-cell kernels, density below
-    3.5) and the densest (4x4x2, density 11 and up), each with partial tiles
-    on every axis: three thermostatted FP64 steps against the oracle, and one
-    FP32 step from a shared state against its emulation."""
+    """The sparse tile shapes (8x8x4 cells, 256-cell kernels, below density
+    1.75; 8x4x4, 128-cell kernels, below 3.5) and the densest (4x4x2, density
+    11 and up), each with partial tiles on every axis: three thermostatted
+    FP64 steps against the oracle, and one FP32 step from a shared state
+    against its emulation."""
     banner(f"tile shapes rho={rho} {n_cells}")
     p = srd.Params(n_cells, seed=81, thermostat=True)
     pos, vel = workloads.fluid(n_cells, rho, seed=82)
@@ -423,7 +427,7 @@ def test_extreme_tile_shapes(rho, n_cells):
         s.step(3)
         gpos, gvel = s.get_state()
         gcells, gcounts = s.get_cells()
-    assert tile == ((8, 8, 4) if rho < 3.5 else (4, 4, 2))
+    assert tile == TILE_SHAPES[rho]
     opos, ovel, info = srd.run(pos, vel, mass, p, 0, 3)
     assert np.array_equal(gcells, info["cell"])
     assert np.array_equal(gcounts, info["count"])
