@@ -186,6 +186,26 @@ mpcd_status mpcd_collide(mpcd_ctx ctx);
  * prepared. Results never depend on how a run is split into calls. */
 mpcd_status mpcd_step(mpcd_ctx ctx, int64_t nsteps);
 
+/* For callers that cannot allocate (tight serving loops, harnesses that
+ * forbid device allocation): mpcd_step without any allocation, the same
+ * steps bit for bit. Differences from mpcd_step:
+ *  - (nsteps + 1) * n_boxes must not exceed MPCD_NOALLOC_MAX_SHIFTS, else
+ *    MPCD_EINVAL and nothing runs;
+ *  - the grid shifts of the call are staged in a table of the library (one
+ *    per GPU, MPCD_NOALLOC_MAX_SHIFTS entries of 40 bytes = 320 KiB, held
+ *    until the process ends) instead of the context's own: calls on one GPU
+ *    whose work overlaps (contexts on different streams or host threads)
+ *    race on it and must be serialised by the caller;
+ *  - kernel timing (mpcd_profile_enable) records nothing during the call;
+ *  - a full particle slab cannot be enlarged: the call returns MPCD_ENOMEM
+ *    with the context rolled back to the input of the launch that
+ *    overflowed -- the state before the call, or step s streamed and binned
+ *    but not yet collided (mpcd_get_step returns s; mpcd_collide completes
+ *    it, after which mpcd_step, which enlarges slabs, can continue).
+ * Synchronises at its end, as mpcd_step does. */
+#define MPCD_NOALLOC_MAX_SHIFTS 8192
+mpcd_status mpcd_step_noalloc(mpcd_ctx ctx, int64_t nsteps);
+
 /* State of the embedded particles only (tags n_solvent .. n_total - 1, box 0):
  * pos, vel are n_embedded x 3 doubles, row i = embedded particle i as given to
  * mpcd_create. get: any state; synchronises. set: only between steps (after

@@ -21,6 +21,7 @@ FP64, FP32 = 0, 1
 SRD, AT = 0, 1
 FLAG_TIGHT_SLABS = 1
 FLAG_MD_SOLUTE = 2
+NOALLOC_MAX_SHIFTS = 8192
 STATUS_NAMES = {0: "MPCD_OK", 1: "MPCD_EINVAL", 2: "MPCD_ENOMEM", 3: "MPCD_EHIP",
                 4: "MPCD_ERANGE", 5: "MPCD_ESTATE"}
 
@@ -76,6 +77,7 @@ def load():
         "mpcd_bin": (st, [_P]),
         "mpcd_collide": (st, [_P]),
         "mpcd_step": (st, [_P, ctypes.c_int64]),
+        "mpcd_step_noalloc": (st, [_P, ctypes.c_int64]),
         "mpcd_get_state": (st, [_P, _P, _P, ctypes.c_int32]),
         "mpcd_get_cells": (st, [_P, _P, _P, ctypes.c_int32]),
         "mpcd_get_cell_props": (st, [_P, _P, _P, _P, ctypes.c_int32]),
@@ -189,6 +191,10 @@ class Sim:
 
     def step(self, nsteps=1):
         _check(load().mpcd_step(self._ctx, int(nsteps)))
+
+    def step_noalloc(self, nsteps=1):
+        """mpcd_step_noalloc: the same steps without any allocation."""
+        _check(load().mpcd_step_noalloc(self._ctx, int(nsteps)))
 
     def sync(self):
         _check(load().mpcd_sync(self._ctx))

@@ -18,6 +18,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -106,6 +107,9 @@ struct mpcd_ctx_s {
 
   ShiftEntry* shifts = nullptr;    // grid shifts of steps shift_n0 .., [step][box]
   uint64_t shift_cap = 0, shift_n0 = 0, shift_count = 0;
+  const ShiftEntry* shift_view = nullptr;  // the table the next launches read (shifts, or
+                                           // the library's static one in mpcd_step_noalloc)
+  int device = 0;                  // the device current at create
 
   uint64_t step = 0;
   uint64_t last_bin_step = 0;
@@ -188,13 +192,14 @@ mpcd_status ensure_shifts(mpcd_ctx c, uint64_t n0, uint64_t count) {
   k_shifts<<<blocks_for(need, 256), 256, 0, c->stream>>>(c->S.boxes, c->nbox, (uint32_t)n0,
                                                           (uint32_t)count, c->p.grid_shift, c->shifts);
   HIP_TRY(hipGetLastError());
+  c->shift_view = c->shifts;
   c->shift_n0 = n0;
   c->shift_count = count;
   return MPCD_OK;
 }
 
 const ShiftEntry* shift_at(const mpcd_ctx c, uint64_t n) {
-  return c->shifts + (n - c->shift_n0) * c->nbox;
+  return c->shift_view + (n - c->shift_n0) * c->nbox;
 }
 
 // --- profiling helpers
@@ -651,6 +656,8 @@ mpcd_status create_impl(int32_t nbox, const mpcd_params* params, const int64_t* 
   c->ncells = cell;
   c->S.ntiles = NT;
 
+  if (hipGetDevice(&c->device) != hipSuccess)
+    return cleanup(fail(MPCD_EHIP, "hipGetDevice failed (no usable GPU?)"));
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
   } else {
@@ -851,6 +858,49 @@ mpcd_status read_totals(mpcd_ctx c, std::vector<long long>& h) {
   return MPCD_OK;
 }
 
+// ------------------------------------------- allocation-free stepping
+// mpcd_step_noalloc stages the grid shifts of its call in this library-wide
+// table instead of the context's own (which mpcd_step allocates on demand).
+// Every device the library runs on holds its own copy until the process
+// ends; host code reaches a copy through the device address that
+// hipGetSymbolAddress returns on that device, never through the name.
+static_assert(sizeof(ShiftEntry) == 40, "the header states 40 bytes per grid-shift entry");
+static __device__ __align__(256) ShiftEntry scratch[MPCD_NOALLOC_MAX_SHIFTS];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+ShiftEntry* g_scratch_ptr[kMaxDevices] = {};  // per device: scratch's device address
+
+// The address of scratch on device dev, which must be current: looked up on
+// the first call on that device, kept after.
+mpcd_status scratch_on(int dev, ShiftEntry** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(MPCD_EHIP, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* q = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !q)
+      return fail(MPCD_EHIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<ShiftEntry*>(q);
+  }
+  *out = g_scratch_ptr[dev];
+  return MPCD_OK;
+}
+
+// Makes `dev` the current device for a scope and restores the caller's.
+struct DeviceScope {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit DeviceScope(int dev) {
+    err = hipGetDevice(&prev);
+    if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+  }
+  ~DeviceScope() {
+    int now = -1;
+    if (prev >= 0 && hipGetDevice(&now) == hipSuccess && now != prev) (void)hipSetDevice(prev);
+  }
+};
+
 }  // namespace
 
 // ======================================================================= ABI
@@ -963,6 +1013,93 @@ mpcd_status mpcd_step(mpcd_ctx c, int64_t nsteps) {
   c->have_bin = true;
   c->phase = Phase::Idle;
   return MPCD_OK;
+}
+
+mpcd_status mpcd_step_noalloc(mpcd_ctx c, int64_t nsteps) {
+  ST_TRY(check_ctx(c));
+  if (nsteps < 0) return fail(MPCD_EINVAL, "nsteps < 0");
+  if (c->phase != Phase::Idle)
+    return fail(MPCD_ESTATE, "mpcd_step_noalloc: expected the state after create or collide");
+  if (nsteps == 0) return MPCD_OK;
+  if (c->step + (uint64_t)nsteps > 0xFFFFFFFFull) return fail(MPCD_ERANGE, "step counter beyond 2^32 - 1");
+  const uint64_t nshift = ((uint64_t)nsteps + 1) * c->nbox;
+  if (nshift > (uint64_t)MPCD_NOALLOC_MAX_SHIFTS)
+    return fail(MPCD_EINVAL,
+                "mpcd_step_noalloc: (nsteps + 1) x n_boxes = %llu grid shifts exceed its table of %d",
+                (unsigned long long)nshift, MPCD_NOALLOC_MAX_SHIFTS);
+  DeviceScope dev(c->device);
+  if (dev.err != hipSuccess) return fail(MPCD_EHIP, "selecting the context's device: %s", hipGetErrorString(dev.err));
+  ShiftEntry* table = nullptr;
+  ST_TRY(scratch_on(c->device, &table));
+  const uint64_t step0 = c->step;
+  k_shifts<<<blocks_for(nshift, 256), 256, 0, c->stream>>>(c->S.boxes, c->nbox, (uint32_t)step0,
+                                                           (uint32_t)nsteps + 1u, c->p.grid_shift, table);
+  HIP_TRY(hipGetLastError());
+  c->shift_view = table;
+  c->shift_n0 = step0;
+  c->shift_count = (uint64_t)nsteps + 1;
+
+  // the launches of mpcd_step (kernel timing off: it would create events)
+  const int cur0 = c->cur, ci0 = c->ci;
+  const bool adopt = c->pre;
+  const int32_t prof = c->prof_every;
+  c->prof_every = 0;
+  mpcd_status st = MPCD_OK;
+  uint32_t seq = 0;
+  if (adopt) {  // the last call left this step's binning ready
+    c->cur = 1 - c->cur;
+    c->ci = (c->ci + 1) % 3;
+    c->pre = false;
+    c->split = false;
+  } else {
+    st = launch_tile(c, Op::BinStream, step0, seq++);
+  }
+  const Op last = (c->p.flags & MPCD_FLAG_MD_SOLUTE) ? Op::Collide : Op::CollideLast;
+  for (int64_t k = 0; k < nsteps && st == MPCD_OK; ++k)
+    st = launch_tile(c, k + 1 < nsteps ? Op::CollideScatter : last, step0 + (uint64_t)k, seq++);
+  c->prof_every = prof;
+  if (st != MPCD_OK) return st;
+  uint32_t h[3];
+  HIP_TRY(hipMemcpyAsync(h, c->status, 12, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (h[1] == 0) {
+    c->step = step0 + (uint64_t)nsteps;
+    c->last_bin_step = c->step - 1;
+    c->have_bin = true;
+    c->phase = Phase::Idle;
+    return MPCD_OK;
+  }
+  // A slab overflowed in launch h[2]; enlarging the slabs would allocate.
+  // Later launches of the call left everything alone and the failing one's
+  // input is intact: roll back to that input -- the state before the call if
+  // it was the first stream + bin, else step s binned and not yet collided --
+  // and clear the counts the failing launch added to.
+  const uint32_t bad = std::min<uint32_t>(h[2], seq - 1u);
+  c->pre = false;
+  c->split = false;
+  if (!adopt && bad == 0) {
+    c->cur = cur0;
+    c->ci = ci0;
+    c->phase = Phase::Idle;
+  } else {
+    const uint64_t k = bad - (adopt ? 0u : 1u);
+    c->cur = (cur0 ^ 1) ^ (int)(k & 1u);
+    c->ci = (int)((ci0 + 1 + k) % 3);
+    c->step = step0 + k;
+    c->phase = Phase::Binned;
+    c->have_bin = true;
+    c->last_bin_step = c->step;
+  }
+  const uint32_t st_reset[2] = {0u, 0xFFFFFFFFu};
+  HIP_TRY(hipMemsetAsync(c->cnt[(c->ci + 1) % 3], 0, (size_t)c->S.ntiles * 4, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->status + 1, st_reset, 8, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return fail(MPCD_ENOMEM,
+              "mpcd_step_noalloc: a particle slab is full at step %llu and enlarging it would "
+              "allocate; the state is %s (mpcd_step enlarges the slabs)",
+              (unsigned long long)(step0 + (adopt ? bad : (bad ? bad - 1u : 0u))),
+              c->phase == Phase::Binned ? "that step binned, awaiting mpcd_collide"
+                                        : "the one before the call");
 }
 
 mpcd_status mpcd_get_state(mpcd_ctx c, double* pos, double* vel, int32_t on_device) {

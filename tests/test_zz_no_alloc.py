@@ -1,0 +1,167 @@
+"""mpcd_step_noalloc, the stepping entry point for callers that cannot
+allocate, against mpcd_step through the C ABI: the same steps bit for bit,
+on calls one after another (the second with a smaller input, so that what
+the library's shared grid-shift table keeps from the first call must not
+leak into it), its size limit, and the roll-back after a full slab.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import paper_1801_10187_amd as m
+import workloads
+from helpers import banner
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    m.load()
+
+
+def _pair(n_cells, rho, seed, precision, thermostat=True, **kw):
+    pos, vel = workloads.fluid(n_cells, rho, seed=seed)
+    mk = lambda: m.Sim(pos, vel, n_cells, seed=seed, precision=precision,  # noqa: E731
+                       thermostat=thermostat, **kw)
+    return mk(), mk()
+
+
+def _same_state(a, b):
+    pa, va = a.get_state()
+    pb, vb = b.get_state()
+    assert np.array_equal(pa, pb) and np.array_equal(va, vb)
+    ca, na = a.get_cells()
+    cb, nb = b.get_cells()
+    assert np.array_equal(ca, cb) and np.array_equal(na, nb)
+    assert a.step_count == b.step_count
+
+
+class _PoolHighWater:
+    """High-water mark of the device's default stream-ordered memory pool
+    (where the library's allocations come from), read through the HIP
+    runtime that torch loaded."""
+
+    def __init__(self):
+        import torch
+        torch.cuda.init()
+        self.hip = ctypes.CDLL("libamdhip64.so")
+        self.pool = ctypes.c_void_p()
+        dev = torch.cuda.current_device()
+        assert self.hip.hipDeviceGetDefaultMemPool(ctypes.byref(self.pool), dev) == 0
+
+    def reset(self):
+        zero = ctypes.c_uint64(0)
+        assert self.hip.hipMemPoolSetAttribute(self.pool, 8, ctypes.byref(zero)) == 0  # UsedMemHigh
+
+    def used(self, attr):
+        v = ctypes.c_uint64(0)
+        assert self.hip.hipMemPoolGetAttribute(self.pool, attr, ctypes.byref(v)) == 0
+        return v.value
+
+    def current(self):
+        return self.used(7)  # UsedMemCurrent
+
+    def high(self):
+        return self.used(8)  # UsedMemHigh since the last reset
+
+
+@pytest.mark.parametrize("form", ["fp32", "fp64"])
+def test_noalloc_equals_step_two_calls(form):
+    """Two calls in a row on one context (50 steps, then 7), and then a call
+    on a smaller box: every state bit for bit that of mpcd_step."""
+    banner(f"noalloc vs step, {form}")
+    prec = m.FP32 if form == "fp32" else m.FP64
+    a, b = _pair((24, 24, 24), 10, 5, prec)
+    with a, b:
+        a.step(50)
+        b.step_noalloc(50)
+        _same_state(a, b)
+        a.step(7)
+        b.step_noalloc(7)
+        _same_state(a, b)
+    c, d = _pair((9, 7, 5), 6, 6, prec)
+    with c, d:
+        c.step(3)
+        d.step_noalloc(3)
+        _same_state(c, d)
+
+
+def test_noalloc_allocates_nothing():
+    """The default pool's high-water mark does not move during the call
+    (mpcd_step, whose shift table grows on demand, does move it)."""
+    banner("noalloc allocates nothing")
+    hw = _PoolHighWater()
+    a, b = _pair((16, 16, 16), 10, 7, m.FP32)
+    with a, b:
+        a.step(2)
+        b.step_noalloc(2)
+        a.sync()
+        b.sync()
+        base = hw.current()
+        hw.reset()
+        b.step_noalloc(300)
+        print(f"pool in use {base} B; high-water during the no-alloc call {hw.high()} B")
+        assert hw.high() <= base
+        base = hw.current()
+        hw.reset()
+        a.step(300)      # its shift table grows from 3 to 301 steps
+        print(f"pool in use {base} B; high-water during mpcd_step {hw.high()} B")
+        assert hw.high() > base
+        _same_state(a, b)
+
+
+def test_noalloc_batch_and_limit():
+    """A batch of boxes steps as with mpcd_step; a call needing more grid
+    shifts than the table holds is refused before anything runs."""
+    banner("noalloc batch and size limit")
+    boxes = []
+    for i, (nc, rho) in enumerate([((8, 6, 5), 9.0), ((10, 10, 10), 5.0), ((5, 5, 5), 2.5)]):
+        pos, vel = workloads.fluid(nc, rho, seed=70 + i)
+        boxes.append(dict(n_cells=nc, pos=pos, vel=vel, seed=80 + i, kT=1.0 + 0.2 * i))
+    a = m.Batch(boxes, precision=m.FP32, thermostat=True)
+    b = m.Batch(boxes, precision=m.FP32, thermostat=True)
+    with a, b:
+        a.step(12)
+        b.step_noalloc(12)
+        _same_state(a, b)
+        too_many = m.binding.NOALLOC_MAX_SHIFTS // 3       # (n + 1) * 3 > table
+        with pytest.raises(m.MpcdError) as e:
+            b.step_noalloc(too_many)
+        assert e.value.status == m.binding.MPCD_EINVAL
+        assert b.step_count == 12
+        a.step(4)
+        b.step_noalloc(4)
+        _same_state(a, b)
+
+
+def test_noalloc_full_slab_rolls_back():
+    """A converging flow in slabs sized to the initial occupancy: the call
+    returns MPCD_ENOMEM with the state rolled back to the input of the
+    launch that overflowed; finishing that step with mpcd_collide and going
+    on with mpcd_step (which enlarges the slabs) gives the run of mpcd_step
+    alone, bit for bit."""
+    banner("noalloc full slab")
+    n_cells = (12, 12, 12)
+    pos, vel = workloads.fluid(n_cells, 9, seed=23)
+    L = np.array(n_cells, dtype=np.float64)
+    vel = vel - (pos - L / 2)
+    mk = lambda: m.Sim(pos, vel, n_cells, seed=22, precision=m.FP32, thermostat=True,  # noqa: E731
+                       flags=m.binding.FLAG_TIGHT_SLABS)
+    with mk() as a, mk() as b:
+        a.step(6)
+        with pytest.raises(m.MpcdError) as e:
+            b.step_noalloc(6)
+        assert e.value.status == m.binding.MPCD_ENOMEM
+        s = b.step_count
+        assert s < 6
+        try:
+            b.collide()          # step s was binned, not collided
+            s += 1
+        except m.MpcdError as err:  # the first stream + bin overflowed
+            assert err.status == m.binding.MPCD_ESTATE and s == 0
+        assert b.step_count == s
+        b.step(6 - s)
+        assert b.layout()[3] >= 1
+        _same_state(a, b)
