@@ -696,21 +696,22 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
     return ok ? cell_index(B, g) : 0u;
   };
 
-  // cell thread: the rotation axis and the numbers of the first attempts of
-  // the thermostat draw need only (cell, step), so they are drawn while the
-  // tile's count is in flight, before the gather (drawn after the gather is
-  // issued, they would be scheduled against the registers the loads fill);
-  // they wait in LDS. With tiles of at most 128 cells the thermostat's lanes
-  // (gthr, cell tid - CPT) are the waves after the cell threads' own, so the
-  // two chains run side by side on different waves.
-  const bool cthr = COLL && tid < (uint32_t)CPT;
+  // The per-cell draws need only (cell, step). The block's threads form
+  // TT / CPT groups of CPT lanes, lane l of each group working for cell l:
+  // group 0 (the cell threads) draws the axis, and the numbers of each of
+  // the first attempts of the thermostat draw come from a group of their
+  // own where the tile leaves one (64-cell tiles: attempt j on group 1 + j),
+  // so the chains run side by side on different waves. They are drawn while
+  // the tile's count is in flight, before the gather (drawn after the gather
+  // is issued, they would be scheduled against the registers the loads
+  // fill), and wait in LDS.
+  constexpr uint32_t NG = TT / CPT;                 // lane groups
+  const uint32_t grp = tid / (uint32_t)CPT, gl = tid & (uint32_t)(CPT - 1);
+  constexpr uint32_t DG = NG > 1 ? 1u : 0u;         // the group that decides the draws
+  const bool cthr = COLL && grp == 0u;
   bool cok = false;
   const uint32_t gcell = cthr ? cell_of(tid, cok) : 0u;
-  constexpr bool GSPLIT = 2 * CPT <= TT;
-  const uint32_t gl = GSPLIT ? tid - (uint32_t)CPT : tid;  // cell of a thermostat lane
-  const bool gthr = THERMO && COLL && (GSPLIT ? (tid >= (uint32_t)CPT && tid < 2u * CPT) : cthr);
-  bool gok = false;
-  const uint32_t ggcell = gthr ? cell_of(gl, gok) : 0u;
+  const bool gthr = THERMO && COLL && grp == DG;
   if constexpr (COLL) {
     if (cthr && !AT) {
       double n[3] = {0.0, 0.0, 0.0};
@@ -720,13 +721,15 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
       s_ax[2][tid] = n[2];
     }
     if constexpr (THERMO) {
-      if (gthr) {
 #pragma unroll
-        for (int j = 0; j < GPRE; ++j) {
+      for (int j = 0; j < GPRE; ++j) {
+        if (grp == min(DG + (uint32_t)j, NG - 1u)) {
+          bool ok;
+          const uint32_t c = cell_of(gl, ok);
           double g = 0.0, lu = -INFINITY;
-          if (gok) {
+          if (ok) {
             double u2;
-            gamma_numbers(ggcell, A.step, (uint32_t)j, B.k0, B.k1, g, u2);
+            gamma_numbers(c, A.step, (uint32_t)j, B.k0, B.k1, g, u2);
             if (!gamma_squeeze(g, u2)) lu = log(u2);
           }
           s_gam[2 * j][gl] = g;
