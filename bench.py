@@ -125,7 +125,10 @@ def measured_traffic(form, workload=WORKLOAD):
     return rec.get("bytes_per_launch", {}).get(workload, {}).get(form)
 
 
-def run_form(m, inp, cfg, precision, steps, warmup, collision=0):
+def run_form(m, inp, cfg, precision, steps, warmup, collision=0, graph=False):
+    """Time `steps` steps in one call. With graph=True the call's kernels are
+    launched as one HIP graph and kernel timing stays off (it would make the
+    call launch on the stream); collide_ms is then 0."""
     import torch
     pos, vel, bpos, bvel, bmass = inp
     # the AT rule thermostats by itself: it runs without the cell thermostat
@@ -134,18 +137,21 @@ def run_form(m, inp, cfg, precision, steps, warmup, collision=0):
                 precision=precision, thermostat=thermo, collision=collision,
                 emb_pos=bpos, emb_vel=bvel, emb_mass=bmass)
     try:
+        sim.set_graph(graph)
         sim.step(warmup)
+        sim.step(steps)       # the graph of a `steps`-step call is kept for the timed call
         sim.sync()
-        sim.profile(True, every=PROFILE_EVERY)
-        for w in (0, 1):
-            sim.profile_read(w)
+        if not graph:
+            sim.profile(True, every=PROFILE_EVERY)
+            for w in (0, 1):
+                sim.profile_read(w)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sim.step(steps)
         sim.sync()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        coll_ms, coll_n = sim.profile_read(0)
+        coll_ms, coll_n = sim.profile_read(0) if not graph else (0.0, 0)
         sim.profile(False)
         P, ke, kT = sim.totals()
     finally:
@@ -328,6 +334,27 @@ def bench_batch(m, workloads, cfg, args):
             bt.step(1)
             bt.sync()
             lat.append(time.perf_counter() - a)
+        # whole calls of `steps` steps, kernels launched one by one on the
+        # stream and as one HIP graph (every box finishes with the call's last
+        # launch, so a box's completion time is the call's)
+        calls = {}
+        for mode in ("stream", "graph"):
+            bt.set_graph(mode == "graph")
+            bt.step(steps)
+            bt.sync()
+            t = []
+            for _ in range(args.batch_calls):
+                a = time.perf_counter()
+                bt.step(steps)
+                bt.sync()
+                t.append(time.perf_counter() - a)
+            t_ms = 1e3 * np.array(t)
+            calls[mode] = {"p50": float(np.percentile(t_ms, 50)), "p99": float(np.percentile(t_ms, 99)),
+                           "min": float(t_ms.min()), "calls": len(t)}
+            print(f"[bench] {steps}-step calls on the {mode}: p50 {calls[mode]['p50']:.1f} ms "
+                  f"p99 {calls[mode]['p99']:.1f} ms", file=sys.stderr, flush=True)
+        calls["graph_instantiations_updates"] = list(bt.graph_stats())
+        bt.set_graph(False)
         P, ke, kT = bt.box_totals()
     finally:
         bt.close()
@@ -347,6 +374,8 @@ def bench_batch(m, workloads, cfg, args):
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
                        "p99": float(np.percentile(lat_ms, 99)),
                        "what": "one mpcd_step(1) call on the whole batch, waited for"},
+        "call_ms": dict(calls, what=f"one mpcd_step({steps}) call on the whole batch, waited for; "
+                                    "every box completes with the call"),
         "roofline": roofline("fp32", N, ncells, avg_us,
                              measured_traffic("fp32", "srd_batch256_fp32")),
         "kT_range_end": [float(kT.min()), float(kT.max())],
@@ -451,10 +480,11 @@ def bench_md(m, workloads, cfg, args):
     """Solutes coupled through an external MD integrator (sec. 3.6): per
     collision the beads' state is handed over (mpcd_set_embedded), one step
     runs and the collided bead velocities come back (mpcd_get_embedded), on
-    device buffers. The integrator itself (forces, moving the beads) is the
-    caller's and is not part of the timed cycle, so the beads keep their
-    positions here; the same context is then stepped without the exchange
-    for comparison."""
+    device buffers. The integrator itself (forces) is the caller's; in its
+    place every bead moves by a fixed random displacement of up to 0.1 cell
+    per axis each cycle (one elementwise torch operation on the device, in
+    the timed cycle), so that some beads change tile as they would under MD.
+    The same context is then stepped without the exchange for comparison."""
     import torch
     steps = cfg["steps"] if args.steps == 1000 else args.steps
     pos, vel, bpos, bvel, bmass = make_input(cfg)
@@ -466,9 +496,16 @@ def bench_md(m, workloads, cfg, args):
     del pos, vel
     dpos = torch.from_numpy(bpos).cuda()
     dvel = torch.from_numpy(bvel).cuda()
+    L = torch.tensor(cfg["n_cells"], dtype=torch.float64, device="cuda")
+    disp = (torch.rand(dpos.shape, generator=torch.Generator(device="cuda").manual_seed(cfg["seed"]),
+                       dtype=torch.float64, device="cuda") - 0.5) * 0.2
     torch.cuda.synchronize()
 
     def cycle():
+        dpos.add_(disp)                   # stands in for the integrator's move
+        dpos.sub_(torch.floor(dpos / L) * L)
+        dpos.masked_fill_(dpos >= L, 0.0)
+        torch.cuda.current_stream().synchronize()
         sim.set_embedded_device(dpos.data_ptr(), dvel.data_ptr())
         sim.step(1)
         sim.get_embedded_device(dpos.data_ptr(), dvel.data_ptr())
@@ -492,6 +529,7 @@ def bench_md(m, workloads, cfg, args):
         sim.sync()
         t3 = time.perf_counter()
         sim.profile(False)
+        handovers = sim.handover_stats()
     finally:
         sim.close()
     cyc = (t1 - t0) / steps
@@ -510,6 +548,7 @@ def bench_md(m, workloads, cfg, args):
         "bin_kernel_avg_us": 1e3 * bin_ms / max(bin_n, 1),
         "ms_per_step_without_exchange": 1e3 * plain,
         "exchange_overhead_ms": 1e3 * (cyc - plain),
+        "handovers_kept_given_up": list(handovers),
     }
     print(json.dumps(out), flush=True)
 
@@ -529,6 +568,8 @@ def main():
                              "srd_batch256_fp32", "srd_serve_poisson50", "srd_400c_rho5_md"])
     ap.add_argument("--serve-workers", type=int, default=8,
                     help="host threads serving requests (srd_serve_poisson50)")
+    ap.add_argument("--batch-calls", type=int, default=12,
+                    help="timed whole calls per launch mode (srd_batch256_fp32)")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the streaming copy kernel (1 GiB, 20 times)")
     args = ap.parse_args()
@@ -588,6 +629,16 @@ def main():
 
     head = res.get("fp32") or res[forms[0]]
     head_form = "fp32" if "fp32" in res else forms[0]
+    # the same call with its kernels launched as one HIP graph
+    base = head_form.split("_")[0]
+    g = run_form(m, inp, cfg, m.FP32 if base == "fp32" else m.FP64, args.steps, args.warmup,
+                 m.AT if head_form.endswith("_at") else m.SRD, graph=True)
+    graph_cmp = {"form": head_form, "stream_ms_per_step": head["ms_per_step"],
+                 "graph_ms_per_step": 1e3 * g["seconds"] / args.steps,
+                 "what": f"one {args.steps}-step call, kernels launched one by one on the "
+                         "stream against one HIP graph (kept and updated between calls)"}
+    print(f"[bench] graph: {graph_cmp['graph_ms_per_step']:.4f} ms/step "
+          f"(stream {head['ms_per_step']:.4f})", file=sys.stderr, flush=True)
     out = {
         "metric": "particle-updates/s (stream+bin+SRD collide) FP32 vs FP64; p99 batch latency",
         "value": head["updates_per_s"],
@@ -610,6 +661,7 @@ def main():
         "roofline": roofline(head_form.split("_")[0], N, ncells, head["collide_avg_us"],
                              measured_traffic(head_form, wl) if head_form in STATE_BYTES else None),
         "step_floor_frac": head["step_floor_frac"],
+        "graph_vs_stream": graph_cmp,
         "forms": {f: {"updates_per_s": r["updates_per_s"], "ms_per_step": r["ms_per_step"],
                       "collide_avg_us": r["collide_avg_us"], "collide_GBs": r["collide_GBs"],
                       "rule": r["rule"], "thermostat": r["thermostat"],

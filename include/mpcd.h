@@ -89,7 +89,7 @@ typedef struct {
   int32_t precision;   /* mpcd_precision: storage form of positions/velocities   */
   int32_t thermostat;  /* 0 none, 1 Maxwell-Boltzmann cell scaling (sec. 2, 3.6) */
   int32_t grid_shift;  /* 1 random grid shift each step (sec. 2), 0 none         */
-  int32_t flags;       /* 0, or MPCD_FLAG_TIGHT_SLABS | MPCD_FLAG_MD_SOLUTE      */
+  int32_t flags;       /* MPCD_FLAG_* bits, and a MPCD_TILE_* shape (0: rule)   */
   int32_t collision;   /* mpcd_collision: MPCD_SRD (0) or MPCD_AT (1)            */
 } mpcd_params;
 
@@ -107,6 +107,20 @@ typedef struct {
  * Without this flag embedded particles stream ballistically like the
  * solvent. */
 #define MPCD_FLAG_MD_SOLUTE 2
+
+/* Tile shape (the cells a block of the step kernel collides together and
+ * whose particles share a slab), in bits 8-10 of flags: 0 chooses by the
+ * box's mean density (rho >= 11: 4x4x2 cells, >= 3.5: 4x4x4, >= 1.75:
+ * 8x4x4, else 8x8x4); MPCD_TILE_4x4x2 .. MPCD_TILE_8x8x4 set it. Results do
+ * not depend on it (only how fast they come). In a batch each box may set
+ * its own; the other flags must match. Sec. 3.5 tunes the equivalent launch
+ * parameters by timing; paper_1801_10187_amd.autotune does that here. */
+#define MPCD_TILE_SHIFT 8
+#define MPCD_TILE_MASK (7 << MPCD_TILE_SHIFT)
+#define MPCD_TILE_4x4x2 (1 << MPCD_TILE_SHIFT)
+#define MPCD_TILE_4x4x4 (2 << MPCD_TILE_SHIFT)
+#define MPCD_TILE_8x4x4 (3 << MPCD_TILE_SHIFT)
+#define MPCD_TILE_8x8x4 (4 << MPCD_TILE_SHIFT)
 
 /* Create a context and upload the initial state (sec. 3.2 particle data).
  *  pos, vel      n_solvent x 3 doubles; positions inside [0, L) per axis.
@@ -179,11 +193,11 @@ mpcd_status mpcd_collide(mpcd_ctx ctx);
  * collided velocities, streamed and binned) beside the collided positions,
  * so that the next mpcd_step starts with its collision; every get_* reads the
  * collided state, joining the two copies where needed.
- * mpcd_stream, mpcd_set_embedded and a changed step counter give the
- * prepared binning up (the next mpcd_step then streams and bins first), as
- * does a slab overflow in that launch; with MPCD_FLAG_MD_SOLUTE, where the
- * solutes' state is handed over before every collision, no binning is
- * prepared. Results never depend on how a run is split into calls. */
+ * mpcd_stream, mpcd_set_embedded (except for the solutes of
+ * MPCD_FLAG_MD_SOLUTE, which it moves into the prepared binning) and a
+ * changed step counter give the prepared binning up (the next mpcd_step
+ * then streams and bins first), as does a slab overflow in that launch.
+ * Results never depend on how a run is split into calls. */
 mpcd_status mpcd_step(mpcd_ctx ctx, int64_t nsteps);
 
 /* For callers that cannot allocate (tight serving loops, harnesses that
@@ -211,17 +225,31 @@ mpcd_status mpcd_step_noalloc(mpcd_ctx ctx, int64_t nsteps);
  * mpcd_create. get: any state; synchronises. set: only between steps (after
  * create or a collide, else MPCD_ESTATE); positions must lie in [0, L)
  * (else MPCD_EINVAL, and nothing is guaranteed about which rows were taken);
- * the values are stored in the context's precision; the next binning moves
- * each particle to the tile of its new position. MPCD_EINVAL if the context
- * has no embedded particles. The exchange with an MD integrator
- * (MPCD_FLAG_MD_SOLUTE). The context keeps the slot of every embedded
- * particle, so both calls cost O(n_embedded) work on the device (one thread
- * per particle), whatever the number of solvent particles; with device
- * pointers they allocate nothing. */
+ * the values are stored in the context's precision. The exchange with an
+ * MD integrator (MPCD_FLAG_MD_SOLUTE; sec. 3.6). The context keeps the slot
+ * of every embedded particle, so both calls cost O(n_embedded) work on the
+ * device (a thread per particle), whatever the number of solvent particles.
+ * With MPCD_FLAG_MD_SOLUTE and the next step's binning prepared (after
+ * mpcd_step), set moves each solute into that binning at the cell its new
+ * position falls in under the next step's grid shift: a solute that stays in
+ * its tile is updated in place, one that changes tile leaves its old tile's
+ * slab (the slab's last particles fill the gap) and takes a slot at the end
+ * of its new tile's slab; the solvent's binning is kept, so the next
+ * mpcd_step starts with its collision. If a destination slab is full, the
+ * prepared binning is given up instead and the next step streams and bins
+ * everything (results are the same). Otherwise the next binning moves each
+ * particle to the tile of its new position. With device pointers and the
+ * handover's small index arrays allocated (on its first use) they allocate
+ * nothing. */
 mpcd_status mpcd_get_embedded(mpcd_ctx ctx, double* pos, double* vel,
                               int32_t pointers_on_device);
 mpcd_status mpcd_set_embedded(mpcd_ctx ctx, const double* pos, const double* vel,
                               int32_t pointers_on_device);
+
+/* Solute handovers (mpcd_set_embedded with MPCD_FLAG_MD_SOLUTE) that kept
+ * the prepared binning, and those that gave it up because a destination
+ * slab was full. Either pointer may be NULL. */
+mpcd_status mpcd_handover_stats(mpcd_ctx ctx, int64_t* kept, int64_t* given_up);
 
 /* Copy the state out in tag order: pos, vel are n_total x 3 doubles, where
  * n_total = n_solvent + n_embedded. Synchronises the context's stream. */
@@ -292,6 +320,37 @@ mpcd_status mpcd_get_sizes(mpcd_ctx ctx, int64_t* n_total, int64_t* n_cells);
  * NULL. */
 mpcd_status mpcd_get_layout(mpcd_ctx ctx, int32_t tile[3], int64_t* n_tiles,
                             int64_t* capacity, int64_t* regrows);
+
+/* Device memory a context of one box with these parameters and
+ * n_particles solvent particles would take from the stream-ordered memory
+ * pool its allocations come from, for a run of nsteps-step calls:
+ * peak_bytes the most it holds at any moment (the upload buffer of
+ * mpcd_create, 48 bytes per particle when host_arrays is 1; the grid-shift
+ * table of a stepping call; the temporaries of mpcd_get_velocity_field or
+ * mpcd_get_state), held_bytes what it keeps between calls. An estimate for
+ * particles spread like a uniform fluid: mpcd_create sizes the slabs from
+ * the fullest tile of the actual input, taken here as a whole tile's mean
+ * occupancy plus five standard deviations (Poisson); a very uneven input, and an
+ * enlargement of the slabs during a step (old and new slabs held at once),
+ * need more. Either pointer may be NULL. Host-only computation. */
+mpcd_status mpcd_footprint(const mpcd_params* params, int64_t n_particles, int64_t nsteps,
+                           int32_t host_arrays, int64_t* peak_bytes, int64_t* held_bytes);
+
+/* Launch mode of the stepping calls (mpcd_step, mpcd_bin; sec. 3.5 names
+ * launch parameters as a tuning choice). on = 1: the tile-kernel launches
+ * of each call are captured into a HIP graph on the context's stream and
+ * the graph is launched; the context keeps the executable graph and updates
+ * it in place from the next call's capture (new step numbers and buffers)
+ * when the capture has the same shape, else instantiates a new one. on = 0
+ * (the default): one stream launch per kernel. Results are the same bit for
+ * bit. While kernel timing (mpcd_profile_enable) is on, calls launch on the
+ * stream. MPCD_EINVAL for on other than 0 or 1, or for on = 1 with a context
+ * created on the null or per-thread stream (which cannot be captured). */
+mpcd_status mpcd_set_graph(mpcd_ctx ctx, int32_t on);
+
+/* Executable graphs instantiated and updated in place by the context's
+ * graph launches so far. Either pointer may be NULL. */
+mpcd_status mpcd_graph_stats(mpcd_ctx ctx, int64_t* instantiations, int64_t* updates);
 
 /* Kernel timing with HIP events on the context's stream. which: 0 the
  * collision kernel (collide with its per-cell draws, stream and bin of the

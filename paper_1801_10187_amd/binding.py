@@ -21,6 +21,13 @@ FP64, FP32 = 0, 1
 SRD, AT = 0, 1
 FLAG_TIGHT_SLABS = 1
 FLAG_MD_SOLUTE = 2
+# tile shapes (bits 8-10 of flags; absent: chosen by density)
+TILE_SHAPES = {"4x4x2": 1, "4x4x4": 2, "8x4x4": 3, "8x8x4": 4}
+
+
+def tile_flag(shape):
+    """flags bits of a tile shape name (None: the density rule)."""
+    return 0 if shape is None else TILE_SHAPES[shape] << 8
 NOALLOC_MAX_SHIFTS = 8192
 STATUS_NAMES = {0: "MPCD_OK", 1: "MPCD_EINVAL", 2: "MPCD_ENOMEM", 3: "MPCD_EHIP",
                 4: "MPCD_ERANGE", 5: "MPCD_ESTATE"}
@@ -88,6 +95,13 @@ def load():
         "mpcd_totals": (st, [_P, _P, _D, _D]),
         "mpcd_sync": (st, [_P]),
         "mpcd_get_sizes": (st, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+        "mpcd_handover_stats": (st, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_int64)]),
+        "mpcd_set_graph": (st, [ctypes.c_void_p, ctypes.c_int32]),
+        "mpcd_graph_stats": (st, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(ctypes.c_int64)]),
+        "mpcd_footprint": (st, [ctypes.POINTER(Params), ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
         "mpcd_get_layout": (st, [_P, _P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                  ctypes.POINTER(ctypes.c_int64)]),
         "mpcd_profile_enable": (st, [_P, ctypes.c_int32]),
@@ -134,7 +148,7 @@ def _ptr(a):
 
 def make_params(n_cells, a=1.0, alpha=130.0 * math.pi / 180.0, dt=0.1, kT=1.0,
                 seed=1, solvent_mass=1.0, precision=FP64, thermostat=False,
-                grid_shift=True, flags=0, collision=0):
+                grid_shift=True, flags=0, collision=0, tile=None):
     p = Params()
     n = [int(x) for x in np.broadcast_to(np.asarray(n_cells), (3,))]
     p.n_cells[:] = n
@@ -144,7 +158,7 @@ def make_params(n_cells, a=1.0, alpha=130.0 * math.pi / 180.0, dt=0.1, kT=1.0,
     p.precision = int(precision)
     p.thermostat = int(bool(thermostat)) if thermostat in (0, 1, True, False) else int(thermostat)
     p.grid_shift = int(bool(grid_shift)) if grid_shift in (0, 1, True, False) else int(grid_shift)
-    p.flags = int(flags)
+    p.flags = int(flags) | tile_flag(tile)
     p.collision = int(collision)
     return p
 
@@ -155,10 +169,10 @@ class Sim:
     def __init__(self, pos, vel, n_cells, a=1.0, alpha=130.0 * math.pi / 180.0,
                  dt=0.1, kT=1.0, seed=1, solvent_mass=1.0, precision=FP64,
                  thermostat=False, grid_shift=True, emb_pos=None, emb_vel=None,
-                 emb_mass=None, hip_stream=None, flags=0, collision=0):
+                 emb_mass=None, hip_stream=None, flags=0, collision=0, tile=None):
         lib = load()
         self.params = make_params(n_cells, a, alpha, dt, kT, seed, solvent_mass,
-                                  precision, thermostat, grid_shift, flags, collision)
+                                  precision, thermostat, grid_shift, flags, collision, tile)
         pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
         vel = np.ascontiguousarray(vel, dtype=np.float64).reshape(-1, 3)
         n_emb = 0
@@ -286,6 +300,23 @@ class Sim:
                                       ctypes.byref(cap), ctypes.byref(rg)))
         return tuple(tile), nt.value, cap.value, rg.value
 
+    def handover_stats(self):
+        """(kept, given up): solute handovers into a prepared binning."""
+        k, g = ctypes.c_int64(), ctypes.c_int64()
+        _check(load().mpcd_handover_stats(self._ctx, ctypes.byref(k), ctypes.byref(g)))
+        return k.value, g.value
+
+    # -- launch mode
+    def set_graph(self, on=True):
+        """Launch each stepping call's kernels as one HIP graph (mpcd_set_graph)."""
+        _check(load().mpcd_set_graph(self._ctx, int(bool(on))))
+
+    def graph_stats(self):
+        """(instantiations, in-place updates) of the context's executable graph."""
+        i, u = ctypes.c_int64(), ctypes.c_int64()
+        _check(load().mpcd_graph_stats(self._ctx, ctypes.byref(i), ctypes.byref(u)))
+        return i.value, u.value
+
     # -- timing
     def profile(self, on=True, every=1):
         """Time launches with HIP events: the first of each kind, then one in
@@ -319,8 +350,9 @@ class Sim:
 class Batch(Sim):
     """Several independent SRD boxes stepped together (one mpcd_ctx made by
     mpcd_create_batch). `boxes` is a list of dicts with the keys pos, vel,
-    n_cells and optionally a, alpha, dt, kT, seed, solvent_mass; precision,
-    thermostat, grid_shift and flags are common to all boxes. Every method of
+    n_cells and optionally a, alpha, dt, kT, seed, solvent_mass and tile (a
+    TILE_SHAPES name); precision, thermostat, grid_shift and flags are common
+    to all boxes. Every method of
     Sim works on all boxes at once; get_state/get_cells return the boxes one
     after the other (see box())."""
 
@@ -336,7 +368,7 @@ class Batch(Sim):
                                  bx.get("alpha", 130.0 * math.pi / 180.0), bx.get("dt", 0.1),
                                  bx.get("kT", 1.0), bx.get("seed", 1 + b),
                                  bx.get("solvent_mass", 1.0), precision, thermostat,
-                                 grid_shift, flags, collision)
+                                 grid_shift, flags, collision, bx.get("tile"))
             pos_l.append(np.asarray(bx["pos"], dtype=np.float64).reshape(-1, 3))
             vel_l.append(np.asarray(bx["vel"], dtype=np.float64).reshape(-1, 3))
             counts[b] = pos_l[-1].shape[0]
@@ -372,6 +404,15 @@ class Batch(Sim):
         kT = np.empty(self.n_boxes)
         _check(load().mpcd_box_totals(self._ctx, _ptr(p), _ptr(ke), _ptr(kT)))
         return p, ke, kT
+
+
+def footprint(n_cells, n_particles, nsteps=1, precision=FP32, host_arrays=True, **kw):
+    """mpcd_footprint: (peak, held) device bytes of a one-box context."""
+    p = make_params(n_cells, precision=precision, **kw)
+    peak, held = ctypes.c_int64(), ctypes.c_int64()
+    _check(load().mpcd_footprint(ctypes.byref(p), int(n_particles), int(nsteps), int(bool(host_arrays)),
+                                 ctypes.byref(peak), ctypes.byref(held)))
+    return peak.value, held.value
 
 
 def philox(ctr, key):

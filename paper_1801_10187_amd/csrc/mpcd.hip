@@ -102,6 +102,13 @@ struct mpcd_ctx_s {
   double* emb_mass = nullptr;
   uint32_t* flag = nullptr;        // one word a host call checks after a kernel (range errors)
   uint32_t* eslot[2] = {nullptr, nullptr};  // slot of each embedded particle in buf[0], buf[1]
+  // handover of embedded particles into a prepared binning (allocated on
+  // first use): departures per tile (list heads, -1 when empty), links,
+  // movers and their count
+  int32_t* dep_head = nullptr;
+  int32_t* dep_next = nullptr;
+  uint32_t* movers = nullptr;
+  uint32_t* nmovers = nullptr;
   uint32_t* status = nullptr;      // [0] errors, [1] overflow, [2] failing launch
   long long* tot = nullptr;        // fixed-point totals, 10 words per box
 
@@ -125,6 +132,14 @@ struct mpcd_ctx_s {
   // before anything needs buf[cur] whole
   bool split = false;
   int64_t regrows = 0;
+  uint64_t handovers[2] = {0, 0};  // solute handovers into a prepared binning: kept, given up
+
+  // graph launches: the tile launches of a stepping call are captured into
+  // a graph and replayed; the executable graph is kept and updated in place
+  // by the next call's capture when its shape allows
+  bool graph = false;
+  hipGraphExec_t gexec = nullptr;
+  uint64_t graph_inst = 0, graph_upd = 0;
 
   int32_t prof_every = 0;          // time one launch in every prof_every of a kind (0: off)
   uint64_t prof_seen[2] = {0, 0};
@@ -454,6 +469,55 @@ mpcd_status drop_prepared(mpcd_ctx c) {
   return MPCD_OK;
 }
 
+// Enqueue launches L[from..] as one graph: capture them on the context's
+// stream (thread-local mode: other threads' calls are unaffected), update the
+// kept executable graph with the capture, or instantiate a new one when the
+// update is refused (another shape), and launch it. in_state records the
+// (buffer, counter) pair each launch reads.
+mpcd_status launch_graph(mpcd_ctx c, const std::vector<Launch>& L, size_t from,
+                         std::vector<std::pair<int, int>>& in_state) {
+  HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  mpcd_status st = MPCD_OK;
+  for (size_t k = from; k < L.size() && st == MPCD_OK; ++k) {
+    in_state.emplace_back(c->cur, c->ci);
+    st = launch_tile(c, L[k].op, L[k].step, (uint32_t)(k - from));
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->stream, &g);
+  if (st != MPCD_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(MPCD_EHIP, "graph capture: %s", hipGetErrorString(e));
+  bool updated = false;
+  if (c->gexec) {
+    hipGraphNode_t bad_node = nullptr;
+    hipGraphExecUpdateResult res;
+    updated = hipGraphExecUpdate(c->gexec, g, &bad_node, &res) == hipSuccess &&
+              res == hipGraphExecUpdateSuccess;
+    if (!updated) {
+      (void)hipGetLastError();
+      (void)hipGraphExecDestroy(c->gexec);
+      c->gexec = nullptr;
+    }
+  }
+  if (!updated) {
+    const hipError_t ei = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      c->gexec = nullptr;
+      (void)hipGraphDestroy(g);
+      return fail(MPCD_EHIP, "graph instantiation: %s", hipGetErrorString(ei));
+    }
+    c->graph_inst += 1;
+  } else {
+    c->graph_upd += 1;
+  }
+  const hipError_t el = hipGraphLaunch(c->gexec, c->stream);
+  (void)hipGraphDestroy(g);
+  if (el != hipSuccess) return fail(MPCD_EHIP, "graph launch: %s", hipGetErrorString(el));
+  return MPCD_OK;
+}
+
 // Run a list of tile launches, then confirm that no slab overflowed; replay
 // from the failing launch after enlarging the slabs if one did.
 mpcd_status run_launches(mpcd_ctx c, const std::vector<Launch>& L) {
@@ -461,9 +525,13 @@ mpcd_status run_launches(mpcd_ctx c, const std::vector<Launch>& L) {
   for (int attempt = 0; attempt < 16; ++attempt) {
     std::vector<std::pair<int, int>> in_state;
     in_state.reserve(L.size() - from);
-    for (size_t k = from; k < L.size(); ++k) {
-      in_state.emplace_back(c->cur, c->ci);
-      ST_TRY(launch_tile(c, L[k].op, L[k].step, (uint32_t)(k - from)));
+    if (c->graph && c->prof_every == 0) {
+      ST_TRY(launch_graph(c, L, from, in_state));
+    } else {
+      for (size_t k = from; k < L.size(); ++k) {
+        in_state.emplace_back(c->cur, c->ci);
+        ST_TRY(launch_tile(c, L[k].op, L[k].step, (uint32_t)(k - from)));
+      }
     }
     uint32_t st[3];
     HIP_TRY(hipMemcpyAsync(st, c->status, 12, hipMemcpyDeviceToHost, c->stream));
@@ -474,6 +542,10 @@ mpcd_status run_launches(mpcd_ctx c, const std::vector<Launch>& L) {
     from += bad;
   }
   return fail(MPCD_ENOMEM, "slab capacity kept overflowing");
+}
+
+int tile_shape(const mpcd_params& p) {
+  return (int)(((uint32_t)p.flags & MPCD_TILE_MASK) >> MPCD_TILE_SHIFT);
 }
 
 mpcd_status validate(const mpcd_params* p, int64_t ns, int64_t ne) {
@@ -492,8 +564,9 @@ mpcd_status validate(const mpcd_params* p, int64_t ns, int64_t ne) {
     return fail(MPCD_EINVAL, "precision must be MPCD_FP64 or MPCD_FP32");
   if (p->thermostat != 0 && p->thermostat != 1) return fail(MPCD_EINVAL, "thermostat must be 0 or 1");
   if (p->grid_shift != 0 && p->grid_shift != 1) return fail(MPCD_EINVAL, "grid_shift must be 0 or 1");
-  if ((uint32_t)p->flags & ~(uint32_t)(MPCD_FLAG_TIGHT_SLABS | MPCD_FLAG_MD_SOLUTE))
+  if ((uint32_t)p->flags & ~(uint32_t)(MPCD_FLAG_TIGHT_SLABS | MPCD_FLAG_MD_SOLUTE | MPCD_TILE_MASK))
     return fail(MPCD_EINVAL, "unknown flags");
+  if (tile_shape(*p) > 4) return fail(MPCD_EINVAL, "unknown tile shape %d", tile_shape(*p));
   if (p->collision != MPCD_SRD && p->collision != MPCD_AT)
     return fail(MPCD_EINVAL, "collision must be MPCD_SRD or MPCD_AT");
   if (p->collision == MPCD_AT && p->thermostat)
@@ -513,14 +586,15 @@ mpcd_status validate(const mpcd_params* p, int64_t ns, int64_t ne) {
 // 15 % faster than 128-cell tiles from density 7 down); sparser boxes take
 // larger tiles. The kernels hold up to 768 particles of a 64-cell tile and
 // 1024 of a larger one in registers; more are read again from memory.
+// shape 1..4 (the MPCD_TILE_* codes) sets the shape instead of the rule.
 // Returns the cells per tile, rounded up to the kernel sizes 64/128/256.
-int choose_tiles(Box& B, double rho) {
+int choose_tiles(Box& B, double rho, int shape = 0) {
   int td[3], cpt;
-  if (rho >= 11.0) {
+  if (shape == 1 || (shape == 0 && rho >= 11.0)) {
     td[0] = 4; td[1] = 4; td[2] = 2; cpt = 64;
-  } else if (rho >= 3.5) {
+  } else if (shape == 2 || (shape == 0 && rho >= 3.5)) {
     td[0] = 4; td[1] = 4; td[2] = 4; cpt = 64;
-  } else if (rho >= 1.75) {
+  } else if (shape == 3 || (shape == 0 && rho >= 1.75)) {
     td[0] = 8; td[1] = 4; td[2] = 4; cpt = 128;
   } else {
     td[0] = 8; td[1] = 8; td[2] = 4; cpt = 256;
@@ -547,6 +621,15 @@ int choose_tiles(Box& B, double rho) {
   B.inv_nt0 = 1.0 / (double)B.nt[0];
   B.inv_nt01 = 1.0 / ((double)B.nt[0] * (double)B.nt[1]);
   return cpt;
+}
+
+// Slots per tile slab: 1.2 x the largest initial tile occupancy, and at least
+// the mean occupancy plus eight standard deviations (Poisson) plus 64,
+// rounded up to 32.
+uint32_t slab_cap(uint64_t max_occupancy, double mean) {
+  const uint64_t want = std::max<uint64_t>(max_occupancy + max_occupancy / 5,
+                                           (uint64_t)(mean + 8.0 * std::sqrt(mean) + 64.0));
+  return round_up(want, 32);
 }
 
 // Per-box constants from the parameters (layout fields are set by the caller).
@@ -596,10 +679,12 @@ mpcd_status create_impl(int32_t nbox, const mpcd_params* params, const int64_t* 
     }
     const mpcd_params& q = params[b];
     if (q.precision != params[0].precision || q.thermostat != params[0].thermostat ||
-        q.grid_shift != params[0].grid_shift || q.flags != params[0].flags ||
+        q.grid_shift != params[0].grid_shift ||
+        ((q.flags ^ params[0].flags) & ~(int32_t)MPCD_TILE_MASK) != 0 ||
         q.collision != params[0].collision)
       return fail(MPCD_EINVAL,
-                  "box %d: precision, thermostat, grid_shift, flags and collision must match box 0", b);
+                  "box %d: precision, thermostat, grid_shift, flags (but the tile shape) and "
+                  "collision must match box 0", b);
     ns_total += n_solv[b];
     ncells_total += (double)q.n_cells[0] * q.n_cells[1] * q.n_cells[2];
   }
@@ -637,7 +722,8 @@ mpcd_status create_impl(int32_t nbox, const mpcd_params* params, const int64_t* 
   for (int32_t b = 0; b < nbox; ++b) {
     Box B = make_box(params[b]);
     const uint32_t nb = (uint32_t)n_solv[b] + (b == 0 ? c->n_emb : 0u);
-    cpt = std::max(cpt, choose_tiles(B, B.ncells ? (double)nb / (double)B.ncells : 0.0));
+    cpt = std::max(cpt, choose_tiles(B, B.ncells ? (double)nb / (double)B.ncells : 0.0,
+                                     tile_shape(params[b])));
     const uint32_t t0 = tile;
     B.tile0 = t0;
     B.tag0 = tag;
@@ -770,9 +856,7 @@ mpcd_status create_impl(int32_t nbox, const mpcd_params* params, const int64_t* 
   if ((uint32_t)params[0].flags & MPCD_FLAG_TIGHT_SLABS) {
     cap = std::max<uint32_t>(mx, 1u);
   } else {
-    const uint64_t want = std::max<uint64_t>((uint64_t)mx + mx / 5,
-                                             (uint64_t)(max_mean + 8.0 * std::sqrt(max_mean) + 64.0));
-    cap = round_up(want, 32);
+    cap = slab_cap(mx, max_mean);
   }
   if ((uint64_t)cap * NT >= (1ull << 32) || cap >= kMaxCap) {
     free_tmp();
@@ -941,6 +1025,7 @@ void mpcd_destroy(mpcd_ctx c) {
       (void)hipEventDestroy(pr.second);
     }
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -999,13 +1084,8 @@ mpcd_status mpcd_step(mpcd_ctx c, int64_t nsteps) {
   } else {
     L.push_back({Op::BinStream, c->step});
   }
-  // With solutes coupled to an MD integrator the caller hands their new state
-  // over before every collision, which gives a prepared binning up: such a
-  // call ends with the plain collision, which leaves the state whole in one
-  // buffer (no velocities to copy back before the next stream and binning).
-  const Op last = (c->p.flags & MPCD_FLAG_MD_SOLUTE) ? Op::Collide : Op::CollideLast;
   for (int64_t k = 0; k < nsteps; ++k) {
-    L.push_back({k + 1 < nsteps ? Op::CollideScatter : last, c->step + (uint64_t)k});
+    L.push_back({k + 1 < nsteps ? Op::CollideScatter : Op::CollideLast, c->step + (uint64_t)k});
   }
   ST_TRY(run_launches(c, L));
   c->step += (uint64_t)nsteps;
@@ -1054,9 +1134,8 @@ mpcd_status mpcd_step_noalloc(mpcd_ctx c, int64_t nsteps) {
   } else {
     st = launch_tile(c, Op::BinStream, step0, seq++);
   }
-  const Op last = (c->p.flags & MPCD_FLAG_MD_SOLUTE) ? Op::Collide : Op::CollideLast;
   for (int64_t k = 0; k < nsteps && st == MPCD_OK; ++k)
-    st = launch_tile(c, k + 1 < nsteps ? Op::CollideScatter : last, step0 + (uint64_t)k, seq++);
+    st = launch_tile(c, k + 1 < nsteps ? Op::CollideScatter : Op::CollideLast, step0 + (uint64_t)k, seq++);
   c->prof_every = prof;
   if (st != MPCD_OK) return st;
   uint32_t h[3];
@@ -1183,12 +1262,81 @@ mpcd_status mpcd_get_embedded(mpcd_ctx c, double* pos, double* vel, int32_t on_d
   return take_err(c);
 }
 
+// The embedded particles' new state into the current buffer, in place; the
+// next step bins them.
+hipError_t emb_import(mpcd_ctx c, const double* dp, const double* dv) {
+  const uint32_t n = c->n_emb, nb = blocks_for(n, kGrid);
+  const size_t ns = (size_t)c->S.ntiles * c->S.cap;
+  if (c->form == 0)
+    k_emb_import<0><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->boxes[0], c->eslot[c->cur], n, ns, dp, dv, c->flag);
+  else
+    k_emb_import<1><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->boxes[0], c->eslot[c->cur], n, ns, dp, dv, c->flag);
+  return hipGetLastError();
+}
+
+// Solutes of an MD integrator handed over while the next step's binning is
+// prepared: the new state goes into the current buffer in place and into
+// the prepared binning at the cell the prepared step's shift puts it in
+// (k_emb_rebin / k_emb_depart / k_emb_arrive), so the solvent's binning is
+// kept. When a destination slab is full the prepared binning is given up
+// and the state imported as without one. *hflag receives the kernels' flag.
+mpcd_status emb_handover(mpcd_ctx c, const double* dp, const double* dv, uint32_t* hflag) {
+  const uint32_t n = c->n_emb, nb = blocks_for(n, kGrid);
+  const uint32_t nt = c->S.ntiles;
+  if (!c->dep_head) {
+    c->dep_head = (int32_t*)c->dalloc((size_t)nt * 4);
+    c->dep_next = (int32_t*)c->dalloc((size_t)n * 4);
+    c->movers = (uint32_t*)c->dalloc((size_t)n * 4);
+    c->nmovers = (uint32_t*)c->dalloc(256);
+    if (!c->dep_head || !c->dep_next || !c->movers || !c->nmovers)
+      return fail(MPCD_ENOMEM, "device allocation for the solute handover failed");
+    HIP_TRY(hipMemsetAsync(c->dep_head, 0xFF, (size_t)nt * 4, c->stream));
+  }
+  ST_TRY(ensure_shifts(c, c->step, 1));
+  const ShiftEntry* sh = shift_at(c, c->step);
+  const int pb = 1 - c->cur;
+  uint32_t* cnt_p = c->cnt[(c->ci + 1) % 3];
+  const size_t ns = (size_t)nt * c->S.cap;
+  const uint32_t cap = c->S.cap;
+  const Box& B = c->boxes[0];
+  HIP_TRY(hipMemsetAsync(c->nmovers, 0, 4, c->stream));
+  if (c->form == 0) {
+    k_emb_rebin<0><<<nb, kGrid, 0, c->stream>>>(c->buf[pb], c->buf[c->cur], B, sh, c->eslot[pb], c->eslot[c->cur], n, ns, cap, dp, dv, c->dep_head, c->dep_next, c->movers, c->nmovers, c->flag);
+    k_emb_depart<0><<<nb, kGrid, 0, c->stream>>>(c->buf[pb], B, c->eslot[pb], cap, cnt_p, c->movers, c->nmovers, c->dep_head, c->dep_next);
+    k_emb_arrive<0><<<nb, kGrid, 0, c->stream>>>(c->buf[pb], B, sh, c->eslot[pb], cap, cnt_p, c->movers, c->nmovers, dp, dv, c->flag);
+  } else {
+    k_emb_rebin<1><<<nb, kGrid, 0, c->stream>>>(c->buf[pb], c->buf[c->cur], B, sh, c->eslot[pb], c->eslot[c->cur], n, ns, cap, dp, dv, c->dep_head, c->dep_next, c->movers, c->nmovers, c->flag);
+    k_emb_depart<1><<<nb, kGrid, 0, c->stream>>>(c->buf[pb], B, c->eslot[pb], cap, cnt_p, c->movers, c->nmovers, c->dep_head, c->dep_next);
+    k_emb_arrive<1><<<nb, kGrid, 0, c->stream>>>(c->buf[pb], B, sh, c->eslot[pb], cap, cnt_p, c->movers, c->nmovers, dp, dv, c->flag);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(hflag, c->flag, 4, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (!(*hflag & 8u)) {
+    c->handovers[0] += 1;
+    return MPCD_OK;
+  }
+  // a destination slab was full: give the prepared binning up (joining the
+  // velocities by tag; the movers left out of it are then imported anew)
+  c->handovers[1] += 1;
+  ST_TRY(drop_prepared(c));
+  HIP_TRY(hipMemsetAsync(c->flag, 0, 4, c->stream));
+  HIP_TRY(emb_import(c, dp, dv));
+  HIP_TRY(hipMemcpyAsync(hflag, c->flag, 4, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return MPCD_OK;
+}
+
 mpcd_status mpcd_set_embedded(mpcd_ctx c, const double* pos, const double* vel, int32_t on_device) {
   ST_TRY(check_ctx(c));
   if (c->n_emb == 0) return fail(MPCD_EINVAL, "no embedded particles");
   if (!pos || !vel) return fail(MPCD_EINVAL, "pos/vel NULL");
   if (c->phase != Phase::Idle) return fail(MPCD_ESTATE, "mpcd_set_embedded: only between steps");
-  ST_TRY(drop_prepared(c));  // the new positions are binned afresh by the next step
+  // solutes of an MD integrator are not streamed: with the next step's
+  // binning prepared they are moved into it; otherwise the next step bins
+  // them afresh
+  const bool handover = c->pre && (c->p.flags & MPCD_FLAG_MD_SOLUTE);
+  if (!handover) ST_TRY(drop_prepared(c));
   const size_t n = c->n_emb;
   const double* dp = pos;
   const double* dv = vel;
@@ -1202,21 +1350,24 @@ mpcd_status mpcd_set_embedded(mpcd_ctx c, const double* pos, const double* vel, 
     dv = tmp + 3 * n;
   }
   if (e == hipSuccess) e = hipMemsetAsync(c->flag, 0, 4, c->stream);
-  if (e == hipSuccess) {
-    const uint32_t nb = blocks_for(n, kGrid);
-    if (c->form == 0)
-      k_emb_import<0><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->boxes[0], c->eslot[c->cur], (uint32_t)n, (size_t)c->S.ntiles * c->S.cap, dp, dv, c->flag);
-    else
-      k_emb_import<1><<<nb, kGrid, 0, c->stream>>>(c->buf[c->cur], c->boxes[0], c->eslot[c->cur], (uint32_t)n, (size_t)c->S.ntiles * c->S.cap, dp, dv, c->flag);
-    e = hipGetLastError();
-  }
   uint32_t hbad = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, c->flag, 4, hipMemcpyDeviceToHost, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (handover) {
+    if (e == hipSuccess) {
+      const mpcd_status st = emb_handover(c, dp, dv, &hbad);
+      if (st != MPCD_OK) {
+        if (tmp) c->release(tmp);
+        return st;
+      }
+    }
+  } else {
+    if (e == hipSuccess) e = emb_import(c, dp, dv);
+    if (e == hipSuccess) e = hipMemcpyAsync(&hbad, c->flag, 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  }
   if (tmp) c->release(tmp);
   if (e != hipSuccess) return fail(MPCD_EHIP, "set_embedded: %s", hipGetErrorString(e));
   if (hbad & 4u) return fail(MPCD_EHIP, "set_embedded: the embedded-particle index is out of date");
-  if (hbad) return fail(MPCD_EINVAL, "an embedded position lies outside [0, L)");
+  if (hbad & 1u) return fail(MPCD_EINVAL, "an embedded position lies outside [0, L)");
   return take_err(c);
 }
 
@@ -1418,6 +1569,46 @@ mpcd_status mpcd_get_n_boxes(mpcd_ctx c, int32_t* n_boxes) {
   return MPCD_OK;
 }
 
+mpcd_status mpcd_footprint(const mpcd_params* params, int64_t n_particles, int64_t nsteps,
+                           int32_t host_arrays, int64_t* peak_bytes, int64_t* held_bytes) {
+  g_err.clear();
+  ST_TRY(validate(params, n_particles, 0));
+  if (nsteps < 0) return fail(MPCD_EINVAL, "nsteps < 0");
+  Box B = make_box(*params);
+  const double rho = B.ncells ? (double)n_particles / (double)B.ncells : 0.0;
+  (void)choose_tiles(B, rho, tile_shape(*params));
+  const uint64_t nt = B.ntiles, C = B.ncells, n = (uint64_t)n_particles;
+  const bool fp64 = params->precision == MPCD_FP64;
+  // every allocation is at least 256 bytes; allow that much again for the
+  // pool's rounding
+  auto sz = [](uint64_t bytes) { return std::max<uint64_t>(bytes, 256) + 256; };
+  // the slab capacity mpcd_create picks when the fullest tile holds a whole
+  // tile's mean occupancy plus five standard deviations (tiles cut by the
+  // box's far faces hold fewer)
+  const double full = rho * (double)B.td[0] * (double)B.td[1] * (double)B.td[2];
+  const uint64_t cap = slab_cap((uint64_t)std::ceil(full + 5.0 * std::sqrt(full)),
+                                (double)n / (double)nt);
+  const uint64_t S = nt * cap;
+  const uint64_t slabs = fp64 ? 2 * (3 * sz(S * 16) + sz(S * 4) + sz(S))   // wa wb wc, tag, cell
+                              : 2 * (2 * sz(S * 16) + sz(S));              // ra rb, cell
+  // counters (3), status, totals, embedded masses, box table, tile table, flag
+  const uint64_t tables = 3 * sz(nt * 4) + sz(256) + sz(10 * 8) + sz(0) + sz(sizeof(Box)) +
+                          sz(nt * 4) + sz(256);
+  const uint64_t held = slabs + tables;
+  const uint64_t shifts = sz(std::max<uint64_t>((uint64_t)nsteps + 1, 64) * sizeof(ShiftEntry));
+  // temporaries, one at a time: the upload buffer of host arrays; the
+  // readbacks' staging (state, cells, cell diagnostics, velocity field and
+  // the join of a split state before it)
+  const uint64_t upload = host_arrays ? sz(n * 48) : 0;
+  const uint64_t h = host_arrays ? 1 : 0;
+  const uint64_t readback = std::max({h * sz(n * 48), h * sz((n + C) * 4 + 16), sz(C * 72),
+                                      sz(C * (64 + 32 * h)), sz(n * 3 * (fp64 ? 8 : 4))});
+  const uint64_t peak = held + std::max(upload, shifts + readback);
+  if (peak_bytes) *peak_bytes = (int64_t)peak;
+  if (held_bytes) *held_bytes = (int64_t)(held + shifts);
+  return MPCD_OK;
+}
+
 mpcd_status mpcd_get_layout(mpcd_ctx c, int32_t tile[3], int64_t* n_tiles, int64_t* capacity,
                             int64_t* regrows) {
   ST_TRY(check_ctx(c));
@@ -1426,6 +1617,29 @@ mpcd_status mpcd_get_layout(mpcd_ctx c, int32_t tile[3], int64_t* n_tiles, int64
   if (n_tiles) *n_tiles = c->S.ntiles;
   if (capacity) *capacity = c->S.cap;
   if (regrows) *regrows = c->regrows;
+  return MPCD_OK;
+}
+
+mpcd_status mpcd_handover_stats(mpcd_ctx c, int64_t* kept, int64_t* given_up) {
+  ST_TRY(check_ctx(c));
+  if (kept) *kept = (int64_t)c->handovers[0];
+  if (given_up) *given_up = (int64_t)c->handovers[1];
+  return MPCD_OK;
+}
+
+mpcd_status mpcd_set_graph(mpcd_ctx c, int32_t on) {
+  ST_TRY(check_ctx(c));
+  if (on != 0 && on != 1) return fail(MPCD_EINVAL, "on must be 0 or 1");
+  if (on && (c->stream == nullptr || c->stream == hipStreamPerThread))
+    return fail(MPCD_EINVAL, "graph launches need a stream other than the null or per-thread stream");
+  c->graph = on != 0;
+  return MPCD_OK;
+}
+
+mpcd_status mpcd_graph_stats(mpcd_ctx c, int64_t* instantiations, int64_t* updates) {
+  ST_TRY(check_ctx(c));
+  if (instantiations) *instantiations = (int64_t)c->graph_inst;
+  if (updates) *updates = (int64_t)c->graph_upd;
   return MPCD_OK;
 }
 

@@ -16,18 +16,13 @@ import threading
 
 from . import binding
 
-# device bytes per particle of a context (two slab buffers with 45 % headroom
-# per tile, the one-byte local cell) and per cell (thermostat draws, the
-# velocity-field readback), plus a fixed part for counters and tables
-_BYTES_PER_PARTICLE = {binding.FP32: 2 * 33 * 1.45, binding.FP64: 2 * 53 * 1.45}
-_BYTES_PER_CELL = 8 * 2 + 96
-_BYTES_FIXED = 1 << 22
-
-
-def footprint(n_particles, n_cells, precision=binding.FP32):
-    """Device bytes a context of this size holds (an upper estimate)."""
-    ncell = int(n_cells[0]) * int(n_cells[1]) * int(n_cells[2])
-    return int(n_particles * _BYTES_PER_PARTICLE[precision] + ncell * _BYTES_PER_CELL + _BYTES_FIXED)
+def footprint(n_particles, n_cells, precision=binding.FP32, steps=1):
+    """Device bytes a request's context takes at its peak (mpcd_footprint:
+    the library's own allocation rules, host arrays uploaded and the
+    velocity field read back)."""
+    peak, _ = binding.footprint(n_cells, n_particles, nsteps=steps, precision=precision,
+                                host_arrays=True)
+    return peak
 
 
 class Request:
@@ -42,7 +37,7 @@ class Request:
         self.make = make
         self.precision = precision
         self.sim_kw = sim_kw
-        self.bytes = footprint(self.n_particles, self.n_cells, precision)
+        self.bytes = footprint(self.n_particles, self.n_cells, precision, self.steps)
 
 
 def run_request(req):

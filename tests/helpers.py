@@ -1,4 +1,6 @@
 """Shared helpers of the GPU parity tests: tolerances and comparisons."""
+import ctypes
+
 import numpy as np
 
 # Velocity tolerance of the FP64 form: per particle,
@@ -71,3 +73,32 @@ def fp32_step_matches(gpos0, gvel0, gpos1, gvel1, gcells1, mass, p, step, fp32fo
 
 def banner(msg):
     print(f"[gpu-test] {msg}", flush=True)
+
+
+class PoolHighWater:
+    """High-water mark of the device's default stream-ordered memory pool
+    (where the library's allocations come from), read through the HIP
+    runtime that torch loaded."""
+
+    def __init__(self):
+        import torch
+        torch.cuda.init()
+        self.hip = ctypes.CDLL("libamdhip64.so")
+        self.pool = ctypes.c_void_p()
+        dev = torch.cuda.current_device()
+        assert self.hip.hipDeviceGetDefaultMemPool(ctypes.byref(self.pool), dev) == 0
+
+    def reset(self):
+        zero = ctypes.c_uint64(0)
+        assert self.hip.hipMemPoolSetAttribute(self.pool, 8, ctypes.byref(zero)) == 0  # UsedMemHigh
+
+    def used(self, attr):
+        v = ctypes.c_uint64(0)
+        assert self.hip.hipMemPoolGetAttribute(self.pool, attr, ctypes.byref(v)) == 0
+        return v.value
+
+    def current(self):
+        return self.used(7)  # UsedMemCurrent
+
+    def high(self):
+        return self.used(8)  # UsedMemHigh since the last reset

@@ -1,15 +1,19 @@
 """Solutes moved by an external MD integrator between collisions and coupled
 to the solvent only in the collision (sec. 3.6; MPCD_FLAG_MD_SOLUTE with
 mpcd_set_embedded / mpcd_get_embedded), against the oracle doing the same
-sequence: MD for one collision time, stream the solvent only, collide all."""
+sequence: MD for one collision time, stream the solvent only, collide all.
+A handover after mpcd_step moves the solutes into the prepared binning of
+the next step (O(solutes)); it must give what binning everything afresh
+gives, bit for bit, also when solutes jump across the box, crowd into one
+tile, or overflow a slab (the prepared binning is then given up)."""
 import numpy as np
 import pytest
 
 import paper_1801_10187_amd as m
 import workloads
-from helpers import FP64_REL, banner, periodic_dist, vel_err_fp64
+from helpers import FP64_REL, banner, f32_close, periodic_dist, vel_err_fp64
 from md_chain import verlet
-from oracle import srd
+from oracle import fp32form, srd
 
 pytestmark = pytest.mark.gpu
 
@@ -34,6 +38,8 @@ def test_md_coupled_chains_match_the_oracle():
             s.step(1)
             gb_pos, gb_vel = s.get_embedded()
         gpos, gvel = s.get_state()
+        # every handover after the first step went into the prepared binning
+        assert s.handover_stats() == (cycles - 1, 0)
     # oracle: the same sequence
     opos, ovel = np.concatenate([pos, bpos]), np.concatenate([vel, bvel])
     for c in range(cycles):
@@ -101,3 +107,101 @@ def test_md_exchange_on_device_buffers():
         pa, va = a.get_state()
         pb, vb = b.get_state()
     assert np.array_equal(pa, pb) and np.array_equal(va, vb)
+
+
+def _jumping_run(prec, n_cells, rho, nb, seed, cycles, fresh, crowd_at=None, thermo=True):
+    """MD-flagged context whose solutes jump to new random places before each
+    collision (crowd_at: the cycle from which all of them sit in one cell).
+    fresh: before each handover the prepared binning is given up (a step
+    counter changed and restored), so the next step bins everything."""
+    rng = np.random.default_rng(seed)
+    L = np.array(n_cells, dtype=np.float64)
+    pos, vel = workloads.fluid(n_cells, rho, seed=seed + 1)
+    bpos = rng.random((nb, 3)) * L
+    bvel = rng.normal(size=(nb, 3)) * 0.4
+    bmass = np.full(nb, 3.0)
+    with m.Sim(pos, vel, n_cells, seed=seed + 2, thermostat=thermo, precision=prec,
+               emb_pos=bpos, emb_vel=bvel, emb_mass=bmass,
+               flags=m.binding.FLAG_MD_SOLUTE) as s:
+        for c in range(cycles):
+            if crowd_at is not None and c >= crowd_at:
+                hp = 2.0 + 0.999 * rng.random((nb, 3))
+            else:
+                hp = rng.random((nb, 3)) * L
+            hv = rng.normal(size=(nb, 3)) * 0.4
+            if fresh:
+                s.step_count = s.step_count + 1
+                s.step_count = s.step_count - 1
+            s.set_embedded(hp, hv)
+            s.step(1)
+            ep, _ = s.get_embedded()
+            if prec == m.FP64:
+                assert np.array_equal(ep, hp)      # solutes are not streamed
+        st = s.get_state()
+        cells = s.get_cells()
+        return st, cells, s.handover_stats(), s.layout()[3]
+
+
+@pytest.mark.parametrize("prec", [m.FP64, m.FP32])
+def test_handover_jumping_solutes_equal_fresh_binning(prec):
+    """300 solutes jumping anywhere in a 10^3 box every cycle (most change
+    tile, several leave or enter one tile at once): six cycles with the
+    handover give the state of the same cycles binned afresh, bit for bit."""
+    banner(f"handover, jumping solutes, prec {prec}")
+    a = _jumping_run(prec, (10, 10, 10), 6.0, 300, 81, 6, fresh=False)
+    b = _jumping_run(prec, (10, 10, 10), 6.0, 300, 81, 6, fresh=True)
+    for x, y in zip(a[0] + a[1], b[0] + b[1]):
+        assert np.array_equal(x, y)
+    assert a[2] == (5, 0) and b[2] == (0, 0)
+
+
+def test_handover_full_slab_gives_the_binning_up():
+    """From the third cycle all 600 solutes are put into one cell, more than
+    its tile's slab holds beside the solvent: that handover gives the
+    prepared binning up (the next step enlarges the slabs), the later ones
+    fit again; results equal the fresh binning's bit for bit."""
+    banner("handover, full slab")
+    a = _jumping_run(m.FP64, (8, 8, 8), 5.0, 600, 85, 5, fresh=False, crowd_at=2)
+    b = _jumping_run(m.FP64, (8, 8, 8), 5.0, 600, 85, 5, fresh=True, crowd_at=2)
+    for x, y in zip(a[0] + a[1], b[0] + b[1]):
+        assert np.array_equal(x, y)
+    kept, given_up = a[2]
+    assert given_up == 1 and kept == 3
+    assert a[3] >= 1     # the slabs were enlarged
+
+
+def test_md_coupled_chains_fp32_each_cycle():
+    """The FP32 form with MD-coupled chains: every cycle (handover into the
+    prepared binning, one step) checked element by element against the FP32
+    emulation of that step from the GPU's state after the handover (solvent
+    streamed, solutes not): cells and positions bit-exact, velocities within
+    one ulp or 2^-40."""
+    banner("md-coupled chains, fp32, each cycle")
+    p = srd.Params((10, 10, 10), seed=86, thermostat=True, kT=1.0)
+    chains, clen = 6, 12
+    pos, vel = workloads.fluid(p.n_cells, 6, seed=87)
+    bpos, bvel, bmass = workloads.beads(p.n_cells, chains, clen, seed=88)
+    ns = pos.shape[0]
+    mass = np.concatenate([np.ones(ns), bmass])
+    gb_pos, gb_vel = bpos.copy(), bvel.copy()
+    with m.Sim(pos, vel, p.n_cells, seed=p.seed, kT=p.kT, thermostat=True, precision=m.FP32,
+               emb_pos=bpos, emb_vel=bvel, emb_mass=bmass,
+               flags=m.binding.FLAG_MD_SOLUTE) as s:
+        for c in range(5):
+            gb_pos, gb_vel = verlet(gb_pos, gb_vel, bmass, clen, p.L, p.dt / 10, 10)
+            s.set_embedded(gb_pos, gb_vel)
+            gpos0, gvel0 = s.get_state()
+            s.step(1)
+            gpos1, gvel1 = s.get_state()
+            gcells1, _ = s.get_cells()
+            h, o, v = fp32form.from_double(gpos0, gvel0, p)
+            assert np.array_equal(fp32form.to_double(h, o, p), gpos0)
+            hs, os_ = fp32form.stream32(h[:ns], o[:ns], v[:ns], p)
+            h1 = np.concatenate([hs, h[ns:]])
+            o1 = np.concatenate([os_, o[ns:]])
+            v1, info = fp32form.collide32(h1, o1, v, mass, p, c)
+            assert np.array_equal(gcells1, info["cell"])
+            assert np.array_equal(gpos1, fp32form.to_double(h1, o1, p))
+            assert np.all(f32_close(gvel1, v1))
+            gb_pos, gb_vel = s.get_embedded()
+        assert s.handover_stats() == (4, 0)

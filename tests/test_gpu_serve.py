@@ -8,7 +8,7 @@ import pytest
 
 import paper_1801_10187_amd as m
 import workloads
-from helpers import banner
+from helpers import PoolHighWater, banner
 from paper_1801_10187_amd.serve import Request, Server, run_request
 
 pytestmark = pytest.mark.gpu
@@ -38,15 +38,50 @@ def test_results_alone_and_in_the_mix(budget):
     reqs = _requests()
     alone = [run_request(r) for r in reqs]
     limit = None if budget == "device" else 2 * max(r.bytes for r in reqs)
+    hw = PoolHighWater()
+    assert hw.current() == 0
+    hw.reset()
     with Server(workers=4, memory_budget=limit) as srv:
         futs = [srv.submit(r) for r in reqs]
         got = [f.result(timeout=120) for f in futs]
+    print(f"requests in flight at most {srv.max_inflight}, admitted bytes at most "
+          f"{srv.max_inflight_bytes}, pool high-water {hw.high()}")
     assert srv.max_inflight > 1
+    # the device memory the requests held together never exceeded what the
+    # server admitted them for
+    assert hw.high() <= srv.max_inflight_bytes
     if limit is not None:
         assert srv.max_inflight_bytes <= limit
     for (u0, m0), (u1, m1) in zip(alone, got):
         assert np.array_equal(m0, m1)
         assert np.array_equal(u0, u1)
+
+
+@pytest.mark.parametrize("case", [((12, 12, 12), 8.0, m.FP32, False),
+                                  ((50, 50, 50), 8.0, m.FP32, True),
+                                  ((30, 30, 30), 10.0, m.FP64, True),
+                                  ((40, 40, 40), 2.5, m.FP64, False)])
+def test_footprint_bounds_the_pool(case):
+    """One request run alone (create from host arrays, steps, velocity
+    field, destroy): the stream-ordered pool's high-water mark stays within
+    the request's footprint, and for boxes of 10^5 particles and more above
+    85 % of it (the estimate is not loose)."""
+    n_cells, rho, prec, thermo = case
+    banner(f"footprint {n_cells} rho {rho} {'fp64' if prec == m.FP64 else 'fp32'}")
+    npart = int(round(rho * np.prod(n_cells)))
+    req = Request(n_cells, npart, 25, lambda: workloads.fluid(n_cells, rho, seed=7),
+                  precision=prec, seed=8, thermostat=thermo)
+    hw = PoolHighWater()
+    assert hw.current() == 0
+    hw.reset()
+    run_request(req)
+    used = hw.high()
+    print(f"{npart} particles: pool high-water {used} B, footprint {req.bytes} B "
+          f"({used / req.bytes:.3f})")
+    assert hw.current() == 0
+    assert used <= req.bytes
+    if npart >= 100_000:
+        assert used > 0.85 * req.bytes
 
 
 def test_serving_stream_full_range():

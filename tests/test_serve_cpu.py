@@ -6,8 +6,12 @@ cancelled."""
 import threading
 import time
 
+import math
+
 import pytest
 
+from paper_1801_10187_amd import binding
+from paper_1801_10187_amd.binding import FP32, FP64
 from paper_1801_10187_amd.serve import Request, Server, footprint
 
 
@@ -36,7 +40,27 @@ def _req(i, n):
 def test_footprint_grows_with_the_box():
     assert footprint(10**6, (100, 100, 100)) > footprint(10**5, (100, 100, 100))
     assert footprint(10**6, (100, 100, 100)) > footprint(10**6, (10, 10, 10))
-    assert 90e6 < footprint(10**6, (50, 50, 50)) < 130e6
+    assert footprint(10**6, (50, 50, 50), precision=FP64) > footprint(10**6, (50, 50, 50))
+
+
+def test_footprint_follows_the_slab_rule():
+    """10^6 particles in 50^3 cells (density 8: 4 x 4 x 4 tiles, 13^3 of
+    them, those at the far faces cut to 2 cells along the axis): slabs sized
+    for a whole tile's mean occupancy (512) plus five standard deviations,
+    +20 % (at least the mean over all tiles + 8 sigma + 64), rounded up to
+    32; two slab buffers of 33 (FP32) or 53 (FP64) bytes per slot; at the
+    peak the 48-byte-per-particle upload buffer beside them. The rest
+    (counters and tables, a few hundred kB here) within 2 MB."""
+    n, nt = 10**6, 13 ** 3
+    mean = n / nt
+    mx = math.ceil(512 + 5 * math.sqrt(512))
+    cap = -(-max(mx + mx // 5, int(mean + 8 * math.sqrt(mean) + 64)) // 32) * 32
+    for prec, rec in ((FP32, 33), (FP64, 53)):
+        peak, held = binding.footprint((50, 50, 50), n, nsteps=10, precision=prec)
+        slabs = 2 * rec * nt * cap
+        assert slabs < held < slabs + 2e6
+        assert slabs + 48 * n < peak < slabs + 48 * n + 2e6
+        assert footprint(n, (50, 50, 50), prec) == peak
 
 
 def test_fifo_budget_results_and_errors():

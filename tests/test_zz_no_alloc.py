@@ -4,14 +4,13 @@ on calls one after another (the second with a smaller input, so that what
 the library's shared grid-shift table keeps from the first call must not
 leak into it), its size limit, and the roll-back after a full slab.
 """
-import ctypes
 
 import numpy as np
 import pytest
 
 import paper_1801_10187_amd as m
 import workloads
-from helpers import banner
+from helpers import PoolHighWater, banner
 
 pytestmark = pytest.mark.gpu
 
@@ -36,35 +35,6 @@ def _same_state(a, b):
     cb, nb = b.get_cells()
     assert np.array_equal(ca, cb) and np.array_equal(na, nb)
     assert a.step_count == b.step_count
-
-
-class _PoolHighWater:
-    """High-water mark of the device's default stream-ordered memory pool
-    (where the library's allocations come from), read through the HIP
-    runtime that torch loaded."""
-
-    def __init__(self):
-        import torch
-        torch.cuda.init()
-        self.hip = ctypes.CDLL("libamdhip64.so")
-        self.pool = ctypes.c_void_p()
-        dev = torch.cuda.current_device()
-        assert self.hip.hipDeviceGetDefaultMemPool(ctypes.byref(self.pool), dev) == 0
-
-    def reset(self):
-        zero = ctypes.c_uint64(0)
-        assert self.hip.hipMemPoolSetAttribute(self.pool, 8, ctypes.byref(zero)) == 0  # UsedMemHigh
-
-    def used(self, attr):
-        v = ctypes.c_uint64(0)
-        assert self.hip.hipMemPoolGetAttribute(self.pool, attr, ctypes.byref(v)) == 0
-        return v.value
-
-    def current(self):
-        return self.used(7)  # UsedMemCurrent
-
-    def high(self):
-        return self.used(8)  # UsedMemHigh since the last reset
 
 
 @pytest.mark.parametrize("form", ["fp32", "fp64"])
@@ -92,7 +62,7 @@ def test_noalloc_allocates_nothing():
     """The default pool's high-water mark does not move during the call
     (mpcd_step, whose shift table grows on demand, does move it)."""
     banner("noalloc allocates nothing")
-    hw = _PoolHighWater()
+    hw = PoolHighWater()
     a, b = _pair((16, 16, 16), 10, 7, m.FP32)
     with a, b:
         a.step(2)
