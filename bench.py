@@ -9,7 +9,12 @@ The headline value is the FP32 cell-relative form; the plain FP64 form runs on
 the same input and is reported beside it, and so does the Andersen-thermostat
 collision rule (eq. 4) in both forms (without the cell thermostat, which that
 rule replaces). A step is one whole pass of the hot
-path: stream, grid shift, binning, cell reduction, draws and rotation.
+path: stream, grid shift, binning, cell reduction, draws and rotation. The
+line also carries: the same FP32 call launched as one HIP graph
+(`graph_vs_stream`); the FP32 form's error and observables against the FP64
+form; the copy ceiling; the latencies of the 256-box batch below
+(`batch_latency`: single-step and 500-step calls, p50/p99; --no-batch leaves
+it out); and the oracle's CPU baselines.
 
     python bench.py --workload srd_20c_rho5_fp64
 
@@ -114,13 +119,13 @@ def measured_traffic(form, workload=WORKLOAD):
     / WRITE_SIZE runs recorded in profiles/traffic.json, scaled by the copy
     calibration stated there; None unless they were taken on the current
     kernel sources."""
-    from paper_1801_10187_amd.build import source_hash
+    from paper_1801_10187_amd.build import kernel_hash
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if rec.get("source_hash") != source_hash():
+    if rec.get("kernel_hash") != kernel_hash():
         return None
     return rec.get("bytes_per_launch", {}).get(workload, {}).get(form)
 
@@ -304,6 +309,87 @@ def fp32_accuracy(m, inp, cfg):
             "velocity_rms": float(np.sqrt(np.mean(dv * dv))),
             "velocity_max_rel": float((np.abs(dv) / np.maximum(vs, 1.0)).max()),
             "position_max_abs": float(np.abs(dx).max())}
+
+
+def fp32_observables(m, inp, cfg, steps=200):
+    """Observables of the FP32 form against the FP64 form after `steps`
+    steps from the same input, both on the GPU (the FP64 form agrees with
+    the FP64 oracle to 1e-12; the FP32 form against the oracle itself over
+    1000 steps is tests/test_gpu_observables.py): kinetic temperature,
+    kurtosis of the velocity components (3 for Maxwell-Boltzmann), net
+    momentum per particle (change since the start), the occupancy histogram
+    of the collision cells (total variation distance between the forms)."""
+    pos, vel, bpos, bvel, bmass = inp
+    obs = {}
+    for name, prec in (("fp32", m.FP32), ("fp64", m.FP64)):
+        with m.Sim(pos, vel, cfg["n_cells"], kT=cfg["kT"], seed=cfg["seed"], precision=prec,
+                   thermostat=cfg["thermostat"], emb_pos=bpos, emb_vel=bvel,
+                   emb_mass=bmass) as s:
+            _, v0 = s.get_state()
+            P0 = v0.sum(axis=0)
+            del v0
+            s.step(steps)
+            _, v = s.get_state()
+            _, counts = s.get_cells()
+        n = v.shape[0]
+        P = v.sum(axis=0)
+        dv = v - P / n
+        m2 = (dv * dv).mean(axis=0)
+        m4 = (dv ** 4).mean(axis=0)
+        hist = np.bincount(counts, minlength=64)[:64] / counts.size
+        obs[name] = {"T": float(m2.sum() / 3.0 * n / (n - 1)),
+                     "kurtosis": float((m4 / (m2 * m2)).mean()),
+                     "momentum_change_per_particle": float(np.abs(P - P0).max() / n),
+                     "_hist": hist}
+        del v, dv
+    tvd = 0.5 * float(np.abs(obs["fp32"]["_hist"] - obs["fp64"]["_hist"]).sum())
+    for o in obs.values():
+        del o["_hist"]
+    return {"what": f"{steps} steps from the same input, FP32 form and FP64 form on the GPU",
+            "fp32": obs["fp32"], "fp64": obs["fp64"],
+            "T_diff": obs["fp32"]["T"] - obs["fp64"]["T"],
+            "kurtosis_diff": obs["fp32"]["kurtosis"] - obs["fp64"]["kurtosis"],
+            "occupancy_tvd": tvd}
+
+
+def batch_latency(m, workloads, cfg, calls=5, singles=100, warmup=20):
+    """The 256-box batch's latencies for the line of the default workload
+    (the metric's "p99 batch latency"): single-step calls and whole
+    `cfg["steps"]`-step calls, each waited for, on the stream; every box
+    completes with its call's last launch."""
+    steps = cfg["steps"]
+    boxes = workloads.replica_inputs(workloads.replica_boxes(cfg["n_rep"], seed=cfg["seed"]))
+    N = sum(b["pos"].shape[0] for b in boxes)
+    bt = m.Batch(boxes, precision=m.FP32, thermostat=cfg["thermostat"])
+    del boxes
+    try:
+        bt.step(warmup)
+        bt.sync()
+        one = []
+        for _ in range(singles):
+            a = time.perf_counter()
+            bt.step(1)
+            bt.sync()
+            one.append(time.perf_counter() - a)
+        bt.step(steps)
+        bt.sync()
+        whole = []
+        for _ in range(calls):
+            a = time.perf_counter()
+            bt.step(steps)
+            bt.sync()
+            whole.append(time.perf_counter() - a)
+    finally:
+        bt.close()
+    one_ms, whole_ms = 1e3 * np.array(one), 1e3 * np.array(whole)
+    return {"workload": "srd_batch256_fp32", "boxes": cfg["n_rep"], "particles": N, "form": "fp32",
+            "step_call_ms": {"p50": float(np.percentile(one_ms, 50)),
+                             "p99": float(np.percentile(one_ms, 99)), "calls": singles},
+            f"call_{steps}_steps_ms": {"p50": float(np.percentile(whole_ms, 50)),
+                                       "p99": float(np.percentile(whole_ms, 99)), "calls": calls},
+            "updates_per_s": N * steps / float(np.median(whole)),
+            "what": "mpcd_step calls on the whole batch, each waited for; every box "
+                    "completes with its call"}
 
 
 def bench_batch(m, workloads, cfg, args):
@@ -568,6 +654,8 @@ def main():
                              "srd_batch256_fp32", "srd_serve_poisson50", "srd_400c_rho5_md"])
     ap.add_argument("--serve-workers", type=int, default=8,
                     help="host threads serving requests (srd_serve_poisson50)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="leave the 256-box batch latencies out of the default workload's line")
     ap.add_argument("--batch-calls", type=int, default=12,
                     help="timed whole calls per launch mode (srd_batch256_fp32)")
     ap.add_argument("--copy-only", action="store_true",
@@ -668,6 +756,11 @@ def main():
                       "step_floor_frac": r["step_floor_frac"], "kT_end": r["kT"],
                       "net_momentum_end": r["net_momentum"]} for f, r in res.items()},
     }
+    if wl == WORKLOAD and not args.no_batch:
+        out["batch_latency"] = batch_latency(m, workloads, workloads.CONFIGS["srd_batch256_fp32"])
+        b = out["batch_latency"]
+        print(f"[bench] batch: step call p99 {b['step_call_ms']['p99']:.3f} ms, "
+              f"{b['updates_per_s']:.4g} updates/s", file=sys.stderr, flush=True)
     copies = copy_ceiling(m)
     out["copy_ceiling_GBs"] = copies["max"]
     out["copies_GBs"] = copies
@@ -675,6 +768,7 @@ def main():
     if "fp32" in res and "fp64" in res:
         out["fp32_over_fp64"] = res["fp32"]["updates_per_s"] / res["fp64"]["updates_per_s"]
         out["fp32_accuracy"] = fp32_accuracy(m, inp, cfg)
+        out["fp32_observables"] = fp32_observables(m, inp, cfg)
     for base in ("fp32", "fp64"):  # the AT rule against the thermostatted SRD step
         if base in res and base + "_at" in res:
             out[base + "_at_over_srd"] = res[base + "_at"]["updates_per_s"] / res[base]["updates_per_s"]

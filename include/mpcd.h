@@ -108,6 +108,12 @@ typedef struct {
  * solvent. */
 #define MPCD_FLAG_MD_SOLUTE 2
 
+/* Test hook for the error paths: after `after` more successful device
+ * allocations by the library (any context, any thread), the next `count`
+ * fail as if the device were out of memory; after < 0 or count <= 0 turns
+ * failures off. Not for production use. */
+mpcd_status mpcd_debug_fail_allocs(int64_t after, int64_t count);
+
 /* Tile shape (the cells a block of the step kernel collides together and
  * whose particles share a slab), in bits 8-10 of flags: 0 chooses by the
  * box's mean density (rho >= 11: 4x4x2 cells, >= 3.5: 4x4x4, >= 1.75:
@@ -197,7 +203,12 @@ mpcd_status mpcd_collide(mpcd_ctx ctx);
  * MPCD_FLAG_MD_SOLUTE, which it moves into the prepared binning) and a
  * changed step counter give the prepared binning up (the next mpcd_step
  * then streams and bins first), as does a slab overflow in that launch.
- * Results never depend on how a run is split into calls. */
+ * Results never depend on how a run is split into calls.
+ * If a slab overflows and cannot be enlarged (MPCD_ENOMEM), the context is
+ * rolled back to the input of the launch that overflowed: the state before
+ * the call, or step s streamed and binned but not yet collided (then
+ * mpcd_get_step returns s and mpcd_collide completes it); the error text
+ * says which. */
 mpcd_status mpcd_step(mpcd_ctx ctx, int64_t nsteps);
 
 /* For callers that cannot allocate (tight serving loops, harnesses that

@@ -95,6 +95,7 @@ def load():
         "mpcd_totals": (st, [_P, _P, _D, _D]),
         "mpcd_sync": (st, [_P]),
         "mpcd_get_sizes": (st, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+        "mpcd_debug_fail_allocs": (st, [ctypes.c_int64, ctypes.c_int64]),
         "mpcd_handover_stats": (st, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(ctypes.c_int64)]),
         "mpcd_set_graph": (st, [ctypes.c_void_p, ctypes.c_int32]),
@@ -404,6 +405,12 @@ class Batch(Sim):
         kT = np.empty(self.n_boxes)
         _check(load().mpcd_box_totals(self._ctx, _ptr(p), _ptr(ke), _ptr(kT)))
         return p, ke, kT
+
+
+def debug_fail_allocs(after, count=1):
+    """Test hook: after `after` more device allocations, `count` fail
+    (mpcd_debug_fail_allocs; after < 0 turns it off)."""
+    _check(load().mpcd_debug_fail_allocs(int(after), int(count)))
 
 
 def footprint(n_cells, n_particles, nsteps=1, precision=FP32, host_arrays=True, **kw):

@@ -43,6 +43,18 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
+def kernel_hash():
+    """SHA-256 over the device-code sources only (the kernels and their
+    launch shapes): identifies the kernels a counter measurement was taken
+    on, unchanged by host-side edits."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in DEPS[1:3]:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose=False):
     """Compile the library (always; a fresh build each call)."""
     tmp = LIB + ".tmp"

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -31,6 +32,20 @@ namespace {
 
 thread_local std::string g_err;
 
+// Allocation-failure injection for tests of the cleanup paths: after
+// g_fail_after more successful device allocations, g_fail_count fail.
+std::atomic<int64_t> g_fail_after{-1}, g_fail_count{0};
+
+bool inject_alloc_failure() {
+  if (g_fail_after.load() < 0) return false;
+  if (g_fail_after.fetch_sub(1) > 0) return false;
+  g_fail_after.store(0);
+  if (g_fail_count.fetch_sub(1) > 0) return true;
+  g_fail_after.store(-1);
+  g_fail_count.store(0);
+  return false;
+}
+
 mpcd_status fail(mpcd_status st, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -45,7 +60,8 @@ mpcd_status fail(mpcd_status st, const char* fmt, ...) {
   do {                                                                             \
     hipError_t e_ = (expr);                                                        \
     if (e_ != hipSuccess)                                                          \
-      return fail(MPCD_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+      return fail(e_ == hipErrorOutOfMemory ? MPCD_ENOMEM : MPCD_EHIP,             \
+                  "%s failed: %s", #expr, hipGetErrorString(e_));                  \
   } while (0)
 
 #define ST_TRY(expr)                    \
@@ -149,7 +165,13 @@ struct mpcd_ctx_s {
   // Device memory comes from the stream-ordered allocator on the context's
   // stream: allocating and freeing never waits for the whole device, so
   // contexts on other streams (concurrent requests) keep running.
-  hipError_t alloc(void** q, size_t bytes) { return hipMallocAsync(q, bytes ? bytes : 256, stream); }
+  hipError_t alloc(void** q, size_t bytes) {
+    if (inject_alloc_failure()) {
+      *q = nullptr;
+      return hipErrorOutOfMemory;
+    }
+    return hipMallocAsync(q, bytes ? bytes : 256, stream);
+  }
   void release(void* q) {
     if (q) (void)hipFreeAsync(q, stream);
   }
@@ -518,6 +540,33 @@ mpcd_status launch_graph(mpcd_ctx c, const std::vector<Launch>& L, size_t from,
   return MPCD_OK;
 }
 
+// A launch overflowed a slab and the slabs could not be enlarged: return to
+// that launch's input (cur, ci), which it and every later launch of the call
+// left intact, and clear the counts it added to. A stream + bin launch's
+// input is the state before the call (or, for mpcd_bin, the streamed
+// state); a collision's input is its step binned and not yet collided.
+mpcd_status rollback_to_input(mpcd_ctx c, int cur, int ci, const Launch& l) {
+  c->cur = cur;
+  c->ci = ci;
+  c->pre = false;
+  c->split = false;
+  if (l.op == Op::BinStream) {
+    c->phase = Phase::Idle;
+  } else if (l.op == Op::Bin) {
+    c->phase = Phase::Streamed;
+  } else {
+    c->phase = Phase::Binned;
+    c->step = l.step;
+    c->have_bin = true;
+    c->last_bin_step = l.step;
+  }
+  const uint32_t st_reset[2] = {0u, 0xFFFFFFFFu};
+  HIP_TRY(hipMemsetAsync(c->cnt[(c->ci + 1) % 3], 0, (size_t)c->S.ntiles * 4, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->status + 1, st_reset, 8, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return MPCD_OK;
+}
+
 // Run a list of tile launches, then confirm that no slab overflowed; replay
 // from the failing launch after enlarging the slabs if one did.
 mpcd_status run_launches(mpcd_ctx c, const std::vector<Launch>& L) {
@@ -538,7 +587,15 @@ mpcd_status run_launches(mpcd_ctx c, const std::vector<Launch>& L) {
     HIP_TRY(hipStreamSynchronize(c->stream));
     if (st[1] == 0) return MPCD_OK;
     const size_t bad = std::min<size_t>(st[2], in_state.size() - 1);
-    ST_TRY(regrow(c, in_state[bad].first, in_state[bad].second));
+    const mpcd_status rs = regrow(c, in_state[bad].first, in_state[bad].second);
+    if (rs != MPCD_OK) {
+      const std::string why = g_err;
+      ST_TRY(rollback_to_input(c, in_state[bad].first, in_state[bad].second, L[from + bad]));
+      return fail(rs, "%s; the state is %s", why.c_str(),
+                  c->phase == Phase::Binned ? "the failing step binned, awaiting mpcd_collide"
+                  : c->phase == Phase::Streamed ? "streamed, awaiting mpcd_bin"
+                                                : "the one before the call");
+    }
     from += bad;
   }
   return fail(MPCD_ENOMEM, "slab capacity kept overflowing");
@@ -1617,6 +1674,17 @@ mpcd_status mpcd_get_layout(mpcd_ctx c, int32_t tile[3], int64_t* n_tiles, int64
   if (n_tiles) *n_tiles = c->S.ntiles;
   if (capacity) *capacity = c->S.cap;
   if (regrows) *regrows = c->regrows;
+  return MPCD_OK;
+}
+
+mpcd_status mpcd_debug_fail_allocs(int64_t after, int64_t count) {
+  if (after < 0 || count <= 0) {
+    g_fail_after.store(-1);
+    g_fail_count.store(0);
+    return MPCD_OK;
+  }
+  g_fail_count.store(count);
+  g_fail_after.store(after);
   return MPCD_OK;
 }
 

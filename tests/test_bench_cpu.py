@@ -38,9 +38,9 @@ def test_algorithmic_bytes():
 
 def test_measured_traffic_is_tied_to_the_sources():
     rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
-    from paper_1801_10187_amd.build import source_hash
+    from paper_1801_10187_amd.build import kernel_hash
     got = bench.measured_traffic("fp32")
-    if rec.get("source_hash") == source_hash():
+    if rec.get("kernel_hash") == kernel_hash():
         assert got == rec["bytes_per_launch"]["srd_100c_rho10_mbthermo"]["fp32"]
         # the counters read close to the layout's bytes (no wasted re-reads)
         assert 1.0 < got / (64.0 * 1e7) < 1.1
