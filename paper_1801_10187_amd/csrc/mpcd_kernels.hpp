@@ -586,13 +586,15 @@ __device__ inline double gamma_finish(uint32_t nc, uint32_t cell, uint32_t step,
 // particle draws a random velocity dv in the gather, the cell sums gain
 // sum m dv, and the update is v <- (u + dv) - sum m dv / M.
 // Register targets (waves per SIMD) of the FP32 rotation kernels, measured:
-// 64-cell tiles seven (72 VGPRs; at the same occupancy the schedule the
-// compiler then picks runs the thermostatted step ~3 % faster), thermostatted
-// 128-cell tiles six (86 -> 80 VGPRs, a few spilled dwords; ~3 % faster).
+// 64-cell tiles eight (64 VGPRs, with the LDS of a block under 20 KB so that
+// eight blocks fit a CU: the thermostatted step ~1.4 % faster than at seven,
+// though a few dwords spill; with embedded particles the compiler cannot
+// meet eight and seven is kept), thermostatted 128-cell tiles six (86 -> 80
+// VGPRs, a few spilled dwords; ~3 % faster).
 template <int FORM, int CPT, int MODE, bool STREAM_IN, bool THERMO, bool EMB, bool ATR>
 constexpr int tile_waves_per_eu() {
   if (FORM != MPCD_FP32 || ATR) return 1;
-  if (CPT == 64) return 7;
+  if (CPT == 64) return EMB ? 7 : 8;
   if (CPT == 128 && THERMO) return 6;
   return 1;
 }
@@ -625,12 +627,16 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
   __shared__ uint32_t s_cnt[CC];
   __shared__ double s_u[3][CC];
   __shared__ double s_ax[3][CC];  // per cell: the rotation axis (SRD) or the mean kick (AT)
-  __shared__ double s_xi[THERMO && MODE != MODE_DIAG ? CC : 1];
+
   // thermostat: attempts 0 and 1 of the cell's Gamma draw, normal g and log U
   // (-inf where the squeeze accepts), drawn before N_c is known; cells whose
   // draw is not decided by them (pending) and whether the block has any
-  __shared__ double s_gam[THERMO ? 2 * GPRE : 1][THERMO ? CC : 1];
-  __shared__ double s_ehat[THERMO ? CC : 1];
+  __shared__ double s_gam[THERMO ? 2 * GPRE : 2][THERMO ? CC : 1];
+  // the drawn energy and xi reuse the rows of the first two attempts: a cell's
+  // thread reads its column before it writes Ehat there, and xi is written
+  // barriers after the last read
+  auto& s_ehat = s_gam[0];
+  auto& s_xi = s_gam[1];
   __shared__ uint32_t s_pend[THERMO ? CC : 1];
   __shared__ uint32_t s_anyp;
   __shared__ uint32_t s_bincnt[27];
