@@ -45,9 +45,10 @@ throughput and request latency p50/p99.
 
     python bench.py --workload srd_400c_rho5_md
 
-couples the beads of the 400^3 box through an external MD integrator: per
-collision their state is handed over and read back on device buffers (50
-collisions), beside the same context stepped without the exchange.
+couples the beads of the 400^3 box to MD: per collision 50 velocity-Verlet
+steps of the bead chains on the device, the beads' state handed over and
+read back on device buffers (50 collisions), beside the integrator alone and
+the same context stepped without the exchange.
 
 Prints one JSON line. `roofline` is for the dominant kernel (the collide
 kernel), timed with HIP events on the library's own stream during the timed
@@ -563,35 +564,40 @@ def bench_serve(m, workloads, cfg, args, workers=8, stop_after=75.0):
 
 
 def bench_md(m, workloads, cfg, args):
-    """Solutes coupled through an external MD integrator (sec. 3.6): per
-    collision the beads' state is handed over (mpcd_set_embedded), one step
-    runs and the collided bead velocities come back (mpcd_get_embedded), on
-    device buffers. The integrator itself (forces) is the caller's; in its
-    place every bead moves by a fixed random displacement of up to 0.1 cell
-    per axis each cycle (one elementwise torch operation on the device, in
-    the timed cycle), so that some beads change tile as they would under MD.
-    The same context is then stepped without the exchange for comparison."""
+    """Solutes coupled through MD (sec. 3.6, sec. 4.3): per collision the
+    beads move by 50 velocity-Verlet steps of 0.002 (harmonic bonds along
+    each chain, the library's mpcd_md_verlet_chains, on the device), their
+    state is handed over (mpcd_set_embedded), one MPCD step runs and the
+    collided bead velocities come back (mpcd_get_embedded) -- all on device
+    buffers and one stream. Reported beside it: the integrator alone and the
+    same context stepping without the exchange."""
     import torch
     steps = cfg["steps"] if args.steps == 1000 else args.steps
     pos, vel, bpos, bvel, bmass = make_input(cfg)
     N = pos.shape[0] + bpos.shape[0]
+    clen, nchains = cfg["chain_len"], cfg["chains"]
     torch.cuda.init()
+    # one stream for the integrator and the context (the handle of torch's
+    # default stream is 0, for which the context would make its own stream)
+    md_stream = torch.cuda.Stream()
+    stream = md_stream.cuda_stream
     sim = m.Sim(pos, vel, cfg["n_cells"], kT=cfg["kT"], seed=cfg["seed"], precision=m.FP32,
                 thermostat=False, emb_pos=bpos, emb_vel=bvel, emb_mass=bmass,
-                flags=m.binding.FLAG_MD_SOLUTE)
+                flags=m.binding.FLAG_MD_SOLUTE, hip_stream=stream)
     del pos, vel
     dpos = torch.from_numpy(bpos).cuda()
     dvel = torch.from_numpy(bvel).cuda()
-    L = torch.tensor(cfg["n_cells"], dtype=torch.float64, device="cuda")
-    disp = (torch.rand(dpos.shape, generator=torch.Generator(device="cuda").manual_seed(cfg["seed"]),
-                       dtype=torch.float64, device="cuda") - 0.5) * 0.2
+    dmass = torch.from_numpy(bmass).cuda()
+    L = [float(x) for x in cfg["n_cells"]]
+    md_steps, md_dt = 50, 0.002
     torch.cuda.synchronize()
 
+    def integrate():
+        m.binding.md_verlet_chains(dpos.data_ptr(), dvel.data_ptr(), dmass.data_ptr(), nchains,
+                                   clen, L, md_dt, md_steps, hip_stream=stream)
+
     def cycle():
-        dpos.add_(disp)                   # stands in for the integrator's move
-        dpos.sub_(torch.floor(dpos / L) * L)
-        dpos.masked_fill_(dpos >= L, 0.0)
-        torch.cuda.current_stream().synchronize()
+        integrate()
         sim.set_embedded_device(dpos.data_ptr(), dvel.data_ptr())
         sim.step(1)
         sim.get_embedded_device(dpos.data_ptr(), dvel.data_ptr())
@@ -610,11 +616,18 @@ def bench_md(m, workloads, cfg, args):
         t1 = time.perf_counter()
         coll_ms, coll_n = sim.profile_read(0)
         bin_ms, bin_n = sim.profile_read(1)
+        sim.profile(False)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(md_stream)
+        for _ in range(10):
+            integrate()
+        e1.record(md_stream)
+        torch.cuda.synchronize()
+        md_ms = e0.elapsed_time(e1) / 10
         t2 = time.perf_counter()
         sim.step(steps)
         sim.sync()
         t3 = time.perf_counter()
-        sim.profile(False)
         handovers = sim.handover_stats()
     finally:
         sim.close()
@@ -628,12 +641,14 @@ def bench_md(m, workloads, cfg, args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "srd_400c_rho5_md", "n_cells": list(cfg["n_cells"]),
                    "particles": N, "density": cfg["density"], "embedded_beads": int(bpos.shape[0]),
-                   "coupling": "external MD, state exchanged on device every collision",
+                   "coupling": f"{md_steps} velocity-Verlet steps of {md_dt} per collision on the "
+                               "device (harmonic bonds), state exchanged on device every collision",
                    "thermostat": "none", "form": "fp32"},
         "roofline": roofline("fp32", N, int(np.prod(cfg["n_cells"])), avg_us),
         "bin_kernel_avg_us": 1e3 * bin_ms / max(bin_n, 1),
+        "md_integrator_ms": md_ms,
         "ms_per_step_without_exchange": 1e3 * plain,
-        "exchange_overhead_ms": 1e3 * (cyc - plain),
+        "exchange_overhead_ms": 1e3 * (cyc - plain) - md_ms,
         "handovers_kept_given_up": list(handovers),
     }
     print(json.dumps(out), flush=True)

@@ -114,6 +114,24 @@ typedef struct {
  * failures off. Not for production use. */
 mpcd_status mpcd_debug_fail_allocs(int64_t after, int64_t count);
 
+/* The MD side of the solute coupling (sec. 3.6; sec. 4.3 integrates its
+ * bead-spring chains by velocity Verlet, 50 MD steps of 0.002 per collision):
+ * nsteps velocity-Verlet steps of size dt for n_chains chains of chain_len
+ * beads with harmonic bonds U = k_bond/2 (|r_{i+1} - r_i| - bond_length)^2
+ * between consecutive beads (minimum image in the periodic box of edge
+ * lengths box[3]), no other forces. pos, vel: device arrays of
+ * n_chains * chain_len x 3 doubles, bead i of chain c in row
+ * c * chain_len + i, positions in [0, box) (kept there: wrapped after each
+ * drift); mass: n_chains * chain_len doubles (> 0). Updated in place,
+ * enqueued on hip_stream (NULL: the null stream), not waited for: the
+ * caller's mpcd_set_embedded on the same stream, or a synchronisation,
+ * orders it before the handover. One block per chain, one thread per bead.
+ * MPCD_EINVAL for chain_len outside 1..1024, negative counts, box lengths
+ * <= 0 or dt < 0. */
+mpcd_status mpcd_md_verlet_chains(double* pos, double* vel, const double* mass, int64_t n_chains,
+                                  int32_t chain_len, const double box[3], double k_bond,
+                                  double bond_length, double dt, int32_t nsteps, void* hip_stream);
+
 /* Tile shape (the cells a block of the step kernel collides together and
  * whose particles share a slab), in bits 8-10 of flags: 0 chooses by the
  * box's mean density (rho >= 11: 4x4x2 cells, >= 3.5: 4x4x4, >= 1.75:

@@ -95,6 +95,9 @@ def load():
         "mpcd_totals": (st, [_P, _P, _D, _D]),
         "mpcd_sync": (st, [_P]),
         "mpcd_get_sizes": (st, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+        "mpcd_md_verlet_chains": (st, [_P, _P, _P, ctypes.c_int64, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_double), ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_int32, _P]),
         "mpcd_debug_fail_allocs": (st, [ctypes.c_int64, ctypes.c_int64]),
         "mpcd_handover_stats": (st, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(ctypes.c_int64)]),
@@ -405,6 +408,17 @@ class Batch(Sim):
         kT = np.empty(self.n_boxes)
         _check(load().mpcd_box_totals(self._ctx, _ptr(p), _ptr(ke), _ptr(kT)))
         return p, ke, kT
+
+
+def md_verlet_chains(pos_ptr, vel_ptr, mass_ptr, n_chains, chain_len, box, dt, nsteps,
+                     k_bond=30.0, bond_length=0.97, hip_stream=None):
+    """mpcd_md_verlet_chains on device arrays (pointers): nsteps velocity-
+    Verlet steps of harmonic bead chains, in place, enqueued on hip_stream."""
+    b = (ctypes.c_double * 3)(*[float(x) for x in np.broadcast_to(np.asarray(box, float), (3,))])
+    _check(load().mpcd_md_verlet_chains(ctypes.c_void_p(pos_ptr), ctypes.c_void_p(vel_ptr),
+                                        ctypes.c_void_p(mass_ptr), int(n_chains), int(chain_len), b,
+                                        float(k_bond), float(bond_length), float(dt), int(nsteps),
+                                        None if hip_stream is None else ctypes.c_void_p(hip_stream)))
 
 
 def debug_fail_allocs(after, count=1):

@@ -18,7 +18,8 @@ ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "mpcd.hip")
 DEPS = [SRC, os.path.join(HERE, "csrc", "mpcd_kernels.hpp"),
         os.path.join(HERE, "csrc", "mpcd_device.hpp"),
-        os.path.join(ROOT, "include", "mpcd.h")]
+        os.path.join(ROOT, "include", "mpcd.h"),
+        os.path.join(HERE, "csrc", "mpcd_md.hpp")]
 LIB = os.path.join(HERE, "libmpcd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -25,6 +25,7 @@
 
 #include "mpcd.h"
 #include "mpcd_kernels.hpp"
+#include "mpcd_md.hpp"
 
 using namespace mpcd;
 
@@ -1786,6 +1787,28 @@ static mpcd_status copy_impl(const void* src, void* dst, int64_t bytes, void* hi
 }
 
 extern "C" {
+
+mpcd_status mpcd_md_verlet_chains(double* pos, double* vel, const double* mass, int64_t n_chains,
+                                  int32_t chain_len, const double box[3], double k_bond,
+                                  double bond_length, double dt, int32_t nsteps, void* hip_stream) {
+  g_err.clear();
+  if (n_chains < 0 || nsteps < 0) return fail(MPCD_EINVAL, "n_chains and nsteps must be >= 0");
+  if (chain_len < 1 || chain_len > 1024) return fail(MPCD_EINVAL, "chain_len must be 1..1024");
+  if (n_chains > 0x7FFFFFFF) return fail(MPCD_EINVAL, "too many chains");
+  if (!box || !(box[0] > 0.0) || !(box[1] > 0.0) || !(box[2] > 0.0))
+    return fail(MPCD_EINVAL, "box lengths must be > 0");
+  if (!std::isfinite(k_bond) || !std::isfinite(bond_length) || !(dt >= 0.0) || !std::isfinite(dt))
+    return fail(MPCD_EINVAL, "k_bond, bond_length must be finite and dt >= 0");
+  if (n_chains == 0 || nsteps == 0) return MPCD_OK;
+  if (!pos || !vel || !mass) return fail(MPCD_EINVAL, "pos/vel/mass NULL");
+  const uint32_t threads = ((uint32_t)chain_len + 63u) / 64u * 64u;
+  const size_t lds = (size_t)chain_len * 3 * sizeof(double);
+  hipStream_t st = (hipStream_t)hip_stream;
+  k_md_chains<<<(uint32_t)n_chains, threads, lds, st>>>(pos, vel, mass, (uint32_t)chain_len, box[0], box[1],
+                                                        box[2], k_bond, bond_length, dt, nsteps);
+  HIP_TRY(hipGetLastError());
+  return MPCD_OK;
+}
 
 mpcd_status mpcd_copy_kernel(const void* src, void* dst, int64_t bytes, void* hip_stream) {
   return copy_impl(src, dst, bytes, hip_stream, false);

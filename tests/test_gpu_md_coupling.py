@@ -205,3 +205,75 @@ def test_md_coupled_chains_fp32_each_cycle():
             assert np.all(f32_close(gvel1, v1))
             gb_pos, gb_vel = s.get_embedded()
         assert s.handover_stats() == (4, 0)
+
+
+def _device_chains(bpos, bvel, bmass):
+    import torch
+    return (torch.from_numpy(bpos.copy()).cuda(), torch.from_numpy(bvel.copy()).cuda(),
+            torch.from_numpy(bmass.copy()).cuda())
+
+
+@pytest.mark.parametrize("clen,chains", [(12, 6), (50, 40), (64, 3), (100, 2)])
+def test_device_verlet_equals_host_integrator(clen, chains):
+    """mpcd_md_verlet_chains (sec. 3.6 / 4.3: 50 velocity-Verlet steps of
+    0.002 per collision) against the host integrator of the tests, bit for
+    bit: both do the same IEEE operations in the same order."""
+    import torch
+    banner(f"device verlet, {chains} chains of {clen}")
+    L = np.array([9.0, 11.0, 10.0])
+    bpos, bvel, bmass = workloads.beads((9, 11, 10), chains, clen, seed=90 + clen)
+    hp, hv = verlet(bpos, bvel, bmass, clen, L, 0.002, 50)
+    dp, dv, dm = _device_chains(bpos, bvel, bmass)
+    m.binding.md_verlet_chains(dp.data_ptr(), dv.data_ptr(), dm.data_ptr(), chains, clen, L,
+                               0.002, 50, hip_stream=torch.cuda.current_stream().cuda_stream)
+    gp, gv = dp.cpu().numpy(), dv.cpu().numpy()
+    print(f"max |dpos| {np.abs(gp - hp).max():.3g}, max |dvel| {np.abs(gv - hv).max():.3g}")
+    assert np.array_equal(gp, hp) and np.array_equal(gv, hv)
+
+
+def test_coupled_cycle_on_device_equals_host_cycle():
+    """The whole coupled cycle on the device (integrator, handover, step,
+    read back, all on one stream) equals the cycle with the host integrator
+    and host arrays, bit for bit."""
+    import torch
+    banner("coupled cycle on device")
+    p = srd.Params((10, 10, 10), seed=97, thermostat=True)
+    clen, chains = 12, 6
+    pos, vel = workloads.fluid(p.n_cells, 6, seed=98)
+    bpos, bvel, bmass = workloads.beads(p.n_cells, chains, clen, seed=99)
+    kw = dict(seed=p.seed, thermostat=True, emb_pos=bpos, emb_vel=bvel, emb_mass=bmass,
+              flags=m.binding.FLAG_MD_SOLUTE)
+    with m.Sim(pos, vel, p.n_cells, **kw) as s:
+        hp, hv = bpos.copy(), bvel.copy()
+        for _ in range(4):
+            hp, hv = verlet(hp, hv, bmass, clen, p.L, 0.002, 50)
+            s.set_embedded(hp, hv)
+            s.step(1)
+            hp, hv = s.get_embedded()
+        want = s.get_state()
+    # one stream for the integrator and the context (torch's default stream
+    # has handle 0, for which the context would create a stream of its own)
+    ts = torch.cuda.Stream()
+    stream = ts.cuda_stream
+    dp, dv, dm = _device_chains(bpos, bvel, bmass)
+    torch.cuda.synchronize()
+    with m.Sim(pos, vel, p.n_cells, hip_stream=stream, **kw) as s:
+        for _ in range(4):
+            m.binding.md_verlet_chains(dp.data_ptr(), dv.data_ptr(), dm.data_ptr(), chains, clen,
+                                       p.L, 0.002, 50, hip_stream=stream)
+            s.set_embedded_device(dp.data_ptr(), dv.data_ptr())
+            s.step(1)
+            s.get_embedded_device(dp.data_ptr(), dv.data_ptr())
+        got = s.get_state()
+        assert s.handover_stats() == (3, 0)
+    assert np.array_equal(want[0], got[0]) and np.array_equal(want[1], got[1])
+
+
+def test_device_verlet_rejects_bad_arguments():
+    with pytest.raises(m.MpcdError):
+        m.binding.md_verlet_chains(0, 0, 0, 1, 0, (5, 5, 5), 0.002, 1)
+    with pytest.raises(m.MpcdError):
+        m.binding.md_verlet_chains(0, 0, 0, 1, 2000, (5, 5, 5), 0.002, 1)
+    with pytest.raises(m.MpcdError):
+        m.binding.md_verlet_chains(0, 0, 0, 1, 10, (5, 0, 5), 0.002, 1)
+    m.binding.md_verlet_chains(0, 0, 0, 0, 10, (5, 5, 5), 0.002, 1)   # nothing to do

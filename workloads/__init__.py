@@ -138,8 +138,9 @@ CONFIGS = {
     "srd_400c_rho5_beads": dict(n_cells=(400, 400, 400), density=5, kT=1.0,
                                 thermostat=False, steps=200, seed=1,
                                 chains=20000, chain_len=50, bead_mass=5.0),
-    # the same box with the beads coupled through an external MD integrator
-    # (MPCD_FLAG_MD_SOLUTE): state exchanged on device buffers every collision
+    # the same box with the beads coupled to MD (MPCD_FLAG_MD_SOLUTE): 50
+    # velocity-Verlet steps of 0.002 per collision, state exchanged on device
+    # buffers every collision
     "srd_400c_rho5_md": dict(n_cells=(400, 400, 400), density=5, kT=1.0,
                              thermostat=False, steps=50, seed=1,
                              chains=20000, chain_len=50, bead_mass=5.0),
