@@ -216,6 +216,11 @@ void shift_for(const mpcd_ctx c, uint32_t b, uint64_t n, double s[3]) {
 
 // Fill the device shift table with steps n0 .. n0 + count - 1 of every box.
 mpcd_status ensure_shifts(mpcd_ctx c, uint64_t n0, uint64_t count) {
+  // the context's own table already holds these steps (the shifts depend on
+  // the seed, the step and the box only)
+  if (c->shifts && c->shift_view == c->shifts && n0 >= c->shift_n0 &&
+      n0 + count <= c->shift_n0 + c->shift_count)
+    return MPCD_OK;
   const uint64_t need = count * c->nbox;
   if (need > c->shift_cap) {
     if (c->shifts) {
@@ -393,8 +398,6 @@ mpcd_status alloc_slabs(mpcd_ctx c, uint32_t cap, Particles out[2], std::vector<
       P.rb = (uint4*)get(S * 16);
       if (!P.ra || !P.rb) return fail(MPCD_ENOMEM, "device allocation of the slabs failed");
     }
-    P.lc = (uint8_t*)get(S);
-    if (!P.lc) return fail(MPCD_ENOMEM, "device allocation of the slabs failed");
   }
   return MPCD_OK;
 }
@@ -1647,8 +1650,8 @@ mpcd_status mpcd_footprint(const mpcd_params* params, int64_t n_particles, int64
   const uint64_t cap = slab_cap((uint64_t)std::ceil(full + 5.0 * std::sqrt(full)),
                                 (double)n / (double)nt);
   const uint64_t S = nt * cap;
-  const uint64_t slabs = fp64 ? 2 * (3 * sz(S * 16) + sz(S * 4) + sz(S))   // wa wb wc, tag, cell
-                              : 2 * (2 * sz(S * 16) + sz(S));              // ra rb, cell
+  const uint64_t slabs = fp64 ? 2 * (3 * sz(S * 16) + sz(S * 4))   // wa wb wc, tag
+                              : 2 * (2 * sz(S * 16));              // ra rb
   // counters (3), status, totals, embedded masses, box table, tile table, flag
   const uint64_t tables = 3 * sz(nt * 4) + sz(256) + sz(10 * 8) + sz(0) + sz(sizeof(Box)) +
                           sz(nt * 4) + sz(256);

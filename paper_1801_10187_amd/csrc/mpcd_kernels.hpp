@@ -1,7 +1,7 @@
 // Kernels of the SRD step on gfx950 (wave64, 160 KB LDS per CU, 8 XCDs).
 //
 // Data layout in HBM. The box is cut into tiles of td[0] x td[1] x td[2]
-// cells (4x4x4 or 4x4x8). Every tile owns a slab of `cap` particle slots in
+// cells (4x4x2 to 8x8x4). Every tile owns a slab of `cap` particle slots in
 // each of two buffers; the first cnt[T] slots of tile T hold its particles in
 // no particular order. Within a slab the data is structure of arrays, one
 // array per component, so a block reads and writes its tile as unit-stride
@@ -13,8 +13,8 @@
 //              rb[S] = {float velocity x, y, z, tag}, so a lane moves a
 //              particle with two vector loads or stores;
 //   tag[S] uint32 particle identity (FP64 form; inside rb in the FP32 form);
-//   lc[S]  uint8 the particle's collision cell inside its tile, written by
-//          the launch that placed it there;      S = ntiles * cap.
+//   S = ntiles * cap. A particle's cell inside its tile is not stored: the
+//   collision recomputes it from the position and the step's shift.
 //
 // One step is one launch of k_tile: block T gathers its tile (binned for this
 // step: every particle's collision cell lies in T), sums each cell exactly in
@@ -91,7 +91,6 @@ struct Particles {
   uint32_t* tag; // FP64 form: tag
   uint4* ra;     // FP32 form: {home cell packed 10:10:10, offset x, y, z (FP32 bits)}
   uint4* rb;     // FP32 form: {velocity x, y, z (FP32 bits), tag}
-  uint8_t* lc;   // local cell of the particle inside its tile (set by a scatter)
 };
 
 template <int FORM>
@@ -185,7 +184,6 @@ __device__ inline Particles tile_view(const Particles& P, size_t off) {
     Q.ra = P.ra + off;
     Q.rb = P.rb + off;
   }
-  Q.lc = P.lc + off;
   return Q;
 }
 
@@ -590,10 +588,13 @@ __device__ inline double gamma_finish(uint32_t nc, uint32_t cell, uint32_t step,
 // eight blocks fit a CU: the thermostatted step ~1.4 % faster than at seven,
 // though a few dwords spill; with embedded particles the compiler cannot
 // meet eight and seven is kept), thermostatted 128-cell tiles six (86 -> 80
-// VGPRs, a few spilled dwords; ~3 % faster).
+// VGPRs, a few spilled dwords; ~3 % faster); under the AT rule 64-cell
+// tiles six (with embedded particles the compiler would otherwise take 82
+// VGPRs and five).
 template <int FORM, int CPT, int MODE, bool STREAM_IN, bool THERMO, bool EMB, bool ATR>
 constexpr int tile_waves_per_eu() {
-  if (FORM != MPCD_FP32 || ATR) return 1;
+  if (FORM != MPCD_FP32) return 1;
+  if (ATR) return CPT == 64 ? 6 : 1;  // AT rule, 64-cell tiles: held at six
   if (CPT == 64) return EMB ? 7 : 8;
   if (CPT == 128 && THERMO) return 6;
   return 1;
@@ -701,6 +702,24 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
          g[2] < B.n[2];
     return ok ? cell_index(B, g) : 0u;
   };
+  // a particle's cell inside this tile: its cell under this step's shift,
+  // which the launch that placed it in this slab computed too (recomputed
+  // from the position rather than stored: a byte per particle written and
+  // read again cost more than the arithmetic)
+  auto lc_from = [&](const Pos<FORM>& rr) -> uint32_t {
+    int c[3];
+    rr.cell3(B, sd, sd32, c);
+    return (((uint32_t)c[0] & B.lm[0]) +
+            (uint32_t)B.td[0] * (((uint32_t)c[1] & B.lm[1]) + (uint32_t)B.td[1] * ((uint32_t)c[2] & B.lm[2]))) &
+           (uint32_t)(CPT - 1);
+  };
+  auto lc_at = [&](uint32_t k) -> uint32_t {
+    Pos<FORM> rr;
+    typename VelT<FORM>::T vv[3];
+    uint32_t t;
+    load_part<FORM>(In, k, rr, vv, t);
+    return lc_from(rr);
+  };
 
   // The per-cell draws need only (cell, step). The block's threads form
   // TT / CPT groups of CPT lanes, lane l of each group working for cell l:
@@ -770,12 +789,22 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
         double z;
         load_vt_z<FORM>(In, k, v[q], tg[q], z);
         if constexpr (FORM == 0) zq[q] = z;
-      } else if constexpr (MODE == MODE_DIAG) {
-        load_vt<FORM>(In, k, v[q], tg[q]);  // the cell sums need no position
       } else {
         load_part<FORM>(In, k, r[q], v[q], tg[q]);
       }
-      if constexpr (COLL) lcs[q] = (uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1);
+      if constexpr (COLL && !LPOS) lcs[q] = lc_from(r[q]);
+    }
+  }
+  if constexpr (LPOS) {
+    __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll
+    for (int q = 0; q < TQ; ++q) {
+      const uint32_t k = tid + (uint32_t)(q * TT);
+      if (k < nreg) {
+        Pos<FORM> rr;
+        pos_from_lds(s_pos[k], FORM == 0 ? zq[q] : 0.0, rr);
+        lcs[q] = lc_from(rr);
+      }
     }
   }
   if constexpr (AT) {
@@ -800,7 +829,7 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
   };
   auto put = [&](size_t j, const VT w[3], uint32_t tag, const Pos<FORM>& rr, uint32_t lcell) {
     store_part<FORM>(A.out, j, rr, w, tag);
-    st(A.out.lc, j, (uint8_t)lcell);
+    (void)lcell;
     if (A.eslot_out) note_slot(A.eslot_out, B, tag, j);
   };
   auto scatter = [&](const double* sd, const float* sd32, const VT (*w)[3]) {
@@ -902,7 +931,7 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
       const double m = mass_of(tag);
       double kv[3] = {0.0, 0.0, 0.0};
       if constexpr (AT) at_kick_tail(tag - B.tag0, A.step, B.k0, B.k1, sqrt(B.kT / m), kv);
-      sum_mom((uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1), vv, m, kv);
+      sum_mom(lc_at(k), vv, m, kv);
     }
     __syncthreads();
 
@@ -969,7 +998,7 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
       for (uint32_t k = TREG + tid; k < cnt; k += TT) {
         VT vv[3];
         load_vel<FORM>(In, k, vv);
-        sum_energy((uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1), vv, mass_of(load_tag<FORM>(In, k)));
+        sum_energy(lc_at(k), vv, mass_of(load_tag<FORM>(In, k)));
       }
       __syncthreads();
       if (cthr) ek = 0.5 * AC::value(s_acc[RE][tid], s_acc[RE + NL - 1][tid]);
@@ -1039,9 +1068,6 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
         for (int k = 0; k < 3; ++k) w[k] = (VT)(u[k] + r[k]);
       };
-      // the staged position records have arrived (each lane reads the slot
-      // its own wave filled)
-      if constexpr (LPOS) __builtin_amdgcn_s_waitcnt(0);
       // LPOS scatter: per particle the local cell in the destination (bits
       // 0-7), bin (8-12) and rank within the bin (13-31), taken in the rotate
       // loop while the streamed position is in registers
@@ -1052,7 +1078,6 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
         if constexpr (MODE == MODE_COLLIDE) {
           const Particles Out = tile_view<FORM>(A.out, tbase);
           store_part<FORM>(Out, k, rr, ww, tag);
-          st(Out.lc, k, (uint8_t)lc);
           if (A.eslot_out) note_slot(A.eslot_out, B, tag, tbase + k);
         } else {
           if (streamed(B, tag)) rr.stream(B, ww, err);
@@ -1080,7 +1105,6 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
             if constexpr (MODE == MODE_COLLIDE) {
               const Particles Out = tile_view<FORM>(A.out, tbase);
               store_part<FORM>(Out, k, rr, v[q], tg[q]);
-              st(Out.lc, k, (uint8_t)lcs[q]);
               if (A.eslot_out) note_slot(A.eslot_out, B, tg[q], tbase + k);
             } else {
               if (streamed(B, tg[q])) rr.stream(B, v[q], err);
@@ -1096,7 +1120,6 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
           } else if constexpr (MODE == MODE_COLLIDE) {
             const Particles Out = tile_view<FORM>(A.out, tbase);
             store_part<FORM>(Out, k, r[q], v[q], tg[q]);
-            st(Out.lc, k, (uint8_t)lcs[q]);
             if (A.eslot_out) note_slot(A.eslot_out, B, tg[q], tbase + k);
           } else {
             if (streamed(B, tg[q])) r[q].stream(B, v[q], err);
@@ -1139,7 +1162,7 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
         VT vv[3], ww[3];
         uint32_t tag;
         Pos<FORM> rr;
-        const uint32_t lc = (uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1);
+        const uint32_t lc = lc_at(k);
         if (THERMO && anyp && s_pend[lc]) continue;
         load_part<FORM>(In, k, rr, vv, tag);
         double kv[3] = {0.0, 0.0, 0.0};
@@ -1162,7 +1185,7 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
           }
           __syncthreads();
           for (uint32_t k = tid; k < cnt; k += TT) {
-            const uint32_t lc = (uint32_t)ld(In.lc, k) & (uint32_t)(CPT - 1);
+            const uint32_t lc = lc_at(k);
             if (!s_pend[lc]) continue;
             VT vv[3], ww[3];
             uint32_t tag;
@@ -1641,7 +1664,6 @@ __global__ __launch_bounds__(256) void k_emb_rebin(Particles Pp, Particles Pc, B
   const uint32_t T0 = (uint32_t)(jp / cap);
   if (T == T0) {
     store_part<FORM>(Pp, jp, r, w, t);
-    Pp.lc[jp] = (uint8_t)lcell;
   } else {
     movers[atomicAdd(nmovers, 1u)] = i;
     dep_next[i] = atomicExch(&dep_head[T0], (int32_t)i);
@@ -1679,7 +1701,6 @@ __global__ __launch_bounds__(256) void k_emb_depart(Particles Pp, Box B, uint32_
     Pos<FORM> r;
     load_part<FORM>(Pp, s, r, v, tag);
     store_part<FORM>(Pp, j, r, v, tag);
-    Pp.lc[j] = Pp.lc[s];
     note_slot(eslot_p, B, tag, j);
   }
   cnt_p[T] = keep;
@@ -1709,7 +1730,6 @@ __global__ __launch_bounds__(256) void k_emb_arrive(Particles Pp, Box B, const S
   }
   const size_t j = (size_t)T * cap + slot;
   store_part<FORM>(Pp, j, r, w, B.tag0 + B.n_solvent + i);
-  Pp.lc[j] = (uint8_t)lcell;
   eslot_p[i] = (uint32_t)j;
 }
 
@@ -1728,7 +1748,6 @@ __global__ __launch_bounds__(256) void k_repack(Particles src, Particles dst, Sl
   Pos<FORM> r;
   load_part<FORM>(src, i, r, v, tag);
   store_part<FORM>(dst, j, r, v, tag);
-  dst.lc[j] = src.lc[i];
   if (eslot) note_slot(eslot, S.boxes[S.tile_box[T]], tag, j);
 }
 

@@ -48,14 +48,14 @@ def test_footprint_follows_the_slab_rule():
     them, those at the far faces cut to 2 cells along the axis): slabs sized
     for a whole tile's mean occupancy (512) plus five standard deviations,
     +20 % (at least the mean over all tiles + 8 sigma + 64), rounded up to
-    32; two slab buffers of 33 (FP32) or 53 (FP64) bytes per slot; at the
+    32; two slab buffers of 32 (FP32) or 52 (FP64) bytes per slot; at the
     peak the 48-byte-per-particle upload buffer beside them. The rest
     (counters and tables, a few hundred kB here) within 2 MB."""
     n, nt = 10**6, 13 ** 3
     mean = n / nt
     mx = math.ceil(512 + 5 * math.sqrt(512))
     cap = -(-max(mx + mx // 5, int(mean + 8 * math.sqrt(mean) + 64)) // 32) * 32
-    for prec, rec in ((FP32, 33), (FP64, 53)):
+    for prec, rec in ((FP32, 32), (FP64, 52)):
         peak, held = binding.footprint((50, 50, 50), n, nsteps=10, precision=prec)
         slabs = 2 * rec * nt * cap
         assert slabs < held < slabs + 2e6
