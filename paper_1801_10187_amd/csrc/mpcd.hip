@@ -336,6 +336,7 @@ TileArgs tile_args(mpcd_ctx c) {
   a.emb_mass = c->emb_mass;
   a.status = c->status;
   a.eslot_out = c->n_emb ? c->eslot[1 - c->cur] : nullptr;
+  a.one_box = c->nbox == 1 ? 1u : 0u;
   return a;
 }
 
@@ -1344,14 +1345,20 @@ hipError_t emb_import(mpcd_ctx c, const double* dp, const double* dv) {
 mpcd_status emb_handover(mpcd_ctx c, const double* dp, const double* dv, uint32_t* hflag) {
   const uint32_t n = c->n_emb, nb = blocks_for(n, kGrid);
   const uint32_t nt = c->S.ntiles;
-  if (!c->dep_head) {
-    c->dep_head = (int32_t*)c->dalloc((size_t)nt * 4);
-    c->dep_next = (int32_t*)c->dalloc((size_t)n * 4);
-    c->movers = (uint32_t*)c->dalloc((size_t)n * 4);
-    c->nmovers = (uint32_t*)c->dalloc(256);
-    if (!c->dep_head || !c->dep_next || !c->movers || !c->nmovers)
-      return fail(MPCD_ENOMEM, "device allocation for the solute handover failed");
-    HIP_TRY(hipMemsetAsync(c->dep_head, 0xFF, (size_t)nt * 4, c->stream));
+  if (!c->dep_head) {  // all four arrays, or none
+    void* q[4] = {nullptr, nullptr, nullptr, nullptr};
+    const size_t bytes[4] = {(size_t)nt * 4, (size_t)n * 4, (size_t)n * 4, 256};
+    for (int k = 0; k < 4; ++k)
+      if (c->alloc(&q[k], bytes[k]) != hipSuccess) {
+        for (int j = 0; j < k; ++j) c->release(q[j]);
+        return fail(MPCD_ENOMEM, "device allocation for the solute handover failed");
+      }
+    for (void* p : q) c->allocs.push_back(p);  // owned by the context from here
+    HIP_TRY(hipMemsetAsync(q[0], 0xFF, bytes[0], c->stream));
+    c->dep_head = (int32_t*)q[0];
+    c->dep_next = (int32_t*)q[1];
+    c->movers = (uint32_t*)q[2];
+    c->nmovers = (uint32_t*)q[3];
   }
   ST_TRY(ensure_shifts(c, c->step, 1));
   const ShiftEntry* sh = shift_at(c, c->step);

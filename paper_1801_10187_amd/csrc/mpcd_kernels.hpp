@@ -494,6 +494,8 @@ struct TileArgs {
   double* d_xi;
   uint32_t* eslot_out;      // slot of each embedded particle in the output
                             // buffer (null without embedded particles)
+  uint32_t one_box;         // 1: a single box (every tile's box is 0; the
+                            // tile -> box table need not be read)
 };
 
 // Record the slot j of an embedded particle (tag) in the index of the buffer
@@ -647,7 +649,7 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
 
   const uint32_t tid = threadIdx.x;
   const uint32_t T = xcd_remap(blockIdx.x, gridDim.x);  // tile, all boxes
-  const uint32_t bx = A.S.tile_box[T];
+  const uint32_t bx = A.one_box ? 0u : A.S.tile_box[T];
   const Box B = A.S.boxes[bx];  // a copy: loaded once, not re-read after stores
   const uint32_t cap = A.S.cap;
   int t3[3];

@@ -101,3 +101,35 @@ def test_readback_staging_failure():
         assert ei.value.status == m.binding.MPCD_ENOMEM
         got = s.get_state()
     assert np.array_equal(want[0], got[0]) and np.array_equal(want[1], got[1])
+
+
+def test_failed_handover_allocation_leaves_the_state_alone():
+    """The solute handover's index arrays are allocated on its first use; if
+    one of them cannot be, the call returns MPCD_ENOMEM having changed
+    nothing, and the same call then succeeds, with the result of a run that
+    never failed."""
+    banner("handover allocation failure")
+    pos, vel = workloads.fluid((8, 8, 8), 5.0, seed=68)
+    bpos, bvel, bmass = workloads.beads((8, 8, 8), 3, 6, seed=69)
+    kw = dict(seed=70, thermostat=True, emb_pos=bpos, emb_vel=bvel, emb_mass=bmass,
+              flags=m.binding.FLAG_MD_SOLUTE)
+    moved = (bpos + 0.3) % 8.0
+
+    def run(fail_at):
+        with m.Sim(pos, vel, (8, 8, 8), **kw) as s:
+            s.step(1)
+            if fail_at is not None:
+                m.binding.debug_fail_allocs(fail_at, 1)
+                with pytest.raises(m.MpcdError) as ei:
+                    s.set_embedded(moved, bvel)
+                m.binding.debug_fail_allocs(-1)
+                assert ei.value.status == m.binding.MPCD_ENOMEM
+            s.set_embedded(moved, bvel)
+            s.step(2)
+            assert s.handover_stats() == (1, 0)
+            return s.get_state()
+
+    want = run(None)
+    for k in (1, 2, 3, 4):   # the staging buffer, then the four index arrays
+        got = run(k)
+        assert np.array_equal(want[0], got[0]) and np.array_equal(want[1], got[1])
