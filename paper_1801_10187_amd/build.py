@@ -19,7 +19,8 @@ SRC = os.path.join(HERE, "csrc", "mpcd.hip")
 DEPS = [SRC, os.path.join(HERE, "csrc", "mpcd_kernels.hpp"),
         os.path.join(HERE, "csrc", "mpcd_device.hpp"),
         os.path.join(ROOT, "include", "mpcd.h"),
-        os.path.join(HERE, "csrc", "mpcd_md.hpp")]
+        os.path.join(HERE, "csrc", "mpcd_md.hpp"),
+        os.path.join(HERE, "csrc", "mpcd_emb.hpp")]
 LIB = os.path.join(HERE, "libmpcd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -25,6 +25,7 @@
 
 #include "mpcd.h"
 #include "mpcd_kernels.hpp"
+#include "mpcd_emb.hpp"
 #include "mpcd_md.hpp"
 
 using namespace mpcd;
@@ -1296,18 +1297,19 @@ mpcd_status mpcd_get_embedded(mpcd_ctx c, double* pos, double* vel, int32_t on_d
   hipError_t e = hipMemsetAsync(c->flag, 0, 4, c->stream);
   if (e == hipSuccess) {
     // a split state: positions from the current buffer, velocities from the
-    // prepared one, each through its own slot index
+    // prepared one, each through its own slot index (one pass)
     const size_t ns = (size_t)c->S.ntiles * c->S.cap;
-    struct {
-      int b;
-      double *p, *v;
-    } part[2] = {{c->cur, dp, c->split ? nullptr : dv}, {1 - c->cur, nullptr, c->split ? dv : nullptr}};
-    for (const auto& q : part) {
-      if (!q.p && !q.v) continue;
+    const int cb = c->cur, pb = 1 - c->cur;
+    if (c->split) {
       if (c->form == 0)
-        k_emb_export<0><<<nb, kGrid, 0, c->stream>>>(c->buf[q.b], c->boxes[0], c->eslot[q.b], (uint32_t)n, ns, q.p, q.v, c->flag);
+        k_emb_export_split<0><<<nb, kGrid, 0, c->stream>>>(c->buf[cb], c->buf[pb], c->boxes[0], c->eslot[cb], c->eslot[pb], (uint32_t)n, ns, dp, dv, c->flag);
       else
-        k_emb_export<1><<<nb, kGrid, 0, c->stream>>>(c->buf[q.b], c->boxes[0], c->eslot[q.b], (uint32_t)n, ns, q.p, q.v, c->flag);
+        k_emb_export_split<1><<<nb, kGrid, 0, c->stream>>>(c->buf[cb], c->buf[pb], c->boxes[0], c->eslot[cb], c->eslot[pb], (uint32_t)n, ns, dp, dv, c->flag);
+    } else {
+      if (c->form == 0)
+        k_emb_export<0><<<nb, kGrid, 0, c->stream>>>(c->buf[cb], c->boxes[0], c->eslot[cb], (uint32_t)n, ns, dp, dv, c->flag);
+      else
+        k_emb_export<1><<<nb, kGrid, 0, c->stream>>>(c->buf[cb], c->boxes[0], c->eslot[cb], (uint32_t)n, ns, dp, dv, c->flag);
     }
     e = hipGetLastError();
   }
