@@ -109,7 +109,8 @@ def test_md_exchange_on_device_buffers():
     assert np.array_equal(pa, pb) and np.array_equal(va, vb)
 
 
-def _jumping_run(prec, n_cells, rho, nb, seed, cycles, fresh, crowd_at=None, thermo=True):
+def _jumping_run(prec, n_cells, rho, nb, seed, cycles, fresh, crowd_at=None, thermo=True,
+                 collision=m.SRD):
     """MD-flagged context whose solutes jump to new random places before each
     collision (crowd_at: the cycle from which all of them sit in one cell).
     fresh: before each handover the prepared binning is given up (a step
@@ -120,8 +121,8 @@ def _jumping_run(prec, n_cells, rho, nb, seed, cycles, fresh, crowd_at=None, the
     bpos = rng.random((nb, 3)) * L
     bvel = rng.normal(size=(nb, 3)) * 0.4
     bmass = np.full(nb, 3.0)
-    with m.Sim(pos, vel, n_cells, seed=seed + 2, thermostat=thermo, precision=prec,
-               emb_pos=bpos, emb_vel=bvel, emb_mass=bmass,
+    with m.Sim(pos, vel, n_cells, seed=seed + 2, thermostat=thermo and collision == m.SRD,
+               precision=prec, collision=collision, emb_pos=bpos, emb_vel=bvel, emb_mass=bmass,
                flags=m.binding.FLAG_MD_SOLUTE) as s:
         for c in range(cycles):
             if crowd_at is not None and c >= crowd_at:
@@ -142,14 +143,15 @@ def _jumping_run(prec, n_cells, rho, nb, seed, cycles, fresh, crowd_at=None, the
         return st, cells, s.handover_stats(), s.layout()[3]
 
 
-@pytest.mark.parametrize("prec", [m.FP64, m.FP32])
-def test_handover_jumping_solutes_equal_fresh_binning(prec):
+@pytest.mark.parametrize("prec,collision", [(m.FP64, m.SRD), (m.FP32, m.SRD), (m.FP32, m.AT)])
+def test_handover_jumping_solutes_equal_fresh_binning(prec, collision):
     """300 solutes jumping anywhere in a 10^3 box every cycle (most change
     tile, several leave or enter one tile at once): six cycles with the
-    handover give the state of the same cycles binned afresh, bit for bit."""
-    banner(f"handover, jumping solutes, prec {prec}")
-    a = _jumping_run(prec, (10, 10, 10), 6.0, 300, 81, 6, fresh=False)
-    b = _jumping_run(prec, (10, 10, 10), 6.0, 300, 81, 6, fresh=True)
+    handover give the state of the same cycles binned afresh, bit for bit
+    (both forms; the AT rule too)."""
+    banner(f"handover, jumping solutes, prec {prec} rule {collision}")
+    a = _jumping_run(prec, (10, 10, 10), 6.0, 300, 81, 6, fresh=False, collision=collision)
+    b = _jumping_run(prec, (10, 10, 10), 6.0, 300, 81, 6, fresh=True, collision=collision)
     for x, y in zip(a[0] + a[1], b[0] + b[1]):
         assert np.array_equal(x, y)
     assert a[2] == (5, 0) and b[2] == (0, 0)
