@@ -13,6 +13,7 @@ rule's choice. Run `python -m paper_1801_10187_amd.autotune` for the table.
 import argparse
 import json
 import os
+import sys
 import time
 
 import numpy as np
@@ -23,15 +24,16 @@ SHAPES = list(binding.TILE_SHAPES)
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "mpcd_tiles.json")
 
 
-def rule_shape(density):
-    """The library's own choice (MPCD_TILE_* 0) for a mean density."""
-    if density >= 11.0:
+def rule_shape(density, single=True, collision=binding.SRD):
+    """The library's own choice (MPCD_TILE_* 0) for a mean density: a box
+    alone or a box of a batch, SRD or AT rule."""
+    if density >= 12.0:
         return "4x4x2"
-    if density >= 3.5:
-        return "4x4x4"
-    if density >= 1.75:
-        return "8x4x4"
-    return "8x8x4"
+    if not single:
+        return "4x4x4" if density >= 3.5 else ("8x4x4" if density >= 1.75 else "8x8x4")
+    if collision == binding.AT:
+        return "4x4x4" if density >= 2.5 else "8x8x4"
+    return "4x4x4" if density >= 7.5 else ("8x4x4" if density >= 3.75 else "8x8x4")
 
 
 def _fluid(n_cells, density, kT, seed):
@@ -105,8 +107,9 @@ def sweep(densities, precision=binding.FP32, thermostat=True, collision=binding.
         t = {sh: min(measure(sh, rho, precision, thermostat, collision, inp=inp, **kw)
                      for _ in range(repeats)) for sh in SHAPES}
         best = min(t, key=t.get)
-        rule = rule_shape(rho)
+        rule = rule_shape(rho, True, collision)
         rows.append((rho, t, best, rule, t[rule] / t[best]))
+        print(f"[autotune] density {rho:g}: fastest {best}", file=sys.stderr, flush=True)
     return rows
 
 

@@ -642,22 +642,38 @@ mpcd_status validate(const mpcd_params* p, int64_t ns, int64_t ne) {
   return MPCD_OK;
 }
 
-// Tile shape of one box: 64-cell tiles (224-768 particles per tile at the
-// box's mean density) wherever the density allows, since their step kernel
-// keeps the particles' positions in LDS and runs at the highest occupancy
-// (measured on the 256-box batch: 64-cell tiles down to density 3.5 step it
-// 15 % faster than 128-cell tiles from density 7 down); sparser boxes take
-// larger tiles. The kernels hold up to 768 particles of a 64-cell tile and
-// 1024 of a larger one in registers; more are read again from memory.
-// shape 1..4 (the MPCD_TILE_* codes) sets the shape instead of the rule.
-// Returns the cells per tile, rounded up to the kernel sizes 64/128/256.
-int choose_tiles(Box& B, double rho, int shape = 0) {
+// Tile shape of one box by its mean density rho, from step times measured
+// for every shape on one MI355X (96^3-cell boxes, both forms, both rules):
+//  - a box alone, SRD rule: 8x8x4 cells below 3.75 particles per cell,
+//    8x4x4 below 7.5, 4x4x4 below 12, 4x4x2 from 12 (each within 5 % of the
+//    fastest shape at the densities measured, 1.5-12 % faster than the
+//    shape of the next band);
+//  - a box alone, AT rule: 8x8x4 below 2.5, 4x4x4 below 12, 4x4x2 from 12
+//    (its FP64 kernels lose more occupancy with larger tiles);
+//  - boxes of a batch: every box runs with the kernel of the largest tile
+//    any box needs (cells per tile 64/128/256), which slows the boxes with
+//    smaller tiles, so a batch keeps 64-cell tiles down to density 3.5
+//    (measured on the 256-box batch: 15 % faster than 128-cell tiles for its
+//    boxes from density 7 down), 8x4x4 below, 8x8x4 below 1.75, 4x4x2 from
+//    12.
+// The kernels hold up to 768 particles of a 64-cell tile and 1024 of a
+// larger one in registers; more are read again from memory (the shapes that
+// overflow them at a density are many times slower). shape 1..4 (the
+// MPCD_TILE_* codes) sets the shape instead of the rule. Returns the cells
+// per tile, rounded up to the kernel sizes 64/128/256.
+int choose_tiles(Box& B, double rho, int shape = 0, bool single = true, bool at_rule = false) {
+  if (shape == 0) {
+    if (rho >= 12.0) shape = 1;
+    else if (!single) shape = rho >= 3.5 ? 2 : (rho >= 1.75 ? 3 : 4);
+    else if (at_rule) shape = rho >= 2.5 ? 2 : 4;
+    else shape = rho >= 7.5 ? 2 : (rho >= 3.75 ? 3 : 4);
+  }
   int td[3], cpt;
-  if (shape == 1 || (shape == 0 && rho >= 11.0)) {
+  if (shape == 1) {
     td[0] = 4; td[1] = 4; td[2] = 2; cpt = 64;
-  } else if (shape == 2 || (shape == 0 && rho >= 3.5)) {
+  } else if (shape == 2) {
     td[0] = 4; td[1] = 4; td[2] = 4; cpt = 64;
-  } else if (shape == 3 || (shape == 0 && rho >= 1.75)) {
+  } else if (shape == 3) {
     td[0] = 8; td[1] = 4; td[2] = 4; cpt = 128;
   } else {
     td[0] = 8; td[1] = 8; td[2] = 4; cpt = 256;
@@ -786,7 +802,8 @@ mpcd_status create_impl(int32_t nbox, const mpcd_params* params, const int64_t* 
     Box B = make_box(params[b]);
     const uint32_t nb = (uint32_t)n_solv[b] + (b == 0 ? c->n_emb : 0u);
     cpt = std::max(cpt, choose_tiles(B, B.ncells ? (double)nb / (double)B.ncells : 0.0,
-                                     tile_shape(params[b])));
+                                     tile_shape(params[b]), nbox == 1,
+                                     params[b].collision == MPCD_AT));
     const uint32_t t0 = tile;
     B.tile0 = t0;
     B.tag0 = tag;
@@ -1646,7 +1663,7 @@ mpcd_status mpcd_footprint(const mpcd_params* params, int64_t n_particles, int64
   if (nsteps < 0) return fail(MPCD_EINVAL, "nsteps < 0");
   Box B = make_box(*params);
   const double rho = B.ncells ? (double)n_particles / (double)B.ncells : 0.0;
-  (void)choose_tiles(B, rho, tile_shape(*params));
+  (void)choose_tiles(B, rho, tile_shape(*params), true, params->collision == MPCD_AT);
   const uint64_t nt = B.ntiles, C = B.ncells, n = (uint64_t)n_particles;
   const bool fp64 = params->precision == MPCD_FP64;
   // every allocation is at least 256 bytes; allow that much again for the

@@ -25,9 +25,10 @@ def _lib():
 
 
 # box, particles in one crowded cell, particles spread over the box, the
-# tile shape the density rule picks and the register-resident part per tile
+# tile shape (set through the flags: the AT rule's density rule never picks
+# 8x4x4) and the register-resident part per tile
 CROWD = {"cpt64": ((4, 4, 4), 3000, 500, (4, 4, 2), 768),
-         "cpt128": ((8, 8, 8), 1100, 600, (8, 4, 4), 1024)}
+         "cpt128": ((8, 8, 8), 1100, 900, (8, 4, 4), 1024)}
 
 
 def _crowd(layout, seed):
@@ -69,7 +70,7 @@ def test_fp32_crowded_tile(rule, layout):
     mass = np.ones(pos.shape[0])
     check = fp32_step_matches if rule == "srd_thermo" else (
         lambda *a: _step_matches_at(*a[:-1]))
-    with _sim(pos, vel, p, m.FP32) as s:
+    with _sim(pos, vel, p, m.FP32, tile="x".join(map(str, tile))) as s:
         assert s.layout()[0] == tile
         gpos, gvel = s.get_state()
         for k in range(2):
@@ -92,7 +93,7 @@ def test_fp64_crowded_128_cell_tile(rule):
     p = srd.Params(n_cells, seed=93, thermostat=rule == "srd_thermo", grid_shift=False,
                    dt=0.01, rule="at" if rule == "at" else "srd")
     pos, vel = _crowd("cpt128", 94)
-    with _sim(pos, vel, p, m.FP64) as s:
+    with _sim(pos, vel, p, m.FP64, tile="x".join(map(str, tile))) as s:
         assert s.layout()[0] == tile
         s.step(2)
         _, gvel = s.get_state()

@@ -408,14 +408,15 @@ def test_full_size_benchmark_fluid_fp32_each_step():
             gpos, gvel = gpos1, gvel1
 
 
-TILE_SHAPES = {1.2: (8, 8, 4), 2.5: (8, 4, 4), 12.5: (4, 4, 2)}
+TILE_SHAPES = {1.2: (8, 8, 4), 5.0: (8, 4, 4), 12.5: (4, 4, 2)}
 
 
-@pytest.mark.parametrize("rho,n_cells", [(1.2, (19, 11, 10)), (2.5, (17, 9, 10)), (12.5, (9, 10, 7))])
+@pytest.mark.parametrize("rho,n_cells", [(1.2, (19, 11, 10)), (5.0, (17, 9, 10)), (12.5, (9, 10, 7))])
 def test_extreme_tile_shapes(rho, n_cells):
-    """The sparse tile shapes (8x8x4 cells, 256-cell kernels, below density
-    1.75; 8x4x4, 128-cell kernels, below 3.5) and the densest (4x4x2, density
-    11 and up), each with partial tiles on every axis: three thermostatted
+    """The tile shapes a box alone takes under the SRD rule at sparse
+    densities (8x8x4 cells, 256-cell kernels, below density 3.75; 8x4x4,
+    128-cell kernels, below 7.5) and the densest (4x4x2, density 12 and up),
+    each with partial tiles on every axis: three thermostatted
     FP64 steps against the oracle, and one FP32 step from a shared state
     against its emulation."""
     banner(f"tile shapes rho={rho} {n_cells}")

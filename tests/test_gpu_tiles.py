@@ -19,7 +19,8 @@ SHAPES = list(m.binding.TILE_SHAPES)
 DIMS = {"4x4x2": (4, 4, 2), "4x4x4": (4, 4, 4), "8x4x4": (8, 4, 4), "8x8x4": (8, 8, 4)}
 
 
-@pytest.mark.parametrize("prec,rule", [(m.FP32, m.SRD), (m.FP64, m.SRD), (m.FP32, m.AT)])
+@pytest.mark.parametrize("prec,rule", [(m.FP32, m.SRD), (m.FP64, m.SRD), (m.FP32, m.AT),
+                                       (m.FP64, m.AT)])
 def test_every_shape_gives_the_same_steps(prec, rule):
     banner(f"tile shapes, prec {prec} rule {rule}")
     n_cells = (20, 18, 13)
