@@ -683,7 +683,7 @@ int choose_tiles(Box& B, double rho, int shape = 0, bool single = true, bool at_
     if (B.n[d] <= td[d]) {
       B.td[d] = B.n[d];
       B.nt[d] = 1;
-      B.tsh[d] = 0;
+      B.tsh[d] = 31;  // every cell coordinate (< 2^10) shifts to tile 0
       B.lm[d] = 0xFFFFFFFFu;
     } else {
       B.td[d] = td[d];

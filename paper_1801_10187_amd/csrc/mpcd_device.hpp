@@ -124,7 +124,7 @@ __device__ inline int bin_axis64(double x, double s, double L, double inv_a,
   const int i = (int)floor(w * inv_a);
   // w is in [0, L) for any position the stream produced, so only the top
   // clamp can act; the bottom one keeps a corrupt position inside the grid.
-  return i < 0 ? 0 : (i < n - 1 ? i : n - 1);
+  return min(max(i, 0), n - 1);
 }
 
 // FP32 cell-relative form: position = home cell h (per axis) + offset o in
@@ -132,6 +132,15 @@ __device__ inline int bin_axis64(double x, double s, double L, double inv_a,
 __device__ inline int wrap_index(int i, int n) {
   i %= n;
   return i < 0 ? i + n : i;
+}
+
+// i in [-n, 2n) -> i mod n, by two unsigned minima (a negative i is a large
+// unsigned value, and i - n wraps round for i < n); any other i is returned
+// as an unsigned value >= n.
+__device__ inline uint32_t wrap_once(int i, int n) {
+  uint32_t u = (uint32_t)i;
+  u = min(u, u + (uint32_t)n);
+  return min(u, u - (uint32_t)n);
 }
 
 __device__ inline void stream_axis32(float& o, int& h, float v, float dt32,
@@ -150,22 +159,23 @@ __device__ inline void stream_axis32(float& o, int& h, float v, float dt32,
   o = o2;
   // periodic home cell; a move of a whole box or more (never for
   // |v dt| < L) takes the general modulo
-  int hn = h + k;
-  hn += hn < 0 ? n : 0;
-  hn -= hn >= n ? n : 0;
-  if (hn < 0 || hn >= n) hn = wrap_index(hn, n);
-  h = hn;
+  const uint32_t hn = wrap_once(h + k, n);
+  h = hn < (uint32_t)n ? (int)hn : wrap_index(h + k, n);
+}
+
+// min(max(floor(x), -1), 1) as an integer: floor and conversion in one
+// instruction (out-of-range values saturate and NaN gives 0, as the separate
+// floor and conversion do), then the clamp as a median of three.
+__device__ inline int floor_unit(float x) {
+  int j;
+  asm("v_cvt_flr_i32_f32 %0, %1\n\tv_med3_i32 %0, %0, -1, 1" : "=v"(j) : "v"(x));
+  return j;
 }
 
 __device__ inline int bin_axis32(float o, int h, float s32, float inv_a32,
                                  int n) {
   const float q = o + s32;
-  int j = (int)floorf(q * inv_a32);
-  j = j < -1 ? -1 : (j > 1 ? 1 : j);
-  int c = h + j;
-  if (c < 0) c += n;
-  if (c >= n) c -= n;
-  return c;
+  return (int)wrap_once(h + floor_unit(q * inv_a32), n);
 }
 
 __device__ inline uint32_t pack_home(int hx, int hy, int hz) {

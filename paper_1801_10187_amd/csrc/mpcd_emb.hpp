@@ -188,8 +188,7 @@ __device__ inline uint32_t emb_tile(const Box& B, const ShiftEntry& sh, const Po
                                     uint32_t& lcell) {
   int c[3];
   r.cell3(B, sh.s, sh.s32, c);
-  lcell = ((uint32_t)c[0] & B.lm[0]) +
-          (uint32_t)B.td[0] * (((uint32_t)c[1] & B.lm[1]) + (uint32_t)B.td[1] * ((uint32_t)c[2] & B.lm[2]));
+  lcell = local_cell(B, c);
   return B.tile0 + tile_index(B, c);
 }
 

@@ -50,7 +50,7 @@ struct Box {
   uint32_t k0, k1;     // Philox key = user seed
   uint32_t n_solvent;
   int td[3];           // tile size in cells
-  int tsh[3];          // log2(td) (td is a power of two whenever nt > 1)
+  int tsh[3];          // cell -> tile coordinate: c >> tsh (log2(td); 31 if nt == 1)
   int nt[3];           // tiles per axis
   uint32_t lm[3];      // cell -> cell inside its tile: c & lm (td - 1, or all ones if nt == 1)
   uint32_t m_td0, m_td01;   // ceil(2^24 / td[0]), ceil(2^24 / (td[0] td[1]))
@@ -66,6 +66,13 @@ struct Box {
 // the MD integrator when the box couples solutes that way, sec. 3.6).
 __device__ inline bool streamed(const Box& B, uint32_t tag) {
   return !(B.md_solute && tag - B.tag0 >= B.n_solvent);
+}
+// The same in a kernel that knows whether its tiles can hold embedded
+// particles (without them every particle streams).
+template <bool MAY_EMB>
+__device__ inline bool streamed_in(const Box& B, uint32_t tag) {
+  if constexpr (MAY_EMB) return streamed(B, tag);
+  return true;
 }
 
 // Several independent boxes share one set of slabs: box b owns the tiles
@@ -222,13 +229,21 @@ __device__ inline void tile_coords(const Box& B, uint32_t T, int t3[3]) {
 __device__ inline void local_coords(const Box& B, uint32_t l, uint32_t l3[3]) {
   const uint32_t a = div_small(l, B.m_td0);
   const uint32_t z = div_small(l, B.m_td01);
-  l3[0] = l - a * (uint32_t)B.td[0];
-  l3[1] = a - z * (uint32_t)B.td[1];
+  l3[0] = l - __umul24(a, (uint32_t)B.td[0]);
+  l3[1] = a - __umul24(z, (uint32_t)B.td[1]);
   l3[2] = z;
 }
 
+// Tile coordinate of cell coordinate c (0 <= c < n < 2^10) along axis d.
 __device__ inline int tile_coord(int c, const Box& B, int d) {
-  return B.nt[d] == 1 ? 0 : (c >> B.tsh[d]);
+  return c >> B.tsh[d];
+}
+
+// Index products of cell and tile coordinates: every factor is below 2^24
+// (at most 1023 cells per axis), so the 24-bit multiply-add gives the exact
+// 32-bit result at full rate.
+__device__ inline uint32_t mad24(uint32_t a, uint32_t b, uint32_t c) {
+  return __umul24(a, b) + c;
 }
 
 // Velocity and tag of a particle. Both forms keep a particle in 16-byte
@@ -419,12 +434,12 @@ __device__ inline void store_vel(const Particles& P, I j, const Pos<FORM>& r,
 }
 
 __device__ inline uint32_t cell_index(const Box& B, const int c[3]) {
-  return (uint32_t)c[0] + (uint32_t)B.n[0] * ((uint32_t)c[1] + (uint32_t)B.n[1] * (uint32_t)c[2]);
+  return mad24((uint32_t)B.n[0], mad24((uint32_t)B.n[1], (uint32_t)c[2], (uint32_t)c[1]), (uint32_t)c[0]);
 }
 
 __device__ inline uint32_t tile_index(const Box& B, const int c[3]) {
   const int tx = tile_coord(c[0], B, 0), ty = tile_coord(c[1], B, 1), tz = tile_coord(c[2], B, 2);
-  return (uint32_t)tx + (uint32_t)B.nt[0] * ((uint32_t)ty + (uint32_t)B.nt[1] * (uint32_t)tz);
+  return mad24((uint32_t)B.nt[0], mad24((uint32_t)B.nt[1], (uint32_t)tz, (uint32_t)ty), (uint32_t)tx);
 }
 
 // ------------------------------------------------------- scatter helpers
@@ -444,25 +459,34 @@ __device__ inline uint32_t bin_tile(const Box& B, const int t[3], uint32_t bin) 
   return (uint32_t)c[0] + (uint32_t)B.nt[0] * ((uint32_t)c[1] + (uint32_t)B.nt[1] * (uint32_t)c[2]);
 }
 
+// Cell c's index inside its tile (x fastest).
+__device__ inline uint32_t local_cell(const Box& B, const int c[3]) {
+  return mad24((uint32_t)B.td[0],
+               mad24((uint32_t)B.td[1], (uint32_t)c[2] & B.lm[2], (uint32_t)c[1] & B.lm[1]),
+               (uint32_t)c[0] & B.lm[0]);
+}
+
 // Where a particle in cell c goes from tile t: its bin 0..26 among the 27
-// neighbour tiles (the +1 neighbour is preferred when it is also the -1
-// one, nt == 2), or 27 for any other tile; and its cell inside the
-// destination tile.
+// neighbour tiles, or 27 for any other tile; and its cell inside the
+// destination tile. Per axis the tile offset diff (in (-nt, nt)) is taken
+// periodically into [-1, 1] where it names a neighbour: down by nt if
+// above 1, then up by nt if below -1 (with nt == 2 the tile at +1 is also
+// the one at -1, and either bin names it).
 __device__ inline uint32_t dest_bin(const Box& B, const int t[3], const int c[3], uint32_t& lcell) {
-  uint32_t bin = 0;
-  bool near = true;
+  uint32_t bin = 0, far = 0;
   constexpr uint32_t mul[3] = {1u, 3u, 9u};
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int nt = B.nt[d];
-    const int diff = tile_coord(c[d], B, d) - t[d];
-    const uint32_t o = diff == 0 ? 1u : ((diff == 1 || diff == 1 - nt) ? 2u : ((diff == -1 || diff == nt - 1) ? 0u : 3u));
-    near = near && o != 3u;
+    int diff = tile_coord(c[d], B, d) - t[d];
+    diff -= diff > 1 ? nt : 0;
+    diff += diff < -1 ? nt : 0;
+    const uint32_t o = (uint32_t)(diff + 1);  // 0, 1, 2 for a neighbour
+    far = max(far, o);
     bin += o * mul[d];
   }
-  lcell = ((uint32_t)c[0] & B.lm[0]) +
-          (uint32_t)B.td[0] * (((uint32_t)c[1] & B.lm[1]) + (uint32_t)B.td[1] * ((uint32_t)c[2] & B.lm[2]));
-  return near ? bin : 27u;
+  lcell = local_cell(B, c);
+  return far > 2u ? 27u : bin;
 }
 
 // ------------------------------------------------------------ tile kernel
@@ -611,6 +635,9 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
   constexpr bool SCAT = MODE == MODE_BIN || MODE == MODE_COLLIDE_SCATTER;
   constexpr bool EK = THERMO || MODE == MODE_DIAG;
   constexpr bool AT = ATR && COLL && MODE != MODE_DIAG;
+  // binning launches share one instantiation with and without embedded
+  // particles: they check each particle's tag
+  constexpr bool MAY_EMB = EMB || MODE == MODE_BIN;
   // 64-cell step kernels of the SRD rule keep the register-resident
   // particles' position records in LDS (loaded there directly) instead of
   // registers: positions are needed only after the rotation, and the
@@ -711,9 +738,7 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
   auto lc_from = [&](const Pos<FORM>& rr) -> uint32_t {
     int c[3];
     rr.cell3(B, sd, sd32, c);
-    return (((uint32_t)c[0] & B.lm[0]) +
-            (uint32_t)B.td[0] * (((uint32_t)c[1] & B.lm[1]) + (uint32_t)B.td[1] * ((uint32_t)c[2] & B.lm[2]))) &
-           (uint32_t)(CPT - 1);
+    return local_cell(B, c) & (uint32_t)(CPT - 1);
   };
   auto lc_at = [&](uint32_t k) -> uint32_t {
     Pos<FORM> rr;
@@ -891,7 +916,7 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
     if constexpr (STREAM_IN) {
 #pragma unroll
       for (int q = 0; q < TQ; ++q)
-        if (tid + (uint32_t)(q * TT) < nreg && streamed(B, tg[q])) r[q].stream(B, v[q], err);
+        if (tid + (uint32_t)(q * TT) < nreg && streamed_in<MAY_EMB>(B, tg[q])) r[q].stream(B, v[q], err);
     }
     scatter(sd, sd32, v);
     for (uint32_t k = TREG + tid; k < cnt; k += TT) {
@@ -899,7 +924,7 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
       uint32_t tag;
       Pos<FORM> rr;
       load_part<FORM>(In, k, rr, vv, tag);
-      if (STREAM_IN && streamed(B, tag)) rr.stream(B, vv, err);
+      if (STREAM_IN && streamed_in<MAY_EMB>(B, tag)) rr.stream(B, vv, err);
       scatter_one(rr, sd, sd32, vv, tag);
     }
   } else {
@@ -1082,7 +1107,7 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
           store_part<FORM>(Out, k, rr, ww, tag);
           if (A.eslot_out) note_slot(A.eslot_out, B, tag, tbase + k);
         } else {
-          if (streamed(B, tag)) rr.stream(B, ww, err);
+          if (streamed_in<MAY_EMB>(B, tag)) rr.stream(B, ww, err);
           scatter_one(rr, sh1.s, sh1.s32, ww, tag);
         }
       };
@@ -1109,7 +1134,7 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
               store_part<FORM>(Out, k, rr, v[q], tg[q]);
               if (A.eslot_out) note_slot(A.eslot_out, B, tg[q], tbase + k);
             } else {
-              if (streamed(B, tg[q])) rr.stream(B, v[q], err);
+              if (streamed_in<MAY_EMB>(B, tg[q])) rr.stream(B, v[q], err);
               int c[3];
               rr.cell3(B, sh1.s, sh1.s32, c);
               uint32_t lcell;
@@ -1124,7 +1149,7 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
             store_part<FORM>(Out, k, r[q], v[q], tg[q]);
             if (A.eslot_out) note_slot(A.eslot_out, B, tg[q], tbase + k);
           } else {
-            if (streamed(B, tg[q])) r[q].stream(B, v[q], err);
+            if (streamed_in<MAY_EMB>(B, tg[q])) r[q].stream(B, v[q], err);
           }
         }
       }
