@@ -73,8 +73,11 @@ typedef enum { MPCD_FP64 = 0, MPCD_FP32 = 1 } mpcd_precision;
 /* Collision rule: stochastic rotation (eq. 2, Alg. 1), or the Andersen
  * thermostat (eq. 4, sec. 3.7): v_i <- u + dv_i - sum_j m_j dv_j / M_c with
  * dv_i ~ N(0, kT / m_i) per component, drawn per particle from Philox counter
- * (tag within the box, step, 3, 0) by Box-Muller. The AT rule thermostats by
- * itself: thermostat must be 0 with it. */
+ * (tag within the box, step, 3, 0) by Box-Muller: in double precision in the
+ * FP64 form; in single precision in the FP32 form (sec. 4.1: the mixed
+ * model keeps double precision for the cell sums and the rotation), from
+ * uniforms u = (w / 2^9 + 1/2) 2^-23 and with the scale sqrt(kT / m) rounded
+ * to FP32. The AT rule thermostats by itself: thermostat must be 0 with it. */
 typedef enum { MPCD_SRD = 0, MPCD_AT = 1 } mpcd_collision;
 
 /* Problem parameters as the paper states the problem (sec. 2, sec. 4). */

@@ -14,12 +14,47 @@ binary32, round to nearest, one rounding per operation, no contraction):
   bin:    q = o + s32; j = floor(q*inv_a32) clamped to [-1, 1];
           cell = (h + j) mod n per axis
   collide: v upcast to FP64; sums, draws and rotation in FP64 exactly as the
-          FP64 oracle; the result rounded once to FP32.
+          FP64 oracle; the result rounded once to FP32. Under the AT rule the
+          kicks are the form's single-precision ones (at_kicks32).
 with dt32 = fl32(dt), a32 = fl32(a), inv_a32 = fl32(fl64(1/a)), s32 = fl32(s).
 """
+import math
+
 import numpy as np
 
 from . import srd
+from .philox import TAG_AT, philox4x32_10, seed_key
+
+
+def uniform23(w):
+    """The FP32 form's uniforms: u = (floor(w / 2^9) + 1/2) 2^-23, from the top
+    23 bits of a 32-bit word; exact in FP32, strictly inside (0, 1)."""
+    return ((np.asarray(w, dtype=np.uint64) >> np.uint64(9)).astype(np.float64) + 0.5) * 2.0 ** -23
+
+
+def at_kicks32(tags, step, mass, p):
+    """Random velocities of the AT rule in the FP32 form (sec. 3.7 with the
+    mixed-precision model of sec. 4.1, which keeps double precision for the
+    cell sums and the rotation only): the words of counter (tag, step,
+    TAG_AT, 0) as in the FP64 form, uniforms by uniform23, the same
+    Box-Muller pairing, and the scale sqrt(kT / m) rounded to FP32. Returned
+    as the exact value of that formula (FP64 evaluation from the same
+    uniforms and scale); the GPU evaluates it in single precision, which
+    differs from it by the rounding of a few single-precision operations."""
+    tags = np.asarray(tags, dtype=np.uint64)
+    n = tags.size
+    ctr = np.stack([tags, np.full(n, step, dtype=np.uint64),
+                    np.full(n, TAG_AT, dtype=np.uint64), np.zeros(n, dtype=np.uint64)],
+                   axis=1).astype(np.uint32)
+    w = philox4x32_10(ctr, seed_key(p.seed))
+    u = uniform23(w)
+    r0 = np.sqrt(-2.0 * np.log(u[:, 0]))
+    r2 = np.sqrt(-2.0 * np.log(u[:, 2]))
+    g = np.stack([r0 * np.cos((2.0 * math.pi) * u[:, 1]),
+                  r0 * np.sin((2.0 * math.pi) * u[:, 1]),
+                  r2 * np.cos((2.0 * math.pi) * u[:, 3])], axis=1)
+    scale = np.sqrt(p.kT / np.asarray(mass, dtype=np.float64)).astype(np.float32).astype(np.float64)
+    return scale[:, None] * g
 
 
 def constants32(p):
@@ -80,7 +115,7 @@ def collide32(h, o, v, mass, p, step):
     cell = bin32(h, o, s, p)
     v64 = v.astype(np.float64)
     if p.rule == "at":
-        vnew, info = srd.collide_at(cell, v64, mass, p, step)
+        vnew, info = srd.collide_at(cell, v64, mass, p, step, kicks=at_kicks32)
         info.update(shift=s, cell=cell)
         return vnew.astype(np.float32), info
     count, M, P, u, ek = srd.cell_sums(cell, v64, mass, p.ncells)

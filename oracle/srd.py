@@ -255,13 +255,14 @@ def at_kicks(tags, step, mass, p):
     return np.sqrt(p.kT / np.asarray(mass, dtype=np.float64))[:, None] * g
 
 
-def collide_at(cell, vel, mass, p, step, tags=None):
+def collide_at(cell, vel, mass, p, step, tags=None, kicks=None):
     """AT collision (eq. 4): v_i <- u + dv_i - sum_j m_j dv_j / M_c, the sums
-    over the particles of the cell."""
+    over the particles of the cell. `kicks` draws the random velocities
+    (default at_kicks; the FP32 form passes its own)."""
     n = vel.shape[0]
     tags = np.arange(n) if tags is None else tags
     count, M, P, u, ek = cell_sums(cell, vel, mass, p.ncells)
-    dv = at_kicks(tags, step, mass, p)
+    dv = (at_kicks if kicks is None else kicks)(tags, step, mass, p)
     Q = np.stack([np.bincount(cell, weights=mass * dv[:, d], minlength=p.ncells)
                   for d in range(3)], axis=1)
     wmean = np.zeros((p.ncells, 3))

@@ -299,6 +299,29 @@ __device__ inline void at_kick(uint32_t tag, uint32_t step, uint32_t k0, uint32_
   dv[2] = scale * (r2 * cospi(2.0 * u01(w.w)));
 }
 
+// The FP32 storage form draws the AT kicks in single precision (sec. 4.1: the
+// mixed-precision model uses single precision wherever the method does not
+// need double, which it names for the cell sums and the rotation only):
+// uniforms from the top 23 bits of each word, u = (w / 2^9 + 1/2) 2^-23
+// (exact in FP32, strictly inside (0, 1)); the same Box-Muller pairing as
+// at_kick with single-precision logf, sqrtf, sincospif and cospif, and the
+// scale sqrt(kT / m) rounded once to FP32. The FP32 kick is exact in FP64.
+__device__ inline float u01f(uint32_t w) {
+  return ((float)(w >> 9) + 0.5f) * 0x1p-23f;
+}
+
+__device__ inline void at_kick32(uint32_t tag, uint32_t step, uint32_t k0, uint32_t k1,
+                                 float scale, float dv[3]) {
+  const U4 w = philox4x32_10(U4{tag, step, TAG_AT, 0u}, k0, k1);
+  const float r0 = sqrtf(-2.0f * logf(u01f(w.x)));
+  const float r2 = sqrtf(-2.0f * logf(u01f(w.z)));
+  float s1, c1;
+  sincospif(2.0f * u01f(w.y), &s1, &c1);
+  dv[0] = scale * (r0 * c1);
+  dv[1] = scale * (r0 * s1);
+  dv[2] = scale * (r2 * cospif(2.0f * u01f(w.w)));
+}
+
 // Right-handed rotation of d by the angle a (cos a, sin a, 1 - cos a given)
 // about the unit axis n, by Rodrigues' formula evaluated in this order:
 // (d cos a + (n x d) sin a) + n ((n . d)(1 - cos a)).

@@ -556,14 +556,30 @@ struct Acc {
   }
 };
 
+// AT kick of particle i of its box in the form's precision (FP64 form:
+// at_kick; FP32 form: at_kick32, returned exactly in FP64).
+template <int FORM>
+__device__ inline void at_kick_form(uint32_t i, uint32_t step, uint32_t k0, uint32_t k1,
+                                    double scale, double dv[3]) {
+  if constexpr (FORM == 0) {
+    at_kick(i, step, k0, k1, scale, dv);
+  } else {
+    float f[3];
+    at_kick32(i, step, k0, k1, (float)scale, f);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) dv[d] = (double)f[d];
+  }
+}
+
 // AT kick of a particle beyond the register-resident part of its tile. Kept
-// out of line: drawn inline there, its FP64 Box-Muller chain would be
-// scheduled around the live register-resident particles and raise every
-// wave's register count (FP32 form 88 -> 74 VGPRs), although only crowded
-// tiles take that path.
+// out of line: drawn inline there, its Box-Muller chain would be scheduled
+// around the live register-resident particles and raise every wave's
+// register count (FP32 form with FP64 kicks: 88 -> 74 VGPRs), although only
+// crowded tiles take that path.
+template <int FORM>
 __device__ __noinline__ void at_kick_tail(uint32_t i, uint32_t step, uint32_t k0, uint32_t k1,
                                           double scale, double dv[3]) {
-  at_kick(i, step, k0, k1, scale, dv);
+  at_kick_form<FORM>(i, step, k0, k1, scale, dv);
 }
 
 // Maxwell-Boltzmann draw of a cell with nc >= 2 particles (sec. 3.6):
@@ -615,12 +631,12 @@ __device__ inline double gamma_finish(uint32_t nc, uint32_t cell, uint32_t step,
 // though a few dwords spill; with embedded particles the compiler cannot
 // meet eight and seven is kept), thermostatted 128-cell tiles six (86 -> 80
 // VGPRs, a few spilled dwords; ~3 % faster); under the AT rule 64-cell
-// tiles six (with embedded particles the compiler would otherwise take 82
-// VGPRs and five).
+// tiles eight (single-precision kicks, kept in LDS as FP32: 60-64 VGPRs and
+// 16 KB of LDS per block; 153 against 160 us at six).
 template <int FORM, int CPT, int MODE, bool STREAM_IN, bool THERMO, bool EMB, bool ATR>
 constexpr int tile_waves_per_eu() {
   if (FORM != MPCD_FP32) return 1;
-  if (ATR) return CPT == 64 ? 6 : 1;  // AT rule, 64-cell tiles: held at six
+  if (ATR) return CPT == 64 ? 8 : 1;  // AT rule, 64-cell tiles: eight
   if (CPT == 64) return EMB ? 7 : 8;
   if (CPT == 128 && THERMO) return 6;
   return 1;
@@ -799,11 +815,12 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
   __shared__ uint4 s_pos[LPOS ? TREG : 1];     // LPOS: position records, slot k at k
   double zq[LPOS && FORM == 0 ? TQ : 1];       // LPOS, FP64 form: z of each position
   // AT rule: each register-resident particle's kick, drawn once and used by
-  // the cell sums and the update, waits in LDS (in registers it would hold 6
-  // VGPRs per particle slot through the whole kernel and cut occupancy)
-  __shared__ double s_dv[AT ? 3 : 1][AT ? TREG : 1];
+  // the cell sums and the update, waits in LDS in the form's precision (in
+  // registers it would hold 3 to 6 VGPRs per particle slot through the whole
+  // kernel and cut occupancy)
+  __shared__ VT s_dv[AT ? 3 : 1][AT ? TREG : 1];
   auto kick = [&](uint32_t tag, double m, double out[3]) {
-    at_kick(tag - B.tag0, A.step, B.k0, B.k1, sqrt(B.kT / m), out);
+    at_kick_form<FORM>(tag - B.tag0, A.step, B.k0, B.k1, sqrt(B.kT / m), out);
   };
 #pragma unroll
   for (int q = 0; q < TQ; ++q) {
@@ -957,7 +974,7 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
       load_vt<FORM>(In, k, vv, tag);
       const double m = mass_of(tag);
       double kv[3] = {0.0, 0.0, 0.0};
-      if constexpr (AT) at_kick_tail(tag - B.tag0, A.step, B.k0, B.k1, sqrt(B.kT / m), kv);
+      if constexpr (AT) at_kick_tail<FORM>(tag - B.tag0, A.step, B.k0, B.k1, sqrt(B.kT / m), kv);
       sum_mom(lc_at(k), vv, m, kv);
     }
     __syncthreads();
@@ -1193,7 +1210,7 @@ __global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(
         if (THERMO && anyp && s_pend[lc]) continue;
         load_part<FORM>(In, k, rr, vv, tag);
         double kv[3] = {0.0, 0.0, 0.0};
-        if constexpr (AT) at_kick_tail(tag - B.tag0, A.step, B.k0, B.k1, sqrt(B.kT / mass_of(tag)), kv);
+        if constexpr (AT) at_kick_tail<FORM>(tag - B.tag0, A.step, B.k0, B.k1, sqrt(B.kT / mass_of(tag)), kv);
         rotate(lc, vv, ww, kv);
         finish_one(k, lc, rr, ww, tag);
       }

@@ -35,6 +35,44 @@ def ulp_diff_f32(a, b):
 # 2^-40 absolute.
 FP32_FIXED_ABS = 2.0 ** -40
 
+# The FP32 form draws AT kicks in single precision (logf, sqrtf, sincospif,
+# cospif and three products); the oracle evaluates the same formula from the
+# same uniforms exactly. With the device library's single-precision functions
+# within 2 ulps and correctly rounded products and square root, a kick is
+# within about 5 ulps of the exact value; 8 ulps (2^-20 relative) is the
+# bound used.
+AT32_KICK_REL = 2.0 ** -20
+
+
+def at32_close(g, v, info):
+    """FP32 form under the AT rule, elementwise: within one ulp of the
+    emulation, or within one ulp plus 2^-20 of the particle's own kick and of
+    the largest kick in its cell (the kick enters the velocity once and the
+    cell's mean kick once), plus 2^-40."""
+    g = np.asarray(g, dtype=np.float64)
+    v32 = np.asarray(v, dtype=np.float32)
+    kick = np.abs(info["kick"])
+    cell = info["cell"]
+    kmax = np.zeros((int(cell.max()) + 1 if cell.size else 1, 3))
+    np.maximum.at(kmax, cell, kick)
+    tol = (np.spacing(np.abs(v32)).astype(np.float64) +
+           AT32_KICK_REL * (kick + kmax[cell]) + FP32_FIXED_ABS)
+    return (ulp_diff_f32(g.astype(np.float32), v32) <= 1) | (np.abs(g - v32.astype(np.float64)) <= tol)
+
+
+def at32_kick_units(g, v, info):
+    """For reports: the largest difference beyond one ulp of the velocity, in
+    FP32 ulps of the kicks it may come from (|own kick| + largest in the
+    cell); at32_close allows 8."""
+    v32 = np.asarray(v, dtype=np.float32)
+    kick = np.abs(info["kick"])
+    cell = info["cell"]
+    kmax = np.zeros((int(cell.max()) + 1 if cell.size else 1, 3))
+    np.maximum.at(kmax, cell, kick)
+    d = np.abs(np.asarray(g, dtype=np.float64) - v32.astype(np.float64))
+    excess = np.maximum(d - np.spacing(np.abs(v32)).astype(np.float64), 0.0)
+    return float((excess / (2.0 ** -23 * (kick + kmax[cell]))).max()) if d.size else 0.0
+
 
 def f32_close(a, b, abs_tol=FP32_FIXED_ABS):
     """Elementwise: within one FP32 ulp, or within abs_tol absolute."""
