@@ -138,8 +138,9 @@ mpcd_status mpcd_md_verlet_chains(double* pos, double* vel, const double* mass, 
 /* Tile shape (the cells a block of the step kernel collides together and
  * whose particles share a slab), in bits 8-10 of flags: 0 chooses by the
  * box's mean density rho (a box alone, SRD rule: rho >= 12: 4x4x2 cells,
- * >= 7.5: 4x4x4, >= 3.75: 8x4x4, else 8x8x4; AT rule: >= 12: 4x4x2,
- * >= 2.5: 4x4x4, else 8x8x4; a box of a batch: >= 12: 4x4x2, >= 3.5: 4x4x4,
+ * >= 7.5: 4x4x4, >= 3.75: 8x4x4, else 8x8x4, and so the FP32 form's AT rule;
+ * the FP64 form's AT rule: >= 12: 4x4x2, >= 2.5: 4x4x4, else 8x8x4; a box of
+ * a batch: >= 12: 4x4x2, >= 3.5: 4x4x4,
  * >= 1.75: 8x4x4, else 8x8x4); MPCD_TILE_4x4x2 .. MPCD_TILE_8x8x4 set it. Results do
  * not depend on it (only how fast they come). In a batch each box may set
  * its own; the other flags must match. Sec. 3.5 tunes the equivalent launch

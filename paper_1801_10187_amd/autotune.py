@@ -24,14 +24,14 @@ SHAPES = list(binding.TILE_SHAPES)
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "mpcd_tiles.json")
 
 
-def rule_shape(density, single=True, collision=binding.SRD):
+def rule_shape(density, single=True, collision=binding.SRD, precision=binding.FP32):
     """The library's own choice (MPCD_TILE_* 0) for a mean density: a box
-    alone or a box of a batch, SRD or AT rule."""
+    alone or a box of a batch, SRD or AT rule, FP32 or FP64 form."""
     if density >= 12.0:
         return "4x4x2"
     if not single:
         return "4x4x4" if density >= 3.5 else ("8x4x4" if density >= 1.75 else "8x8x4")
-    if collision == binding.AT:
+    if collision == binding.AT and precision == binding.FP64:
         return "4x4x4" if density >= 2.5 else "8x8x4"
     return "4x4x4" if density >= 7.5 else ("8x4x4" if density >= 3.75 else "8x8x4")
 
@@ -107,7 +107,7 @@ def sweep(densities, precision=binding.FP32, thermostat=True, collision=binding.
         t = {sh: min(measure(sh, rho, precision, thermostat, collision, inp=inp, **kw)
                      for _ in range(repeats)) for sh in SHAPES}
         best = min(t, key=t.get)
-        rule = rule_shape(rho, True, collision)
+        rule = rule_shape(rho, True, collision, precision)
         rows.append((rho, t, best, rule, t[rule] / t[best]))
         print(f"[autotune] density {rho:g}: fastest {best}", file=sys.stderr, flush=True)
     return rows

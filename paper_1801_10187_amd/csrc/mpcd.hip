@@ -648,8 +648,9 @@ mpcd_status validate(const mpcd_params* p, int64_t ns, int64_t ne) {
 //    8x4x4 below 7.5, 4x4x4 below 12, 4x4x2 from 12 (each within 5 % of the
 //    fastest shape at the densities measured, 1.5-12 % faster than the
 //    shape of the next band);
-//  - a box alone, AT rule: 8x8x4 below 2.5, 4x4x4 below 12, 4x4x2 from 12
-//    (its FP64 kernels lose more occupancy with larger tiles);
+//  - a box alone, AT rule in the FP64 form: 8x8x4 below 2.5, 4x4x4 below
+//    12, 4x4x2 from 12 (its kernels lose more occupancy with larger tiles);
+//    the FP32 form's AT kernels follow the SRD rule;
 //  - boxes of a batch: every box runs with the kernel of the largest tile
 //    any box needs (cells per tile 64/128/256), which slows the boxes with
 //    smaller tiles, so a batch keeps 64-cell tiles down to density 3.5
@@ -803,7 +804,8 @@ mpcd_status create_impl(int32_t nbox, const mpcd_params* params, const int64_t* 
     const uint32_t nb = (uint32_t)n_solv[b] + (b == 0 ? c->n_emb : 0u);
     cpt = std::max(cpt, choose_tiles(B, B.ncells ? (double)nb / (double)B.ncells : 0.0,
                                      tile_shape(params[b]), nbox == 1,
-                                     params[b].collision == MPCD_AT));
+                                     params[b].collision == MPCD_AT &&
+                                         params[b].precision == MPCD_FP64));
     const uint32_t t0 = tile;
     B.tile0 = t0;
     B.tag0 = tag;
@@ -1663,7 +1665,8 @@ mpcd_status mpcd_footprint(const mpcd_params* params, int64_t n_particles, int64
   if (nsteps < 0) return fail(MPCD_EINVAL, "nsteps < 0");
   Box B = make_box(*params);
   const double rho = B.ncells ? (double)n_particles / (double)B.ncells : 0.0;
-  (void)choose_tiles(B, rho, tile_shape(*params), true, params->collision == MPCD_AT);
+  (void)choose_tiles(B, rho, tile_shape(*params), true,
+                     params->collision == MPCD_AT && params->precision == MPCD_FP64);
   const uint64_t nt = B.ntiles, C = B.ncells, n = (uint64_t)n_particles;
   const bool fp64 = params->precision == MPCD_FP64;
   // every allocation is at least 256 bytes; allow that much again for the

@@ -15,6 +15,9 @@ namespace mpcd {
 // block per chain, one thread per bead; the chain's positions wait in LDS
 // for the force evaluation of each substep. Positions are wrapped into
 // [0, L) after each drift (x mod L, then a result that rounds to L is 0).
+// A drift leaves y = x + dt v in (-L, 2L) but for huge velocities: there
+// fmod(y, L) is y, or y - L (exact: L <= y < 2L), taken without the
+// library's general remainder.
 // Forces on bead i: the bond to i - 1 first, then the bond to i + 1.
 __device__ inline void bond_pair(const double* pi, const double* pj, const double L[3], double k,
                                  double b, double f[3]) {
@@ -74,7 +77,8 @@ __global__ __launch_bounds__(1024) void k_md_chains(double* __restrict__ pos, do
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         v[c] = v[c] + (h * f[c]) / m;
-        double x = fmod(p[c] + dt * v[c], L[c]);
+        const double y = p[c] + dt * v[c];
+        double x = (y > -L[c] && y < 2.0 * L[c]) ? (y >= L[c] ? y - L[c] : y) : fmod(y, L[c]);
         if (x < 0.0) x = x + L[c];
         if (x >= L[c]) x = 0.0;
         p[c] = x + 0.0;  // -0 -> +0
