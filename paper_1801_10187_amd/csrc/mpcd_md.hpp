@@ -19,14 +19,26 @@ namespace mpcd {
 // fmod(y, L) is y, or y - L (exact: L <= y < 2L), taken without the
 // library's general remainder.
 // Forces on bead i: the bond to i - 1 first, then the bond to i + 1.
+// Minimum image d - L rint(d / L). For |d| < L (two positions in [0, L))
+// the rounded quotient is 1 exactly when d > L/2 (a quotient that rounds to
+// 0.5 has d <= L/2, and a tie rounds to even, 0), -1 when d < -L/2, and a
+// zero carrying the sign of d otherwise; the general form is kept for other d.
+__device__ inline double min_image(double d, double L) {
+  double n;
+  if (fabs(d) < L) {
+    const double h = 0.5 * L;
+    n = d > h ? 1.0 : (d < -h ? -1.0 : copysign(0.0, d));
+  } else {
+    n = rint(d / L);
+  }
+  return d - L * n;
+}
+
 __device__ inline void bond_pair(const double* pi, const double* pj, const double L[3], double k,
                                  double b, double f[3]) {
   double d[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    d[c] = pj[c] - pi[c];
-    d[c] = d[c] - L[c] * rint(d[c] / L[c]);
-  }
+  for (int c = 0; c < 3; ++c) d[c] = min_image(pj[c] - pi[c], L[c]);
   const double r = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
   const double fm = ((-k) * (r - b)) / r;
 #pragma unroll
