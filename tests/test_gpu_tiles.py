@@ -39,6 +39,22 @@ def test_every_shape_gives_the_same_steps(prec, rule):
             assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("prec,rule", [(m.FP32, m.SRD), (m.FP64, m.SRD), (m.FP32, m.AT),
+                                       (m.FP64, m.AT)])
+def test_density_rule_matches_the_tuner_table(prec, rule):
+    """The library's own choice of shape for a box alone (flags 0) is the one
+    autotune.rule_shape names for the density, rule and form."""
+    banner(f"density rule, prec {prec} rule {rule}")
+    n_cells = (20, 18, 13)
+    for rho in (1.5, 3.0, 5.0, 9.0, 13.0):
+        pos, vel = workloads.fluid(n_cells, rho, seed=int(10 * rho))
+        with m.Sim(pos, vel, n_cells, precision=prec, thermostat=rule == m.SRD,
+                   collision=rule) as s:
+            tile = tuple(s.layout()[0])
+        want = autotune.rule_shape(pos.shape[0] / np.prod(n_cells), True, rule, prec)
+        assert tile == DIMS[want], (rho, tile, want)
+
+
 def test_batch_boxes_with_their_own_shapes():
     banner("tile shapes per box in a batch")
     boxes = workloads.replica_inputs(workloads.replica_boxes(4, seed=5, side=(6, 16)))
