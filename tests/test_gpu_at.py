@@ -135,3 +135,5 @@ def test_at_full_size_benchmark_fluid(form):
         assert np.array_equal(gcells, info["cell"])
         assert np.array_equal(gpos, fp32form.to_double(h1, o1, p))
         assert np.all(at32_close(gvel, v1, info))
+        print(f"[gpu-test] AT fp32 full size: largest difference beyond one ulp: "
+              f"{at32_kick_units(gvel, v1, info):.3g} kick ulps")
