@@ -629,8 +629,9 @@ __device__ inline double gamma_finish(uint32_t nc, uint32_t cell, uint32_t step,
 // 64-cell tiles eight (64 VGPRs, with the LDS of a block under 20 KB so that
 // eight blocks fit a CU: the thermostatted step ~1.4 % faster than at seven,
 // though a few dwords spill; with embedded particles the compiler cannot
-// meet eight and seven is kept), thermostatted 128-cell tiles six (86 -> 80
-// VGPRs, a few spilled dwords; ~3 % faster); under the AT rule 64-cell
+// meet eight and seven is kept), thermostatted 128-cell tiles seven (72
+// VGPRs, a few spilled dwords; ~1 % faster than six at densities 4-7, six
+// ~3 % faster than the compiler's own choice); under the AT rule 64-cell
 // tiles eight (single-precision kicks, kept in LDS as FP32: 60-64 VGPRs and
 // 16 KB of LDS per block; 153 against 160 us at six).
 template <int FORM, int CPT, int MODE, bool STREAM_IN, bool THERMO, bool EMB, bool ATR>
@@ -638,7 +639,7 @@ constexpr int tile_waves_per_eu() {
   if (FORM != MPCD_FP32) return 1;
   if (ATR) return CPT == 64 ? 8 : 1;  // AT rule, 64-cell tiles: eight
   if (CPT == 64) return EMB ? 7 : 8;
-  if (CPT == 128 && THERMO) return 6;
+  if (CPT == 128 && THERMO) return 7;
   return 1;
 }
 
